@@ -1,0 +1,194 @@
+/*
+ * t3pcf -- multipole estimator of the shear three-point correlation
+ * function on AMD Instinct MI355X (gfx950).
+ *
+ * Porth, Heydenreich, Burger, Linke & Schneider (2023), "Efficient
+ * estimation of third-order shear correlation functions", Sect. 3.
+ *
+ * Plain C ABI.  All catalog and output pointers are DEVICE pointers unless
+ * stated otherwise; streams are hipStream_t passed as void* (NULL = the
+ * null stream).  The caller owns every buffer it passes; the library never
+ * frees caller memory.  A plan owns its internal workspace (device memory
+ * it allocates on first use and keeps until t3_plan_destroy).  A plan must
+ * not be used from two host threads or two streams at the same time.
+ *
+ * Return codes: 0 on success, a negative T3_E* code on failure.  Argument
+ * errors are detected before any launch and leave outputs untouched.
+ * t3_last_error_message() returns a thread-local description of the most
+ * recent failure on the calling thread.  No C++ exception crosses the ABI.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ * Positions are int32 coordinates on a square lattice of step
+ * `lattice_unit` arcmin (default 2^-16); they must lie inside the plan's
+ * box [box_lo, box_lo + box_size) on both axes.  Separations are therefore
+ * exact integers, and a pair (i, j) falls in radial bin b when
+ *     (edges[b] / lattice_unit)^2 <= dx^2 + dy^2 < (edges[b+1] / lattice_unit)^2
+ * (half-open bins; squares evaluated in IEEE double).
+ * Shears g1 + i g2 and weights w are float32.  c_j = w_j (g1_j + i g2_j).
+ * phi_ij is the polar angle of theta_j - theta_i.
+ *
+ * The multipoles follow eq. (Upsilon0_Derivation), eqs. (Upsilon1-3) and
+ * eq. (3PCF_Normalization), summed over pairwise-distinct triplets (the
+ * j = k terms that the product of two harmonic sums contains are removed
+ * unless T3_FLAG_KEEP_JK is set):
+ *   Upsilon_{0,n}(b1,b2) = -sum_i c_i  [G_{n-3}(b1)   G_{-n-3}(b2)]
+ *   Upsilon_{1,n}        = -sum_i c_i* [G_{n-1}(b1)   G_{-n-1}(b2)]
+ *   Upsilon_{2,n}        = -sum_i c_i  [G_{-n-1}(b1)* G_{-n-3}(b2)]
+ *   Upsilon_{3,n}        = -sum_i c_i  [G_{n-3}(b1)   G_{n-1}(b2)*]
+ *   N_n                  =  sum_i w_i  [W_n(b1)       W_n(b2)*]
+ * with G_m(i;b) = sum_j c_j e^{i m phi_ij}, W_m(i;b) = sum_j w_j e^{i m phi_ij}
+ * over neighbours j of centre i in bin b (eq. Gn_disc).
+ *
+ * Multipole output layout ("ups"): complex128 as interleaved (re, im)
+ * doubles, row-major [5][n_max+1][B][B] with index 0..3 = Upsilon_0..3 and
+ * 4 = N, orders n = 0..n_max.  Negative orders follow from the symmetries
+ * of Appendix A: Upsilon_{0,-n}(b1,b2) = Upsilon_{0,n}(b2,b1) (same for 1
+ * and N), Upsilon_{2,-n}(b1,b2) = Upsilon_{3,n}(b2,b1).
+ * Tomographic output: [n_z][n_z][n_z][5][n_max+1][B][B] indexed
+ * (Z1 centres, Z2 = b1-side neighbours, Z3 = b2-side neighbours), eq. tomoGn.
+ */
+#ifndef T3PCF_H
+#define T3PCF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define T3_OK 0
+#define T3_EINVAL (-1)   /* bad argument (null pointer, bad size, bad bins) */
+#define T3_ERANGE (-2)   /* parameter outside the supported range          */
+#define T3_ENOMEM (-3)   /* device allocation failed                       */
+#define T3_EHIP (-4)     /* a HIP runtime call failed                      */
+#define T3_ELATTICE (-5) /* a position lies outside the plan's box          */
+
+/* Precision of the contraction over centres (stage 2). */
+#define T3_PREC_FP32 0    /* FP32 MFMA products, FP32 runs promoted to FP64 */
+#define T3_PREC_BF16X3 1  /* x = hi + lo in bf16; hi*hi + hi*lo + lo*hi     */
+#define T3_PREC_FP16X3 2  /* same in fp16 with power-of-two row scaling     */
+
+#define T3_FLAG_KEEP_JK 1u /* keep the j = k terms (the paper's literal sum) */
+#define T3_FLAG_TIMING 2u  /* record HIP events around each stage (t3_stage_times) */
+
+typedef struct {
+    int32_t n_bins;        /* B >= 1                                         */
+    const double *edges;   /* HOST, n_bins + 1 arcmin, strictly increasing,  */
+                           /* edges[0] > 0, edges[n_bins] < 512 arcmin       */
+    int32_t n_max;         /* largest multipole, 0 <= n_max <= 64            */
+    int32_t precision;     /* T3_PREC_*                                      */
+    uint32_t flags;        /* T3_FLAG_*                                      */
+    double lattice_unit;   /* arcmin per lattice step; 0 -> 2^-16            */
+    int32_t box_lo_x;      /* lattice box holding every position             */
+    int32_t box_lo_y;
+    int64_t box_size;      /* side in lattice steps, > 0, box_lo + size <= 2^31 */
+    double cell_arcmin;    /* spatial-hash cell side; 0 -> automatic          */
+    int32_t chunk_centres; /* centres per stage-1/stage-2 chunk; 0 -> auto    */
+} t3_params;
+
+typedef struct {
+    int64_t n;            /* number of galaxies (>= 0)                       */
+    const int32_t *x;     /* DEVICE [n] lattice coordinates                  */
+    const int32_t *y;     /* DEVICE [n]                                      */
+    const float *g1;      /* DEVICE [n] shear, Cartesian frame               */
+    const float *g2;      /* DEVICE [n]                                      */
+    const float *w;       /* DEVICE [n] weights                              */
+} t3_catalog;
+
+typedef struct t3_plan t3_plan;
+
+/* Create a plan: validates parameters, derives squared edges and the
+ * cell grid, and picks the stage-1 kernel variant for n_max.  No device
+ * memory is allocated here.  *out is set only on success. */
+int t3_plan_create(const t3_params *params, t3_plan **out);
+
+/* Release the plan and its workspace (synchronises the device first). */
+void t3_plan_destroy(t3_plan *plan);
+
+/* Non-tomographic forward pass (Sect. 3.1, eq. Upsilon0_Derivation).
+ * cat:       the neighbour catalog; centres are drawn from the same catalog.
+ * centres:   DEVICE int32 [n_centres] indices into cat.  n_centres < 0 selects
+ *            every galaxy of cat (centres must then be NULL); n_centres == 0
+ *            selects none (centres may be NULL) and yields zero multipoles.
+ * ups_out:   DEVICE double [5][n_max+1][B][B][2]; overwritten.
+ * n_pairs:   HOST int64*, optional: number of in-range ordered
+ *            (centre, neighbour) pairs visited.
+ * The call enqueues its work on `stream` and returns after the last
+ * kernel completes (it synchronises the stream once, to check the
+ * lattice bounds of the catalog). */
+int t3_forward(t3_plan *plan, const t3_catalog *cat, const int32_t *centres,
+               int64_t n_centres, double *ups_out, int64_t *n_pairs, void *stream);
+
+/* Tomographic forward pass over all ordered bin triples (Sect. 3.5,
+ * eq. tomoGn).  cats: HOST array of n_z catalogs (device arrays).
+ * centres: HOST array of n_z DEVICE pointers, or NULL for every galaxy of
+ * every bin; n_centres: HOST array of n_z counts with the t3_forward
+ * convention per bin (a count < 0 selects every galaxy of that bin and
+ * needs a NULL pointer).  ups_out: DEVICE [n_z][n_z][n_z][5][n_max+1][B][B][2].
+ * The normaliser is N_n(Z1,Z2,Z3) = sum_{i in Z1} w_i W^{(Z2)}_n W^{(Z3)*}_n;
+ * j = k terms are removed only for Z2 == Z3.  1 <= n_z <= 8. */
+int t3_forward_tomo(t3_plan *plan, const t3_catalog *cats, int32_t n_z,
+                    const int32_t *const *centres, const int64_t *n_centres,
+                    double *ups_out, int64_t *n_pairs, void *stream);
+
+/* Stage 1 alone, for inspection: the harmonic sums of eq. (Gn_disc) for
+ * the given centres against the neighbour catalog.
+ * centres: DEVICE int32 [n_centres] indices into cat.
+ * G_out:   DEVICE float [n_centres][B][2 n_max + 3][2], orders
+ *          m = -n_max-3 .. n_max-1;
+ * W_out:   DEVICE float [n_centres][B][n_max + 1][2], orders m = 0..n_max;
+ * D_out:   DEVICE float [n_centres][B][4][2]: sum c_j^2 e^{-6i phi},
+ *          sum c_j^2 e^{-2i phi}, sum |c_j|^2 e^{-2i phi}, sum w_j^2. */
+int t3_harmonics(t3_plan *plan, const t3_catalog *cat, const int32_t *centres,
+                 int64_t n_centres, float *G_out, float *W_out, float *D_out,
+                 void *stream);
+
+/* Normalisation and resummation in FP64 (Sect. 3.4, eq. Gamma0_binned).
+ * ups:       DEVICE double [n_sets][5][n_max+1][B][B][2] (t3_forward output,
+ *            n_sets = 1, or n_z^3 for tomography).
+ * gamma_n:   DEVICE double [n_sets][4][n_max+1][B][B][2]:
+ *            Gamma_{mu,n} = Upsilon_{mu,n} / N_0 (0 where N_0 == 0).
+ * gamma_phi: DEVICE double [n_sets][4][B][B][n_phi][2] or NULL:
+ *            sum_{|n|<=n_max} Gamma_{mu,n} s_n(Phi_k), with angular bins
+ *            Phi_k = [2 pi k / n_phi, 2 pi (k+1) / n_phi) and
+ *            s_n = (e^{i n Phi_up} - e^{i n Phi_lo}) / (i n dPhi), s_0 = 1.
+ *            Negative n come from the symmetries (tomographic sets use the
+ *            set with Z2 and Z3 swapped).  1 <= n_phi <= 4096. */
+int t3_normalise_resum(t3_plan *plan, const double *ups, int32_t n_sets,
+                       int32_t n_phi, double *gamma_n, double *gamma_phi,
+                       void *stream);
+
+/* Adjoint of the non-tomographic forward pass (hand-written, recomputing
+ * the harmonic sums).  Given dL/dUpsilon (grad_ups, DEVICE, same layout as
+ * ups, holding dL/dRe and dL/dIm of each entry), accumulates dL/dg1,
+ * dL/dg2, dL/dw for every galaxy of cat (DEVICE float [cat->n], overwritten).
+ * Centres are all galaxies of cat. */
+int t3_backward(t3_plan *plan, const t3_catalog *cat, const double *grad_ups,
+                float *grad_g1, float *grad_g2, float *grad_w, void *stream);
+
+/* Stage timings of the most recent t3_forward / t3_forward_tomo call of a
+ * plan created with T3_FLAG_TIMING, from HIP events recorded on the
+ * caller's stream around each launch group.  ms[4] (HOST) receives the
+ * summed durations in milliseconds of: [0] cell-list build and centre
+ * gather, [1] stage 1 (neighbour scan, all chunks), [2] stage 2 (contraction
+ * over centres incl. j = k sums and FP64 reduction), [3] unused (0);
+ * launches[4] (HOST, optional) the number of stage-1 / stage-2 kernel
+ * launches timed.  Returns T3_EINVAL if the plan has no timing flag. */
+int t3_stage_times(const t3_plan *plan, double *ms, int64_t *launches);
+
+/* Static description of an error code. */
+const char *t3_error_string(int code);
+
+/* Thread-local message describing the last failure on this thread. */
+const char *t3_last_error_message(void);
+
+/* Library version string. */
+const char *t3_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* T3PCF_H */

@@ -55,8 +55,15 @@ def _load():
         lib.o1_harmonics.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_int64, dp, dp, dp, dp, dp,
                                      ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      dp, dp, dp, lp]
+        lib.o1_threads.restype = ctypes.c_int
+        lib.o1_threads.argtypes = []
         _lib = lib
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the C core runs with."""
+    return int(_load().o1_threads())
 
 
 def _dp(a: np.ndarray):

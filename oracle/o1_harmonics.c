@@ -29,9 +29,16 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Number of OpenMP threads the oracle uses. */
+int o1_threads(void)
+{
+    return omp_get_max_threads();
+}
 
 static int find_bin(double r2, int n_bins, const double *e2)
 {

@@ -1,0 +1,483 @@
+// Stage 1 of the multipole estimator: per-centre harmonic sums
+//     G_m(i; b) = sum_j c_j z_ij^m,   W_m(i; b) = sum_j w_j z_ij^m,
+// z_ij = e^{i phi_ij}, over the neighbours j of centre i in radial bin b
+// (Porth et al. 2023, eq. Gn_disc and the W_n of eq. 3PCF_Normalization),
+// plus the single-neighbour sums that remove j = k from the products.
+//
+// Mapping (one wavefront per centre, one radial bin at a time):
+//  * the annulus [e_b, e_{b+1}) around the centre is covered by, per cell
+//    row, at most two runs of cells; each run is one contiguous range of the
+//    cell-sorted catalog, computed per centre in FP64;
+//  * 64 lanes test 64 consecutive candidates, in-bin ones are compacted with
+//    a ballot into a 128-entry LDS ring; every time 64 are pending each lane
+//    takes one neighbour through the harmonic recurrence (lane = neighbour);
+//  * per-lane FP32 accumulators hold one bin of one centre; at the end of the
+//    bin a 6-step reduce-scatter leaves each lane a few finished sums, which
+//    it stores into the chunk planes (layout in t3_internal.h).
+//
+// Arithmetic per neighbour: dx, dy are exact lattice integers, r^2 is exact
+// in FP64 and is compared with the same FP64 squared edges as everywhere
+// else, so bin membership is exact.  z is formed in FP64 (rsqrt seed + one
+// Newton step), anchors z^{8k} are FP64 and rounded once to FP32; between
+// anchors powers p_m = z^m advance by FP32 complex multiplication, so the
+// error of any p_m is a few FP32 ulp whatever m.  G_m and G_{-m} share p_m:
+//     S1 += Re c Re p,  S2 += Im c Im p,  S3 += Re c Im p,  S4 += Im c Re p
+//     G_m = (S1 - S2, S3 + S4),   G_{-m} = (S1 + S2, S4 - S3)
+// which costs 4 FMAs for two orders.
+#include "t3_internal.h"
+
+namespace t3 {
+namespace {
+
+constexpr int kWaves = 4;       // wavefronts (centres) per workgroup
+constexpr int kRing = 128;      // LDS ring entries per wavefront
+constexpr int kAnchor = 8;      // FP64 anchor stride of the power recurrence
+constexpr int kMaxBins = 64;
+constexpr int kFlush = 32;      // batches of 64 neighbours per FP32 run before FP64 promotion
+
+struct ScanArgs {
+    const int2 *npos;       // cell-sorted neighbour positions
+    const float4 *ncw;      // (w g1, w g2, w, 0) in the same order
+    const int *cell_start;  // [ncells + 1]
+    CellGrid g;
+    const int2 *cpos;       // centre positions (chunk-relative)
+    const float4 *ccw;      // centre factors (unused here, kept for symmetry)
+    int n_c;                // centres in the chunk
+    int n_bins;
+    int n_max;
+    int K;                  // chunk capacity (plane layout)
+    float *out;             // chunk planes
+    const short *dest;      // slot -> plane (or -1) for this pass
+    unsigned long long *npairs;
+    double e2[kMaxBins + 1];
+};
+
+__device__ __forceinline__ long long floor_div(long long a, long long b)
+{
+    long long q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+__device__ __forceinline__ long long ceil_div(long long a, long long b)
+{
+    return -floor_div(-a, b);
+}
+
+// Per-pass register footprint.
+template <int GA, int GB, int WA, int WB, bool EXTRA>
+struct PassShape {
+    static constexpr int NG = GB >= GA ? GB - GA + 1 : 0;  // +-m order pairs
+    static constexpr int NW = WB >= WA ? WB - WA + 1 : 0;  // W orders
+    static constexpr int NX = EXTRA ? 11 : 0;               // G0, W0, D terms
+    static constexpr int V = 4 * NG + 2 * NW + NX;
+    static constexpr int P = (V + 63) / 64;                // slots per lane after reduce
+    static constexpr int VP = 64 * P;
+    static constexpr int M0 = GA > 1 ? ((GA - 1) / kAnchor) * kAnchor : 0;
+    static constexpr int MTOP = GB > WB ? GB : WB;
+};
+
+// One neighbour through the recurrence.  acc layout: [4*NG S-sums][2*NW W][NX extras]
+template <int GA, int GB, int WA, int WB, bool EXTRA, int V>
+__device__ __forceinline__ void accumulate(float (&acc)[V], int dx, int dy, float cr, float ci,
+                                           float wt)
+{
+    using S = PassShape<GA, GB, WA, WB, EXTRA>;
+    static_assert(V == S::V, "accumulator size");
+    const double xd = (double)dx, yd = (double)dy;
+    const double r2 = fma(xd, xd, yd * yd);
+    double s = (double)__builtin_amdgcn_rsqf((float)r2);
+    s = s * fma(-0.5 * r2 * s, s, 1.5);
+    const double zr = xd * s, zi = yd * s;
+    const float fzr = (float)zr, fzi = (float)zi;
+    // z^2, z^4, z^8 in FP64
+    const double z2r = fma(zr, zr, -zi * zi), z2i = 2.0 * zr * zi;
+    const double z4r = fma(z2r, z2r, -z2i * z2i), z4i = 2.0 * z2r * z2i;
+    const double z8r = fma(z4r, z4r, -z4i * z4i), z8i = 2.0 * z4r * z4i;
+    // running FP64 anchor a = z^{M0}
+    double ar = 1.0, ai = 0.0;
+#pragma unroll
+    for (int k = 0; k < S::M0 / kAnchor; ++k) {
+        const double tr = fma(ar, z8r, -ai * z8i);
+        ai = fma(ar, z8i, ai * z8r);
+        ar = tr;
+    }
+    float pr = (float)ar, pi = (float)ai;
+#pragma unroll
+    for (int m = S::M0 + 1; m <= S::MTOP; ++m) {
+        if (m % kAnchor == 0) {
+            const double tr = fma(ar, z8r, -ai * z8i);
+            ai = fma(ar, z8i, ai * z8r);
+            ar = tr;
+            pr = (float)ar;
+            pi = (float)ai;
+        } else {
+            const float tr = fmaf(pr, fzr, -pi * fzi);
+            pi = fmaf(pr, fzi, pi * fzr);
+            pr = tr;
+        }
+        if (m >= GA && m <= GB) {
+            const int k = 4 * (m - GA);
+            acc[k + 0] = fmaf(cr, pr, acc[k + 0]);
+            acc[k + 1] = fmaf(ci, pi, acc[k + 1]);
+            acc[k + 2] = fmaf(cr, pi, acc[k + 2]);
+            acc[k + 3] = fmaf(ci, pr, acc[k + 3]);
+        }
+        if (m >= WA && m <= WB) {
+            const int k = 4 * S::NG + 2 * (m - WA);
+            acc[k + 0] = fmaf(wt, pr, acc[k + 0]);
+            acc[k + 1] = fmaf(wt, pi, acc[k + 1]);
+        }
+    }
+    if constexpr (EXTRA) {
+        constexpr int k = 4 * S::NG + 2 * S::NW;
+        // G_0 += c ; W_0 += w (imaginary part stays 0)
+        acc[k + 0] += cr;
+        acc[k + 1] += ci;
+        acc[k + 2] += wt;
+        // z^-2, z^-6 (conjugates of FP64 powers rounded once)
+        const float p2r = (float)z2r, p2i = (float)z2i;
+        const double z6r = fma(z4r, z2r, -z4i * z2i), z6i = fma(z4r, z2i, z4i * z2r);
+        const float p6r = (float)z6r, p6i = (float)z6i;
+        const float c2r = fmaf(cr, cr, -ci * ci), c2i = 2.0f * cr * ci;
+        const float a2 = fmaf(cr, cr, ci * ci);
+        // D6 += c^2 conj(z^6)
+        acc[k + 4] = fmaf(c2r, p6r, fmaf(c2i, p6i, acc[k + 4]));
+        acc[k + 5] = fmaf(c2i, p6r, fmaf(-c2r, p6i, acc[k + 5]));
+        // D2 += c^2 conj(z^2)
+        acc[k + 6] = fmaf(c2r, p2r, fmaf(c2i, p2i, acc[k + 6]));
+        acc[k + 7] = fmaf(c2i, p2r, fmaf(-c2r, p2i, acc[k + 7]));
+        // DA += |c|^2 conj(z^2)
+        acc[k + 8] = fmaf(a2, p2r, acc[k + 8]);
+        acc[k + 9] = fmaf(-a2, p2i, acc[k + 9]);
+        // DW += w^2
+        acc[k + 10] = fmaf(wt, wt, acc[k + 10]);
+    }
+}
+
+// Wave reduction of the per-lane accumulators: S -> G conversion, then a
+// 6-step reduce-scatter (each step exchanges half of the remaining slots
+// with the partner lane), after which lane l holds the wave totals of slots
+// [P l, P l + P).  These are added to the lane's FP64 partials and the FP32
+// accumulators restart from zero.
+template <int GA, int GB, int WA, int WB, bool EXTRA, int V, int P>
+__device__ __forceinline__ void flush(float (&acc)[V], double (&accd)[P], int lane)
+{
+    using S = PassShape<GA, GB, WA, WB, EXTRA>;
+    float v[S::VP];
+#pragma unroll
+    for (int k = 0; k < S::NG; ++k) {
+        const float s1 = acc[4 * k], s2 = acc[4 * k + 1], s3 = acc[4 * k + 2], s4 = acc[4 * k + 3];
+        v[4 * k + 0] = s1 - s2;  // Re G_m
+        v[4 * k + 1] = s3 + s4;  // Im G_m
+        v[4 * k + 2] = s1 + s2;  // Re G_-m
+        v[4 * k + 3] = s4 - s3;  // Im G_-m
+    }
+#pragma unroll
+    for (int k = 4 * S::NG; k < S::V; ++k) v[k] = acc[k];
+#pragma unroll
+    for (int k = S::V; k < S::VP; ++k) v[k] = 0.0f;
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int d = 32 >> st;
+        const int L = S::VP >> st;
+        const bool hi = (lane & d) != 0;
+#pragma unroll
+        for (int k = 0; k < L / 2; ++k) {
+            const float keep = hi ? v[k + L / 2] : v[k];
+            const float send = hi ? v[k] : v[k + L / 2];
+            v[k] = keep + __shfl_xor(send, d, 64);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < S::P; ++k) accd[k] += (double)v[k];
+#pragma unroll
+    for (int k = 0; k < S::V; ++k) acc[k] = 0.0f;
+}
+
+template <int GA, int GB, int WA, int WB, bool EXTRA>
+__global__ __launch_bounds__(64 * kWaves) void k_scan(ScanArgs a)
+{
+    using S = PassShape<GA, GB, WA, WB, EXTRA>;
+    __shared__ int4 q_xyc[kWaves][kRing];  // dx, dy, bits(Re c), bits(Im c)
+    __shared__ float q_w[kWaves][kRing];
+    __shared__ int2 spans[kWaves][128];
+
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    // XCD-aware order: consecutive centres stay on one XCD (round-robin dispatch)
+    const int nwg = gridDim.x;  // multiple of 8
+    const int per = nwg >> 3;
+    const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int ci = wg * kWaves + wv;
+    if (ci >= a.n_c) return;  // whole wavefront leaves together
+
+    const int2 cp = a.cpos[ci];
+    const CellGrid g = a.g;
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    unsigned long long pairs = 0;
+
+    for (int b = 0; b < a.n_bins; ++b) {
+        const double e2lo = a.e2[b], e2hi = a.e2[b + 1];
+        float acc[S::V];
+#pragma unroll
+        for (int k = 0; k < S::V; ++k) acc[k] = 0.0f;
+        double accd[S::P];
+#pragma unroll
+        for (int k = 0; k < S::P; ++k) accd[k] = 0.0;
+        int batches = 0;  // wave-uniform: batches since the last FP64 promotion
+
+        const long long R = (long long)sqrt(e2hi) + 1;
+        long long row_lo = floor_div((long long)cp.y - R - g.oy, g.cell);
+        long long row_hi = floor_div((long long)cp.y + R - g.oy, g.cell);
+        row_lo = row_lo < 0 ? 0 : row_lo;
+        row_hi = row_hi > g.ncy - 1 ? g.ncy - 1 : row_hi;
+
+        int head = 0, tail = 0;  // wave-uniform ring pointers
+        for (long long r0 = row_lo; r0 <= row_hi; r0 += 64) {
+            // ---- lanes build the (up to) two galaxy ranges of their cell row
+            int2 sa = make_int2(0, 0), sb = make_int2(0, 0);
+            const long long r = r0 + lane;
+            if (r <= row_hi) {
+                const long long y0 = (long long)g.oy + r * g.cell;
+                const long long y1 = y0 + g.cell - 1;
+                const long long py = cp.y, px = cp.x;
+                const long long dyn = py < y0 ? y0 - py : (py > y1 ? py - y1 : 0);
+                const long long d0 = y0 - py < 0 ? py - y0 : y0 - py;
+                const long long d1 = y1 - py < 0 ? py - y1 : y1 - py;
+                const long long dyx = d0 > d1 ? d0 : d1;
+                const double dmin2 = (double)dyn * (double)dyn;
+                const double dmax2 = (double)dyx * (double)dyx;
+                if (dmin2 < e2hi) {
+                    const long long xr = (long long)sqrt(e2hi - dmin2) + 1;
+                    long long c_lo = floor_div(px - xr - g.ox, g.cell);
+                    long long c_hi = floor_div(px + xr - g.ox, g.cell);
+                    c_lo = c_lo < 0 ? 0 : c_lo;
+                    c_hi = c_hi > g.ncx - 1 ? g.ncx - 1 : c_hi;
+                    long long a0 = c_lo, a1 = c_hi, b0 = 1, b1 = 0;
+                    if (e2lo > dmax2) {
+                        const long long xin = (long long)sqrt(e2lo - dmax2) - 1;
+                        if (xin >= 0) {
+                            const long long in_lo = ceil_div(px - xin - g.ox, g.cell);
+                            const long long in_hi = floor_div(px + xin - g.ox + 1, g.cell) - 1;
+                            if (in_lo <= in_hi) {
+                                a1 = c_hi < in_lo - 1 ? c_hi : in_lo - 1;
+                                b0 = c_lo > in_hi + 1 ? c_lo : in_hi + 1;
+                                b1 = c_hi;
+                            }
+                        }
+                    }
+                    const int *cs = a.cell_start + r * g.ncx;
+                    if (a0 <= a1) sa = make_int2(cs[a0], cs[a1 + 1]);
+                    if (b0 <= b1) sb = make_int2(cs[b0], cs[b1 + 1]);
+                }
+            }
+            spans[wv][2 * lane] = sa;
+            spans[wv][2 * lane + 1] = sb;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int nsp = 2 * (int)((row_hi - r0 + 1) < 64 ? (row_hi - r0 + 1) : 64);
+            for (int t = 0; t < nsp; ++t) {
+                const int2 sp = spans[wv][t];
+                for (int g0 = sp.x; g0 < sp.y; g0 += 64) {
+                    const int gi = g0 + lane;
+                    const bool valid = gi < sp.y;
+                    int2 p = make_int2(cp.x, cp.y);
+                    if (valid) p = a.npos[gi];
+                    const int dx = p.x - cp.x, dy = p.y - cp.y;
+                    const double r2 = fma((double)dx, (double)dx, (double)dy * (double)dy);
+                    const bool in = valid && r2 >= e2lo && r2 < e2hi;
+                    const unsigned long long m = __ballot(in);
+                    if (in) {
+                        const int slot = (tail + __popcll(m & lt_mask)) & (kRing - 1);
+                        const float4 c = a.ncw[gi];
+                        q_xyc[wv][slot] = make_int4(dx, dy, __float_as_int(c.x), __float_as_int(c.y));
+                        q_w[wv][slot] = c.z;
+                    }
+                    tail += __popcll(m);
+                    if (tail - head >= 64) {
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        const int slot = (head + lane) & (kRing - 1);
+                        const int4 e = q_xyc[wv][slot];
+                        const float ew = q_w[wv][slot];
+                        accumulate<GA, GB, WA, WB, EXTRA>(acc, e.x, e.y, __int_as_float(e.z),
+                                                          __int_as_float(e.w), ew);
+                        head += 64;
+                        if (++batches == kFlush) {
+                            flush<GA, GB, WA, WB, EXTRA>(acc, accd, lane);
+                            batches = 0;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (tail > head) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const bool act = lane < tail - head;
+            const int slot = (head + lane) & (kRing - 1);
+            int4 e = q_xyc[wv][slot];
+            float ew = q_w[wv][slot];
+            if (!act) e = make_int4(1, 0, 0, 0), ew = 0.0f;
+            accumulate<GA, GB, WA, WB, EXTRA>(acc, e.x, e.y, __int_as_float(e.z),
+                                              __int_as_float(e.w), ew);
+        }
+        pairs += (unsigned long long)(tail);
+
+        flush<GA, GB, WA, WB, EXTRA>(acc, accd, lane);
+        // lane holds slots [P*lane, P*lane + P)
+#pragma unroll
+        for (int k = 0; k < S::P; ++k) {
+            const int slot = S::P * lane + k;
+            const int pl = a.dest[slot];
+            if (pl >= 0) a.out[chunk_offset(pl, ci, b, a.K, a.n_bins)] = (float)accd[k];
+        }
+    }
+    if (lane == 0 && a.npairs) atomicAdd(a.npairs, pairs);
+}
+
+// --------------------------------------------------------------- host side
+struct PassDesc {
+    int ga, gb, wa, wb;
+    bool extra;
+    void (*kernel)(ScanArgs);
+};
+
+template <int GA, int GB, int WA, int WB, bool EXTRA>
+PassDesc make_pass()
+{
+    return PassDesc{GA, GB, WA, WB, EXTRA, k_scan<GA, GB, WA, WB, EXTRA>};
+}
+
+// Variant table: a single pass for n_max up to the capacity C (orders
+// 1..C+3 for G, 1..C for W); two passes beyond 32.
+struct Variant {
+    int cap;
+    int npass;
+    PassDesc pass[2];
+};
+
+const std::vector<Variant> &variants()
+{
+    static const std::vector<Variant> v = {
+        {2, 1, {make_pass<1, 5, 1, 2, true>()}},
+        {4, 1, {make_pass<1, 7, 1, 4, true>()}},
+        {8, 1, {make_pass<1, 11, 1, 8, true>()}},
+        {10, 1, {make_pass<1, 13, 1, 10, true>()}},
+        {12, 1, {make_pass<1, 15, 1, 12, true>()}},
+        {16, 1, {make_pass<1, 19, 1, 16, true>()}},
+        {20, 1, {make_pass<1, 23, 1, 20, true>()}},
+        {24, 1, {make_pass<1, 27, 1, 24, true>()}},
+        {30, 1, {make_pass<1, 33, 1, 30, true>()}},
+        {32, 1, {make_pass<1, 35, 1, 32, true>()}},
+        {40, 2, {make_pass<1, 22, 1, 20, true>(), make_pass<23, 43, 21, 40, false>()}},
+        {48, 2, {make_pass<1, 26, 1, 24, true>(), make_pass<27, 51, 25, 48, false>()}},
+        {64, 2, {make_pass<1, 34, 1, 32, true>(), make_pass<35, 67, 33, 64, false>()}},
+    };
+    return v;
+}
+
+// Destination table of one pass for a given n_max: slot -> plane or -1.
+std::vector<short> dest_table(const PassDesc &p, const ChunkLayout &L)
+{
+    const int NG = p.gb >= p.ga ? p.gb - p.ga + 1 : 0;
+    const int NW = p.wb >= p.wa ? p.wb - p.wa + 1 : 0;
+    const int V = 4 * NG + 2 * NW + (p.extra ? 11 : 0);
+    const int VP = 64 * ((V + 63) / 64);
+    std::vector<short> d(VP, -1);
+    const int nm = L.n_max;
+    for (int k = 0; k < NG; ++k) {
+        const int m = p.ga + k;
+        if (m <= nm - 1) {
+            d[4 * k + 0] = (short)L.plane_G(m, 0);
+            d[4 * k + 1] = (short)L.plane_G(m, 1);
+        }
+        if (m <= nm + 3) {
+            d[4 * k + 2] = (short)L.plane_G(-m, 0);
+            d[4 * k + 3] = (short)L.plane_G(-m, 1);
+        }
+    }
+    for (int k = 0; k < NW; ++k) {
+        const int m = p.wa + k;
+        if (m <= nm) {
+            d[4 * NG + 2 * k] = (short)L.plane_W(m, 0);
+            d[4 * NG + 2 * k + 1] = (short)L.plane_W(m, 1);
+        }
+    }
+    if (p.extra) {
+        const int k = 4 * NG + 2 * NW;
+        if (nm >= 1) {  // G_0 is needed only for n_max >= 1
+            d[k + 0] = (short)L.plane_G(0, 0);
+            d[k + 1] = (short)L.plane_G(0, 1);
+        }
+        d[k + 2] = (short)L.plane_W(0, 0);
+        d[k + 3] = (short)L.plane_W(0, 1);  // stays zero
+        for (int j = 0; j < 7; ++j) d[k + 4 + j] = (short)L.plane_D(j);
+    }
+    return d;
+}
+
+}  // namespace
+
+int scan_prepare(t3_plan *plan)
+{
+    const auto &vars = variants();
+    int vi = -1;
+    for (size_t i = 0; i < vars.size(); ++i)
+        if (vars[i].cap >= plan->n_max) {
+            vi = (int)i;
+            break;
+        }
+    if (vi < 0) return fail(T3_ERANGE, "n_max above the largest compiled variant");
+    ChunkLayout L;
+    L.n_max = plan->n_max;
+    L.B = plan->B;
+    std::vector<short> all;
+    for (int p = 0; p < vars[vi].npass; ++p) {
+        plan->scan_dest_off[p] = all.size();
+        auto d = dest_table(vars[vi].pass[p], L);
+        all.insert(all.end(), d.begin(), d.end());
+    }
+    T3_TRY(plan->dest.reserve(all.size() * sizeof(short)));
+    T3_HIP_CHECK(hipMemcpy(plan->dest.ptr, all.data(), all.size() * sizeof(short),
+                           hipMemcpyHostToDevice));
+    plan->scan_var = vi;
+    return T3_OK;
+}
+
+int scan_chunk(t3_plan *plan, const SortedCatalog &sc, const CentreSet &cs, int64_t c0, int n_c,
+               const ChunkLayout &L, float *planes, unsigned long long *npairs, hipStream_t s)
+{
+    if (n_c <= 0) return T3_OK;
+    if (plan->scan_var < 0) T3_TRY(scan_prepare(plan));
+    const Variant &var = variants()[plan->scan_var];
+    ScanArgs a{};
+    a.npos = sc.pos.as<int2>();
+    a.ncw = sc.cw.as<float4>();
+    a.cell_start = sc.cell_start.as<int>();
+    a.g = sc.grid;
+    a.cpos = cs.pos.as<int2>() + c0;
+    a.ccw = cs.cw.as<float4>() + c0;
+    a.n_c = n_c;
+    a.n_bins = L.B;
+    a.n_max = L.n_max;
+    a.K = L.K;
+    a.out = planes;
+    for (int b = 0; b <= L.B; ++b) a.e2[b] = plan->e2[b];
+    int nwg = (n_c + kWaves - 1) / kWaves;
+    nwg = (nwg + 7) & ~7;
+    for (int p = 0; p < var.npass; ++p) {
+        a.dest = plan->dest.as<short>() + plan->scan_dest_off[p];
+        a.npairs = p == 0 ? npairs : nullptr;  // count pairs once
+        hipLaunchKernelGGL(var.pass[p].kernel, dim3((unsigned)nwg), dim3(64 * kWaves), 0, s, a);
+        T3_HIP_CHECK(hipGetLastError());
+    }
+    return T3_OK;
+}
+
+}  // namespace t3

@@ -1,0 +1,166 @@
+// Internal declarations shared by the t3pcf HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "t3pcf.h"
+
+namespace t3 {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define T3_HIP_CHECK(expr)                                                          \
+    do {                                                                            \
+        hipError_t _e = (expr);                                                     \
+        if (_e != hipSuccess)                                                       \
+            return ::t3::fail(T3_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+#define T3_TRY(expr)                  \
+    do {                              \
+        int _rc = (expr);             \
+        if (_rc != T3_OK) return _rc; \
+    } while (0)
+
+// ---------------------------------------------------------------- device buffers
+// Grow-only device allocation owned by a plan.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int reserve(size_t want);
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// ---------------------------------------------------------------- chunk layout
+// Stage-1 output for a chunk of K centres (K a multiple of 4): "planes" of
+// FP32 values, one plane per (order, real/imag part) or per j = k sum.
+// Element (plane p, centre i, bin b) lives at
+//     ((p * (K/4) + i/4) * B + b) * 4 + (i & 3)
+// so that four consecutive centres of one bin are one 16-byte vector and a
+// row of B bins for those four centres is contiguous (stage-2 operand load).
+// Plane numbering, with n_g = 2 n_max + 3 G orders m = -n_max-3 .. n_max-1:
+//     G_m   : 2 (m + n_max + 3) + {0 re, 1 im}
+//     W_m   : 2 n_g + 2 m + {0, 1},          m = 0 .. n_max
+//     D     : 2 n_g + 2 (n_max + 1) + {0..6} = D6 re, D6 im, D2 re, D2 im,
+//             DA re, DA im, DW
+struct ChunkLayout {
+    int n_max = 0, B = 0, K = 0;
+    int n_g() const { return 2 * n_max + 3; }
+    int plane_G(int m, int part) const { return 2 * (m + n_max + 3) + part; }
+    int plane_W(int m, int part) const { return 2 * n_g() + 2 * m + part; }
+    int plane_D(int d) const { return 2 * n_g() + 2 * (n_max + 1) + d; }
+    int n_planes() const { return plane_D(0) + 7; }
+    size_t plane_stride() const { return (size_t)K * B; }  // floats per plane
+    size_t floats() const { return (size_t)n_planes() * plane_stride(); }
+};
+
+__host__ __device__ inline size_t chunk_offset(int p, int i, int b, int K, int B)
+{
+    return (((size_t)p * (K >> 2) + (size_t)(i >> 2)) * B + b) * 4 + (i & 3);
+}
+
+// ---------------------------------------------------------------- cell grid
+struct CellGrid {
+    int cell = 1;        // side, lattice steps
+    int ncx = 1, ncy = 1;
+    int ox = 0, oy = 0;  // lattice origin of cell (0, 0)
+    int64_t ncells() const { return (int64_t)ncx * ncy; }
+};
+
+// Cell-sorted copy of one neighbour catalog.
+struct SortedCatalog {
+    int64_t n = 0;
+    CellGrid grid;
+    DevBuf pos;         // int2  [n]   (x, y)
+    DevBuf cw;          // float4[n]   (w g1, w g2, w, 0)
+    DevBuf cell_start;  // int   [ncells + 1]
+    DevBuf perm;        // int   [n]   sorted slot -> original index
+    DevBuf keys;        // int   [n]   scratch
+    DevBuf counts;      // int   [ncells + 1] scratch
+    DevBuf scan_tmp;    // int   scratch for the block sums
+};
+
+// Centres of one forward call (gathered positions and factors).
+struct CentreSet {
+    int64_t n = 0;
+    DevBuf pos;  // int2  [n]
+    DevBuf cw;   // float4[n]
+};
+
+}  // namespace t3
+
+// ---------------------------------------------------------------- plan
+struct t3_plan {
+    int B = 0, n_max = 0, precision = 0;
+    uint32_t flags = 0;
+    double unit = 0;
+    std::vector<double> edges_lat;  // [B+1] edges in lattice steps
+    std::vector<double> e2;         // [B+1] squared, lattice steps^2
+    int32_t box_lo_x = 0, box_lo_y = 0;
+    int64_t box_size = 0;
+    double cell_arcmin = 0;
+    int chunk_req = 0;
+    int device = 0;
+
+    t3::SortedCatalog cats[8];
+    t3::CentreSet centres;
+    t3::DevBuf chunk;     // stage-1 planes
+    t3::DevBuf partial;   // stage-2 FP64 partial tiles
+    t3::DevBuf diag;      // FP64 j = k sums per chunk
+    t3::DevBuf flag;      // int error flag (lattice bounds)
+    t3::DevBuf dest;      // int16 destination tables of the stage-1 passes
+    t3::DevBuf scales;    // fp16 row scales
+    t3::DevBuf counter;   // uint64 pair counter
+    t3::DevBuf misc;      // adjoint scratch
+    t3::DevBuf misc2;
+    int scan_var = -1;          // stage-1 variant index (see scan.hip)
+    size_t scan_dest_off[2] = {0, 0};
+
+    // optional stage timing (T3_FLAG_TIMING)
+    std::vector<hipEvent_t> events;  // pool, pairs (start, stop)
+    std::vector<int> event_stage;    // stage of each pair
+    size_t events_used = 0;          // pairs recorded in the current call
+    double stage_ms[4] = {0, 0, 0, 0};
+    int64_t stage_launches[4] = {0, 0, 0, 0};
+};
+
+namespace t3 {
+
+// Launchers (each returns T3_OK or an error; all asynchronous on `s`).
+int build_cells(t3_plan *plan, SortedCatalog &sc, const t3_catalog &cat, const CellGrid &g,
+                hipStream_t s);
+int gather_centres(t3_plan *plan, const t3_catalog &cat, const int32_t *idx, int64_t n,
+                   CentreSet &cs, hipStream_t s);
+int gather_sorted_centres(t3_plan *plan, const SortedCatalog &sc, CentreSet &cs, hipStream_t s);
+int check_flag(t3_plan *plan, hipStream_t s, const char *what);
+
+int scan_prepare(t3_plan *plan);
+int scan_chunk(t3_plan *plan, const SortedCatalog &sc, const CentreSet &cs, int64_t c0, int n_c,
+               const ChunkLayout &L, float *planes, unsigned long long *npairs, hipStream_t s);
+int zero_doubles(double *p, size_t n, hipStream_t s);
+int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, const ChunkLayout &L,
+                   const float *planes_x, const float *planes_y, bool jk, double *ups_out,
+                   hipStream_t s);
+int normalise_resum(t3_plan *plan, const double *ups, int n_sets, int n_z, int n_phi,
+                    double *gamma_n, double *gamma_phi, hipStream_t s);
+int harmonics_export(t3_plan *plan, const CentreSet &cs, const ChunkLayout &L, const float *planes,
+                     int64_t c0, int n_c, float *G, float *W, float *D, hipStream_t s);
+int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float *gg1, float *gg2,
+             float *gw, hipStream_t s);
+
+// Stage timing helpers (no-ops unless the plan has T3_FLAG_TIMING).
+int timing_begin_call(t3_plan *plan);
+int timing_mark(t3_plan *plan, int stage, bool start, hipStream_t s);
+int timing_end_call(t3_plan *plan);  // after the stream has been synchronised
+
+CellGrid choose_grid(const t3_plan *plan, int64_t n_gal);
+int choose_chunk(const t3_plan *plan, const ChunkLayout &L);
+
+}  // namespace t3

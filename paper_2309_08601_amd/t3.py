@@ -1,0 +1,248 @@
+"""Thin ctypes binding of the t3pcf C ABI (include/t3pcf.h).
+
+Argument marshalling only: every step of the estimator runs in the HIP
+library.  PyTorch provides device memory and the current stream.  If the
+library is not built this module raises on import; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libt3pcf.so")
+
+T3_OK = 0
+T3_EINVAL = -1
+T3_ERANGE = -2
+T3_ENOMEM = -3
+T3_EHIP = -4
+T3_ELATTICE = -5
+
+PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
+T3_FLAG_KEEP_JK = 1
+T3_FLAG_TIMING = 2
+
+
+class t3_params(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("edges", ctypes.POINTER(ctypes.c_double)),
+                ("n_max", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("lattice_unit", ctypes.c_double), ("box_lo_x", ctypes.c_int32),
+                ("box_lo_y", ctypes.c_int32), ("box_size", ctypes.c_int64),
+                ("cell_arcmin", ctypes.c_double), ("chunk_centres", ctypes.c_int32)]
+
+
+class t3_catalog(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("g1", ctypes.c_void_p), ("g2", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+
+
+class T3Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"t3pcf error {code}: {msg}")
+        self.code = code
+
+
+EXPORTED = ["t3_plan_create", "t3_plan_destroy", "t3_forward", "t3_forward_tomo", "t3_harmonics",
+            "t3_normalise_resum", "t3_backward", "t3_stage_times", "t3_error_string",
+            "t3_last_error_message", "t3_version"]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"t3pcf HIP library not built: {path} (run paper_2309_08601_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    lib.t3_plan_create.argtypes = [P(t3_params), P(vp)]
+    lib.t3_plan_create.restype = ctypes.c_int
+    lib.t3_plan_destroy.argtypes = [vp]
+    lib.t3_plan_destroy.restype = None
+    lib.t3_forward.argtypes = [vp, P(t3_catalog), vp, ctypes.c_int64, vp, P(ctypes.c_int64), vp]
+    lib.t3_forward.restype = ctypes.c_int
+    lib.t3_forward_tomo.argtypes = [vp, P(t3_catalog), ctypes.c_int32, P(vp), P(ctypes.c_int64), vp,
+                                    P(ctypes.c_int64), vp]
+    lib.t3_forward_tomo.restype = ctypes.c_int
+    lib.t3_harmonics.argtypes = [vp, P(t3_catalog), vp, ctypes.c_int64, vp, vp, vp, vp]
+    lib.t3_harmonics.restype = ctypes.c_int
+    lib.t3_normalise_resum.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+    lib.t3_normalise_resum.restype = ctypes.c_int
+    lib.t3_backward.argtypes = [vp, P(t3_catalog), vp, vp, vp, vp, vp]
+    lib.t3_backward.restype = ctypes.c_int
+    lib.t3_stage_times.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
+    lib.t3_stage_times.restype = ctypes.c_int
+    lib.t3_error_string.argtypes = [ctypes.c_int]
+    lib.t3_error_string.restype = ctypes.c_char_p
+    lib.t3_last_error_message.argtypes = []
+    lib.t3_last_error_message.restype = ctypes.c_char_p
+    lib.t3_version.argtypes = []
+    lib.t3_version.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(rc: int):
+    if rc != T3_OK:
+        raise T3Error(rc, _lib.t3_last_error_message().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class DeviceCatalog:
+    """Device-resident SoA catalog (int32 lattice positions, float32 shears)."""
+
+    def __init__(self, x, y, g1, g2, w, device="cuda"):
+        def t(a, dt):
+            return torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(device).contiguous()
+        self.x = t(x, torch.int32)
+        self.y = t(y, torch.int32)
+        self.g1 = t(g1, torch.float32)
+        self.g2 = t(g2, torch.float32)
+        self.w = t(w, torch.float32)
+        self.n = int(self.x.shape[0])
+
+    @classmethod
+    def from_catalog(cls, cat, device="cuda"):
+        return cls(cat.x, cat.y, cat.g1, cat.g2, cat.w, device=device)
+
+    def c_struct(self) -> t3_catalog:
+        return t3_catalog(self.n, self.x.data_ptr(), self.y.data_ptr(), self.g1.data_ptr(),
+                          self.g2.data_ptr(), self.w.data_ptr())
+
+
+class Plan:
+    """Owns one t3_plan (radial bins, n_max, precision, lattice box)."""
+
+    def __init__(self, edges: Sequence[float], n_max: int, box_lo=(0, 0), box_size: int = 1 << 30,
+                 precision: str = "fp32", keep_jk: bool = False, lattice_unit: float = 0.0,
+                 cell_arcmin: float = 0.0, chunk_centres: int = 0, timing: bool = False):
+        self.edges = np.ascontiguousarray(edges, dtype=np.float64)
+        self.B = len(self.edges) - 1
+        self.n_max = int(n_max)
+        p = t3_params(self.B, self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.n_max,
+                      PRECISIONS[precision],
+                      (T3_FLAG_KEEP_JK if keep_jk else 0) | (T3_FLAG_TIMING if timing else 0),
+                      float(lattice_unit),
+                      int(box_lo[0]), int(box_lo[1]), int(box_size), float(cell_arcmin),
+                      int(chunk_centres))
+        h = ctypes.c_void_p()
+        _check(_lib.t3_plan_create(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.t3_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _out_shape(self, sets: int = 1):
+        return (sets, 5, self.n_max + 1, self.B, self.B, 2)
+
+    def forward(self, cat: DeviceCatalog, centres: Optional[torch.Tensor] = None,
+                out: Optional[torch.Tensor] = None):
+        """Upsilon_{0..3,n} and N_n for n = 0..n_max: complex128 [5, n_max+1, B, B]."""
+        if out is None:
+            out = torch.empty(self._out_shape()[1:], dtype=torch.float64, device=cat.x.device)
+        cs = cat.c_struct()
+        npairs = ctypes.c_int64(0)
+        if centres is not None:
+            centres = centres.to(torch.int32).contiguous()
+        _check(_lib.t3_forward(self._h, ctypes.byref(cs), _ptr(centres),
+                               -1 if centres is None else int(centres.numel()), _ptr(out),
+                               ctypes.byref(npairs), _stream()))
+        return torch.view_as_complex(out), int(npairs.value)
+
+    def forward_tomo(self, cats: List[DeviceCatalog], centres: Optional[List[Optional[torch.Tensor]]] = None,
+                     out: Optional[torch.Tensor] = None):
+        nz = len(cats)
+        if out is None:
+            out = torch.empty((nz, nz, nz) + self._out_shape()[1:], dtype=torch.float64,
+                              device=cats[0].x.device)
+        arr = (t3_catalog * nz)(*[c.c_struct() for c in cats])
+        cptr = None
+        cnt = None
+        keep = []
+        if centres is not None:
+            cptr = (ctypes.c_void_p * nz)()
+            cnt = (ctypes.c_int64 * nz)()
+            for z, c in enumerate(centres):
+                if c is None:
+                    cptr[z] = None
+                    cnt[z] = -1
+                else:
+                    c = c.to(torch.int32).contiguous()
+                    keep.append(c)
+                    cptr[z] = c.data_ptr()
+                    cnt[z] = c.numel()
+        npairs = ctypes.c_int64(0)
+        _check(_lib.t3_forward_tomo(self._h, arr, nz, cptr, cnt, _ptr(out), ctypes.byref(npairs),
+                                    _stream()))
+        return torch.view_as_complex(out), int(npairs.value)
+
+    def harmonics(self, cat: DeviceCatalog, centres: torch.Tensor):
+        """Stage-1 sums: G [n_c, B, 2 n_max + 3] (m = -n_max-3 .. n_max-1),
+        W [n_c, B, n_max + 1], D [n_c, B, 4] (complex64)."""
+        centres = centres.to(torch.int32).contiguous()
+        nc = int(centres.numel())
+        dev = cat.x.device
+        G = torch.empty((nc, self.B, 2 * self.n_max + 3, 2), dtype=torch.float32, device=dev)
+        W = torch.empty((nc, self.B, self.n_max + 1, 2), dtype=torch.float32, device=dev)
+        D = torch.empty((nc, self.B, 4, 2), dtype=torch.float32, device=dev)
+        cs = cat.c_struct()
+        _check(_lib.t3_harmonics(self._h, ctypes.byref(cs), _ptr(centres), nc, _ptr(G), _ptr(W),
+                                 _ptr(D), _stream()))
+        return torch.view_as_complex(G), torch.view_as_complex(W), torch.view_as_complex(D)
+
+    def normalise_resum(self, ups: torch.Tensor, n_phi: int = 32, with_phi: bool = True):
+        """Gamma_{mu,n} = Upsilon/N_0 [.., 4, n_max+1, B, B] and the resummed
+        Gamma(b1, b2, Phi_k) [.., 4, B, B, n_phi] (complex128)."""
+        u = torch.view_as_real(ups).contiguous() if ups.is_complex() else ups.contiguous()
+        lead = u.shape[:-5]
+        sets = int(np.prod(lead)) if len(lead) else 1
+        gn = torch.empty(lead + (4, self.n_max + 1, self.B, self.B, 2), dtype=torch.float64,
+                         device=u.device)
+        gp = None
+        if with_phi:
+            gp = torch.empty(lead + (4, self.B, self.B, n_phi, 2), dtype=torch.float64, device=u.device)
+        _check(_lib.t3_normalise_resum(self._h, _ptr(u), sets, int(n_phi), _ptr(gn), _ptr(gp), _stream()))
+        return torch.view_as_complex(gn), (None if gp is None else torch.view_as_complex(gp))
+
+    def stage_times(self):
+        """(ms[4], launches[4]) of the last forward call (timing plans only):
+        cell build, stage 1, stage 2, unused."""
+        ms = (ctypes.c_double * 4)()
+        nl = (ctypes.c_int64 * 4)()
+        _check(_lib.t3_stage_times(self._h, ms, nl))
+        return list(ms), list(nl)
+
+    def backward(self, cat: DeviceCatalog, grad_ups: torch.Tensor):
+        g = torch.view_as_real(grad_ups).contiguous() if grad_ups.is_complex() else grad_ups.contiguous()
+        dev = cat.x.device
+        gg1 = torch.empty(cat.n, dtype=torch.float32, device=dev)
+        gg2 = torch.empty(cat.n, dtype=torch.float32, device=dev)
+        gw = torch.empty(cat.n, dtype=torch.float32, device=dev)
+        cs = cat.c_struct()
+        _check(_lib.t3_backward(self._h, ctypes.byref(cs), _ptr(g), _ptr(gg1), _ptr(gg2), _ptr(gw),
+                                _stream()))
+        return gg1, gg2, gw
+
+
+def version() -> str:
+    return _lib.t3_version().decode()

@@ -1,0 +1,217 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerance: relative Frobenius error over (b1, b2) per (mu, n) of 1e-6 for
+the FP32 path (split-precision contractions: 1e-5).  Bin membership and
+pair counts are exact and compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+from paper_2309_08601_amd.synth import (LATTICE_UNIT, WORKLOADS, Catalog, centre_sample,
+                                        make_catalogs, random_catalog)
+from _util import FP32_TOL, SPLIT_TOL, box_for, multipole_errors, rel_fro, rel_max
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def t3():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08601_amd import t3 as mod
+    return mod
+
+
+def _oracle():
+    import oracle
+    from oracle import multipole as mp
+    return oracle, mp
+
+
+def _pack(o, n_max):
+    from oracle import multipole as mp
+    return mp.pack_nonneg(o["ups"], o["N"], n_max)
+
+
+def _check(gpu, ref, tol, label=""):
+    """gpu, ref: packed multipoles [..., 5, n_max + 1, B, B]."""
+    e, e_own = multipole_errors(gpu, ref)
+    m = rel_max(gpu, ref)
+    worst = np.unravel_index(np.argmax(e), e.shape)
+    print(f"{label}: max rel-F {e.max():.3e} at {worst}, Upsilon {e[..., :4, :].max():.3e}, "
+          f"N_0 {e[..., 4, 0].max():.3e}, N_n/N_0 {e[..., 4, 1:].max() if e.shape[-1] > 1 else 0:.3e}, "
+          f"N_n own {e_own.max():.3e}, max rel-max {m.max():.3e}", flush=True)
+    assert e.max() <= tol, (label, e.max(), worst)
+    assert e_own.max() <= 50 * tol, (label, e_own.max())
+
+
+def test_harmonics_match_oracle(t3):
+    _, mp = _oracle()
+    cat = random_catalog(3000, 60.0, seed=7)
+    edges = np.geomspace(0.8, 14.0, 7)
+    nm = 10
+    lo, size = box_for(60.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size)
+    dc = t3.DeviceCatalog.from_catalog(cat)
+    idx = centre_sample(cat.n, 300, seed=1)
+    G, W, D = plan.harmonics(dc, torch.from_numpy(idx).cuda())
+    h = mp.harmonics(cat.subset(idx), cat, edges, nm)
+    G = G.cpu().numpy().astype(np.complex128)
+    W = W.cpu().numpy().astype(np.complex128)
+    D = D.cpu().numpy().astype(np.complex128)
+    scale = np.abs(h["G"]).max()
+    assert np.abs(G - h["G"]).max() < 2e-6 * scale
+    Wo = h["W"][:, :, nm:]
+    assert np.abs(W - Wo).max() < 2e-6 * np.abs(Wo).max()
+    assert np.abs(D - h["D"]).max() < 2e-6 * np.abs(h["D"]).max()
+    # W_0 holds the weight sums exactly up to FP32 rounding; the count of
+    # in-bin neighbours is exact
+    plan_u = t3.Plan(edges, nm, box_lo=lo, box_size=size)
+    ones = Catalog(cat.x, cat.y, cat.g1, cat.g2, np.ones(cat.n, np.float32))
+    _, W1, _ = plan_u.harmonics(t3.DeviceCatalog.from_catalog(ones), torch.from_numpy(idx).cuda())
+    cnt = mp.harmonics(ones.subset(idx), ones, edges, nm)["W"][:, :, nm].real
+    assert np.array_equal(W1[:, :, 0].real.cpu().numpy().astype(np.float64), cnt)
+
+
+@pytest.mark.parametrize("nm", [0, 3, 10, 20, 30])
+def test_forward_small_orders(t3, nm):
+    _, mp = _oracle()
+    cat = random_catalog(1500, 40.0, seed=100 + nm)
+    edges = np.geomspace(1.0, 15.0, 6)
+    lo, size = box_for(40.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size)
+    ups, npairs = plan.forward(t3.DeviceCatalog.from_catalog(cat))
+    o = mp.multipoles(cat, edges, nm)
+    assert npairs == o["npairs"]
+    _check(ups.cpu().numpy(), _pack(o, nm), FP32_TOL, f"n_max={nm}")
+
+
+def test_forward_small_2k_workload(t3):
+    """The 2,000-galaxy, 1 deg^2 workload in full (10 bins 1'-30', n_max 10)."""
+    _, mp = _oracle()
+    wl = WORKLOADS["small_2k"]
+    cat = make_catalogs(wl)[0]
+    lo, size = box_for(wl.side)
+    plan = t3.Plan(wl.edges(), wl.n_max, box_lo=lo, box_size=size)
+    ups, npairs = plan.forward(t3.DeviceCatalog.from_catalog(cat))
+    o = mp.multipoles(cat, wl.edges(), wl.n_max)
+    assert npairs == o["npairs"]
+    _check(ups.cpu().numpy(), _pack(o, wl.n_max), FP32_TOL, "small_2k")
+
+
+def test_forward_field_1m_sampled_centres(t3):
+    """1M galaxies in 10 deg x 10 deg, 20 bins 0.5'-100', n_max 30: GPU on a
+    sample of centres against the full neighbour catalog."""
+    _, mp = _oracle()
+    wl = WORKLOADS["field_1m"]
+    cat = make_catalogs(wl)[0]
+    idx = centre_sample(cat.n, 600, seed=11)
+    lo, size = box_for(wl.side)
+    plan = t3.Plan(wl.edges(), wl.n_max, box_lo=lo, box_size=size)
+    dc = t3.DeviceCatalog.from_catalog(cat)
+    ups, npairs = plan.forward(dc, torch.from_numpy(idx).cuda())
+    o = mp.multipoles(cat, wl.edges(), wl.n_max, centres=idx)
+    assert npairs == o["npairs"]
+    _check(ups.cpu().numpy(), _pack(o, wl.n_max), FP32_TOL, "field_1m sample")
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+def test_split_precision(t3, prec):
+    _, mp = _oracle()
+    cat = random_catalog(4000, 60.0, seed=55)
+    edges = np.geomspace(0.7, 20.0, 9)
+    nm = 12
+    lo, size = box_for(60.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size, precision=prec)
+    ups, _ = plan.forward(t3.DeviceCatalog.from_catalog(cat))
+    o = mp.multipoles(cat, edges, nm)
+    _check(ups.cpu().numpy(), _pack(o, nm), SPLIT_TOL, prec)
+
+
+def test_normalise_and_resum(t3):
+    _, mp = _oracle()
+    cat = random_catalog(2500, 50.0, seed=8)
+    edges = np.geomspace(1.0, 16.0, 6)
+    nm = 8
+    lo, size = box_for(50.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size)
+    ups, _ = plan.forward(t3.DeviceCatalog.from_catalog(cat))
+    gn, gp = plan.normalise_resum(ups, n_phi=24)
+    o = mp.multipoles(cat, edges, nm)
+    g_all, _ = mp.normalise(o["ups"], o["N"])
+    e = rel_fro(gn.cpu().numpy(), g_all[:, nm:])
+    assert e.max() <= FP32_TOL, e.max()
+    ref_phi = mp.resum(g_all, nm, mp.phi_bin_edges(24))
+    gp = gp.cpu().numpy()
+    e = np.sqrt(np.sum(np.abs(gp - ref_phi) ** 2, axis=(1, 2, 3))) / np.sqrt(
+        np.sum(np.abs(ref_phi) ** 2, axis=(1, 2, 3)))
+    assert e.max() < FP32_TOL
+
+
+def test_tomography_small(t3):
+    _, mp = _oracle()
+    cats = [random_catalog(n, 40.0, seed=300 + z) for z, n in enumerate([700, 1200, 900])]
+    edges = np.geomspace(1.0, 12.0, 5)
+    nm = 6
+    lo, size = box_for(40.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size)
+    ups, npairs = plan.forward_tomo([t3.DeviceCatalog.from_catalog(c) for c in cats])
+    o = mp.multipoles_tomo(cats, edges, nm)
+    assert npairs == o["npairs"]
+    _check(ups.cpu().numpy(), mp.pack_nonneg(o["ups"], o["N"], nm), FP32_TOL, "tomo")
+
+
+def test_edge_cases(t3):
+    _, mp = _oracle()
+    u = int(round(1.0 / LATTICE_UNIT))
+    edges = [1.0, 3.0, 5.0]
+    lo, size = box_for(20.0)
+    # empty catalog
+    plan = t3.Plan(edges, 4, box_lo=lo, box_size=size)
+    empty = t3.DeviceCatalog(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32),
+                             np.zeros(0, np.float32), np.zeros(0, np.float32))
+    ups, npairs = plan.forward(empty)
+    assert npairs == 0 and float(ups.abs().max()) == 0.0
+    # neighbours exactly on bin edges, a coincident pair, the box corner
+    xs = np.array([2 * u, 4 * u, 2 * u, 2 * u + 3 * u, 2 * u, 0, 20 * u - 1], np.int32)
+    ys = np.array([2 * u, 2 * u, 5 * u, 6 * u, 2 * u, 0, 20 * u - 1], np.int32)
+    n = xs.size
+    rng = np.random.default_rng(0)
+    cat = Catalog(xs, ys, rng.normal(0, .3, n).astype(np.float32), rng.normal(0, .3, n).astype(np.float32),
+                  rng.uniform(.5, 1.5, n).astype(np.float32))
+    ups, npairs = plan.forward(t3.DeviceCatalog.from_catalog(cat))
+    o = mp.multipoles(cat, edges, 4)
+    assert npairs == o["npairs"]
+    ref = _pack(o, 4)
+    assert np.abs(ups.cpu().numpy() - ref).max() <= 1e-6 * max(np.abs(ref).max(), 1e-30)
+    # empty centre list (n_centres == 0 is "no centre", not "all")
+    ups, npairs = plan.forward(t3.DeviceCatalog.from_catalog(cat), torch.zeros(0, dtype=torch.int32).cuda())
+    assert npairs == 0 and float(ups.abs().max()) == 0.0
+
+
+def test_errors_are_reported(t3):
+    lo, size = box_for(10.0)
+    plan = t3.Plan([1.0, 2.0], 3, box_lo=lo, box_size=size)
+    bad = t3.DeviceCatalog(np.array([0, size + 5], np.int32), np.array([0, 0], np.int32),
+                           np.zeros(2, np.float32), np.zeros(2, np.float32), np.ones(2, np.float32))
+    with pytest.raises(t3.T3Error) as ei:
+        plan.forward(bad)
+    assert ei.value.code == t3.T3_ELATTICE
+    good = t3.DeviceCatalog(np.array([0, 5], np.int32), np.array([0, 0], np.int32),
+                            np.zeros(2, np.float32), np.zeros(2, np.float32), np.ones(2, np.float32))
+    with pytest.raises(t3.T3Error) as ei:
+        plan.forward(good, torch.tensor([0, 7], dtype=torch.int32).cuda())
+    assert ei.value.code == t3.T3_EINVAL
+
+
+def test_repeatable_bitwise(t3):
+    cat = random_catalog(3000, 50.0, seed=9)
+    edges = np.geomspace(1.0, 16.0, 6)
+    lo, size = box_for(50.0)
+    plan = t3.Plan(edges, 10, box_lo=lo, box_size=size)
+    dc = t3.DeviceCatalog.from_catalog(cat)
+    a, _ = plan.forward(dc)
+    b, _ = plan.forward(dc)
+    assert torch.equal(a, b)
