@@ -78,6 +78,13 @@ def main():
         return ups, npairs
 
     if args.profile_steps:
+        # plain copy of a known size: calibrates the HBM byte counters
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
         for i in range(args.profile_steps):
             _, npairs = step(plan)
             torch.cuda.synchronize()

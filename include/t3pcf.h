@@ -160,11 +160,24 @@ int t3_normalise_resum(t3_plan *plan, const double *ups, int32_t n_sets,
                        int32_t n_phi, double *gamma_n, double *gamma_phi,
                        void *stream);
 
-/* Adjoint of the non-tomographic forward pass (hand-written, recomputing
- * the harmonic sums).  Given dL/dUpsilon (grad_ups, DEVICE, same layout as
- * ups, holding dL/dRe and dL/dIm of each entry), accumulates dL/dg1,
- * dL/dg2, dL/dw for every galaxy of cat (DEVICE float [cat->n], overwritten).
- * Centres are all galaxies of cat. */
+/* Reverse of the normalisation Gamma_{mu,n} = Upsilon_{mu,n} / N_0 (mu < 4).
+ * ups: DEVICE [n_sets][5][n_max+1][B][B][2] forward multipoles;
+ * grad_gamma_n: DEVICE [n_sets][4][n_max+1][B][B][2] holding dL/dRe and
+ * dL/dIm of each Gamma entry; grad_ups (DEVICE, layout of ups, overwritten)
+ * receives dL/dUpsilon for mu < 4 and dL/dN_0 in the real part of the
+ * (mu = 4, n = 0) entries (0 elsewhere).  Bin pairs with N_0 = 0 pass no
+ * gradient. */
+int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets,
+                          const double *grad_gamma_n, double *grad_ups, void *stream);
+
+/* Adjoint of the non-tomographic forward pass over all galaxies of cat as
+ * centres (hand-written; the harmonic sums are recomputed, not stored).
+ * grad_ups: DEVICE, layout of the t3_forward output, holding dL/dRe and
+ * dL/dIm of every Upsilon_{mu,n} and N_n entry (n >= 0).
+ * grad_g1, grad_g2, grad_w: DEVICE float [cat->n], overwritten with dL/dg1,
+ * dL/dg2, dL/dw of every galaxy.  Neighbour contributions are summed with
+ * FP32 atomics, so results can differ between calls at rounding level.
+ * Synchronises the stream before returning. */
 int t3_backward(t3_plan *plan, const t3_catalog *cat, const double *grad_ups,
                 float *grad_g1, float *grad_g2, float *grad_w, void *stream);
 

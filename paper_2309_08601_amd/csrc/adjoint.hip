@@ -1,19 +1,528 @@
-// Adjoint of the multipole estimator (placeholder until the kernels land).
-#include "t3_internal.h"
+// Hand-written adjoint of the multipole estimator (reverse mode through
+// stage 2 and stage 1, recomputing the harmonic sums instead of storing them).
+//
+// Gradient convention for a real loss L and a complex quantity u = a + i b:
+//     grad u = dL/da + i dL/db.
+// Then a holomorphic map v = f(u) gives grad u = conj(f'(u)) grad v, and
+// v = conj(u) gives grad u = conj(grad v).
+//
+// Forward (Porth et al. 2023, eqs. Upsilon0_Derivation, Upsilon1-3,
+// 3PCF_Normalization): for each (mu, n),
+//     Upsilon(b1, b2) = sum_i alpha_i [X_i(b1) Y_i(b2) - [b1 == b2] D_i(b1)]
+// with (alpha, X, Y, D) = (-c, G_{n-3}, G_{-n-3}, D6), (-c*, G_{n-1}, G_{-n-1}, D2),
+// (-c, G*_{-n-1}, G_{-n-3}, DA), (-c, G_{n-3}, G*_{n-1}, DA), (w, W_n, W_n*, DW).
+// Reverse, per centre i (given Ub = grad Upsilon):
+//     grad X(b1)  = conj(alpha) sum_b2 Ub(b1, b2) conj(Y(b2))
+//     grad Y(b2)  = conj(alpha) sum_b1 Ub(b1, b2) conj(X(b1))
+//     grad alpha  = sum_b1 conj(X(b1)) sum_b2 Ub conj(Y(b2)) - sum_b conj(D(b)) Ub(b, b)
+//     grad D(b)   = -conj(alpha) Ub(b, b)
+// accumulated over (mu, n) into Gb_m(i, b), Wb_m(i, b) and the j = k sums.
+// Then every neighbour j of i in bin b (z = e^{i phi_ij}, p_m = z^m):
+//     G_m  = sum_j c_j p_m       ->  grad c_j += sum_m conj(p_m) Gb_m
+//     W_m  = sum_j w_j p_m       ->  grad w_j += sum_m Re(conj(p_m) Wb_m)
+//     D6   = sum_j c_j^2 conj(p_6)  ->  grad c_j += 2 conj(c_j) p_6 D6b
+//     D2   = sum_j c_j^2 conj(p_2)  ->  grad c_j += 2 conj(c_j) p_2 D2b
+//     DA   = sum_j |c_j|^2 conj(p_2) -> grad c_j += 2 c_j Re(DAb p_2)
+//     DW   = sum_j w_j^2            ->  grad w_j += 2 w_j Re(DWb)
+// The +-m orders share p_m: conj(p) a + p b = Re p (a + b) + Im p i (b - a),
+// so each lane needs 4 FMAs per order pair with per-(centre, bin)
+// coefficients s_m = Gb_m + Gb_{-m}, d_m = i (Gb_{-m} - Gb_m) that are uniform
+// across the wavefront (read from LDS).  The centre factors give
+//     grad c_i += -grad alpha_0 - conj(grad alpha_1) - grad alpha_2 - grad alpha_3,
+//     grad w_i += Re grad alpha_4,
+// and finally c = w gamma: grad gamma = w grad c, grad w += Re(conj(gamma) grad c).
+//
+// The transpose scan walks the same annuli as the forward scan (sweep.h),
+// every lane one neighbour, and adds its three gradient terms with
+// hardware FP32 atomics into per-galaxy buffers (summation order therefore
+// varies between runs at the level of FP32 rounding).
+#include "sweep.h"
 
 namespace t3 {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kAnchor = 8;
+
+// Coefficient block of one (centre, bin) for a compiled order capacity C:
+//   [0, 4M)       m = 1..M (M = C + 3): s_m re, s_m im, d_m re, d_m im
+//   [4M, 4M+2)    Gb_0
+//   next 2(C+1)   Wb_m, m = 0..C
+//   next 7        D6b (2), D2b (2), DAb (2), DWb (1)
+__host__ __device__ constexpr int coef_size(int C) { return 4 * (C + 3) + 2 + 2 * (C + 1) + 7; }
+
+struct CoefArgs {
+    const float *planes;   // stage-1 chunk planes
+    const float4 *ccw;     // centre factors (chunk-relative)
+    const double *gups;    // grad Upsilon [5][n_max+1][B][B][2]
+    int n_c, K, B, n_max, cap, jk;
+    float *coef;           // [n_c][B][coef_size(cap)]
+    float2 *cen_gc;        // [n_c] centre part of grad c (chunk-relative)
+    float *cen_gw;         // [n_c] centre part of grad w
+};
+
+// One wavefront per centre.
+__global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
+{
+    extern __shared__ double2 sm[];
+    const int B = a.B, nm = a.n_max;
+    const int n_g = 2 * nm + 3;
+    double2 *Gb = sm;                     // [B][n_g]   index m + nm + 3
+    double2 *Wb = Gb + B * n_g;           // [B][nm+1]
+    double2 *Db = Wb + B * (nm + 1);      // [B][4]
+    double2 *Xs = Db + B * 4;             // [32]
+    double2 *Ys = Xs + 32;                // [32]
+    const int lane = threadIdx.x;
+    const int i = blockIdx.x;
+    if (i >= a.n_c) return;
+    const int K = a.K;
+    for (int t = lane; t < B * (n_g + nm + 1 + 4); t += 64) sm[t] = make_double2(0.0, 0.0);
+
+    const float4 f = a.ccw[i];
+    const double cr = f.x, ci = f.y, w = f.z;
+    // alpha per mu
+    const double al_r[5] = {-cr, -cr, -cr, -cr, w};
+    const double al_i[5] = {-ci, ci, -ci, -ci, 0.0};
+    double ga_r[5] = {0, 0, 0, 0, 0}, ga_i[5] = {0, 0, 0, 0, 0};  // grad alpha (lanes 0..B-1 partials)
+    __syncthreads();
+
+    const int b = lane & 31;
+    const bool side_y = lane >= 32;   // lanes 32.. compute grad Y
+    const size_t pstr = (size_t)(nm + 1) * B * B;
+    for (int mu = 0; mu < 5; ++mu) {
+        for (int n = 0; n <= nm; ++n) {
+            int xm, ym, xs = 0, ys = 0;  // orders; xs/ys = 1 when the operand is conjugated
+            switch (mu) {
+                case 0: xm = n - 3; ym = -n - 3; break;
+                case 1: xm = n - 1; ym = -n - 1; break;
+                case 2: xm = -n - 1; ym = -n - 3; xs = 1; break;
+                case 3: xm = n - 3; ym = n - 1; ys = 1; break;
+                default: xm = n; ym = n; ys = 1; break;
+            }
+            const int pxr = mu < 4 ? 2 * (xm + nm + 3) : 2 * n_g + 2 * n;
+            const int pyr = mu < 4 ? 2 * (ym + nm + 3) : 2 * n_g + 2 * n;
+            if (b < B) {
+                const int pl = side_y ? pyr : pxr;
+                const int cj = side_y ? ys : xs;
+                const double re = a.planes[chunk_offset(pl, i, b, K, B)];
+                double im = a.planes[chunk_offset(pl + 1, i, b, K, B)];
+                if (cj) im = -im;
+                (side_y ? Ys : Xs)[b] = make_double2(re, im);
+            }
+            __syncthreads();
+            const double *U = a.gups + 2 * ((size_t)mu * pstr + (size_t)n * B * B);
+            double2 gop = make_double2(0.0, 0.0);
+            if (b < B) {
+                // side X: u(b1) = sum_b2 Ub(b1, b2) conj(Y(b2)); side Y: v(b2) = sum_b1 Ub(b1, b2) conj(X(b1))
+                double ur = 0.0, ui = 0.0;
+                for (int k = 0; k < B; ++k) {
+                    const double2 o = side_y ? Xs[k] : Ys[k];
+                    const size_t idx = side_y ? ((size_t)k * B + b) : ((size_t)b * B + k);
+                    const double gr = U[2 * idx], gi = U[2 * idx + 1];
+                    ur += gr * o.x + gi * o.y;   // Ub * conj(o)
+                    ui += gi * o.x - gr * o.y;
+                }
+                // grad operand = conj(alpha) * u
+                const double ar = al_r[mu], ai = al_i[mu];
+                double gr = ar * ur + ai * ui, gi = ar * ui - ai * ur;
+                if (!side_y) {
+                    // grad alpha += conj(X(b1)) u(b1)
+                    const double2 x = Xs[b];
+                    ga_r[mu] += x.x * ur + x.y * ui;
+                    ga_i[mu] += x.x * ui - x.y * ur;
+                }
+                const int cj = side_y ? ys : xs;
+                if (cj) gi = -gi;  // operand was conj(G): grad G = conj(grad operand)
+                gop = make_double2(gr, gi);
+            }
+            // the two sides may update the same (b, order): one side at a time
+            double2 *tx = mu < 4 ? &Gb[b * n_g + (xm + nm + 3)] : &Wb[b * (nm + 1) + n];
+            double2 *ty = mu < 4 ? &Gb[b * n_g + (ym + nm + 3)] : &Wb[b * (nm + 1) + n];
+            if (b < B && !side_y) *tx = make_double2(tx->x + gop.x, tx->y + gop.y);
+            __syncthreads();
+            if (b < B && side_y) *ty = make_double2(ty->x + gop.x, ty->y + gop.y);
+            __syncthreads();
+        }
+    }
+    // j = k terms
+    if (a.jk && lane < B) {
+        const int bb = lane;
+        const int pD = 2 * n_g + 2 * (nm + 1);
+        double dsum_r[5], dsum_i[5];
+        for (int mu = 0; mu < 5; ++mu) {
+            double sr = 0.0, si = 0.0;
+            const double *U = a.gups + 2 * ((size_t)mu * pstr);
+            for (int n = 0; n <= nm; ++n) {
+                const size_t idx = (size_t)n * B * B + (size_t)bb * B + bb;
+                sr += U[2 * idx];
+                si += U[2 * idx + 1];
+            }
+            dsum_r[mu] = sr;
+            dsum_i[mu] = si;
+        }
+        // D values of this centre
+        const double d6r = a.planes[chunk_offset(pD + 0, i, bb, K, B)];
+        const double d6i = a.planes[chunk_offset(pD + 1, i, bb, K, B)];
+        const double d2r = a.planes[chunk_offset(pD + 2, i, bb, K, B)];
+        const double d2i = a.planes[chunk_offset(pD + 3, i, bb, K, B)];
+        const double dar = a.planes[chunk_offset(pD + 4, i, bb, K, B)];
+        const double dai = a.planes[chunk_offset(pD + 5, i, bb, K, B)];
+        const double dw = a.planes[chunk_offset(pD + 6, i, bb, K, B)];
+        // grad D = -conj(alpha) sum_n Ub(b, b); grad alpha -= conj(D) sum_n Ub(b, b)
+        auto gD = [&](int mu, double &gr, double &gi) {
+            const double ar = al_r[mu], ai = al_i[mu], ur = dsum_r[mu], ui = dsum_i[mu];
+            gr = -(ar * ur + ai * ui);
+            gi = -(ar * ui - ai * ur);
+        };
+        double r0, i0, r1, i1, r2, i2, r3, i3, r4, i4;
+        gD(0, r0, i0);
+        gD(1, r1, i1);
+        gD(2, r2, i2);
+        gD(3, r3, i3);
+        gD(4, r4, i4);
+        Db[bb * 4 + 0] = make_double2(r0, i0);
+        Db[bb * 4 + 1] = make_double2(r1, i1);
+        Db[bb * 4 + 2] = make_double2(r2 + r3, i2 + i3);
+        Db[bb * 4 + 3] = make_double2(r4, i4);
+        auto sub = [&](int mu, double dr, double di) {
+            ga_r[mu] -= dr * dsum_r[mu] + di * dsum_i[mu];
+            ga_i[mu] -= dr * dsum_i[mu] - di * dsum_r[mu];
+        };
+        sub(0, d6r, d6i);
+        sub(1, d2r, d2i);
+        sub(2, dar, dai);
+        sub(3, dar, dai);
+        sub(4, dw, 0.0);
+    }
+    __syncthreads();
+    // centre gradient: reduce grad alpha over lanes 0..B-1 (other lanes hold 0)
+    double gcr = 0.0, gci = 0.0, gw = 0.0;
+    {
+        double vr = -ga_r[0] - ga_r[1] - ga_r[2] - ga_r[3];
+        double vi = -ga_i[0] + ga_i[1] - ga_i[2] - ga_i[3];
+        double vw = ga_r[4];
+        if (lane >= 32) vr = vi = vw = 0.0;
+        for (int d = 32; d > 0; d >>= 1) {
+            vr += __shfl_xor(vr, d, 64);
+            vi += __shfl_xor(vi, d, 64);
+            vw += __shfl_xor(vw, d, 64);
+        }
+        gcr = vr;
+        gci = vi;
+        gw = vw;
+    }
+    if (lane == 0) {
+        a.cen_gc[i] = make_float2((float)gcr, (float)gci);
+        a.cen_gw[i] = (float)gw;
+    }
+    // coefficient blocks
+    const int C = a.cap, M = C + 3, CS = coef_size(C);
+    for (int t = lane; t < B * CS; t += 64) {
+        const int bb = t / CS, k = t % CS;
+        float v = 0.0f;
+        if (k < 4 * M) {
+            const int m = k / 4 + 1, q = k % 4;
+            double2 gp = make_double2(0.0, 0.0), gm = make_double2(0.0, 0.0);
+            if (m <= nm - 1) gp = Gb[bb * n_g + (m + nm + 3)];
+            if (m <= nm + 3) gm = Gb[bb * n_g + (-m + nm + 3)];
+            // s = gp + gm ; d = i (gm - gp) = (-(gm.y - gp.y), gm.x - gp.x)
+            const double val = q == 0 ? gp.x + gm.x : q == 1 ? gp.y + gm.y
+                             : q == 2 ? -(gm.y - gp.y) : (gm.x - gp.x);
+            v = (float)val;
+        } else if (k < 4 * M + 2) {
+            if (nm >= 1) {
+                const double2 g0 = Gb[bb * n_g + (nm + 3)];
+                v = (float)(k == 4 * M ? g0.x : g0.y);
+            }
+        } else if (k < 4 * M + 2 + 2 * (C + 1)) {
+            const int kk = k - 4 * M - 2, m = kk / 2;
+            if (m <= nm) {
+                const double2 wv = Wb[bb * (nm + 1) + m];
+                v = (float)(kk % 2 == 0 ? wv.x : wv.y);
+            }
+        } else {
+            const int kk = k - 4 * M - 2 - 2 * (C + 1);  // 0..6
+            const double2 d = Db[bb * 4 + (kk < 6 ? kk / 2 : 3)];
+            v = (float)(kk == 6 ? d.x : (kk % 2 == 0 ? d.x : d.y));
+        }
+        a.coef[((size_t)i * B + bb) * CS + k] = v;
+    }
+}
+
+struct ScatterArgs {
+    SweepArgs sw;
+    const int2 *cpos;     // centre positions (chunk-relative)
+    const float *coef;    // [n_c][B][coef_size(cap)]
+    int n_c, B, jk;
+    float *nb_gc;         // [2 n] grad c of neighbours (sorted index)
+    float *nb_gw;         // [n]
+    double e2[65];
+};
+
+template <int C>
+__global__ __launch_bounds__(64 * kWaves) void k_adj_scatter(ScatterArgs a)
+{
+    constexpr int M = C + 3;
+    constexpr int CS = coef_size(C);
+    __shared__ int4 q_xyc[kWaves][kRing];
+    __shared__ int2 q_wi[kWaves][kRing];
+    __shared__ int2 spans[kWaves][2 * kRowsPerBlock + 1];
+    constexpr int CSP = (CS + 3) & ~3;  // 16-byte aligned rows
+    __shared__ __align__(16) float cf[kWaves][CSP];
+
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int nwg = gridDim.x;
+    const int per = nwg >> 3;
+    const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int ci = wg * kWaves + wv;
+    if (ci >= a.n_c) return;
+    const int2 cp = a.cpos[ci];
+    const SweepLDS lds{q_xyc[wv], q_wi[wv], spans[wv]};
+    float *c = cf[wv];
+
+    for (int b = 0; b < a.B; ++b) {
+        wave_sync_lds();
+        for (int k = lane; k < CS; k += 64) c[k] = a.coef[((size_t)ci * a.B + b) * CS + k];
+        wave_sync_lds();
+        sweep_annulus(a.sw, cp, a.e2[b], a.e2[b + 1], lane, lds,
+                      [&](const int4 &e, float wt, int gi, bool act) {
+            const float cr = __int_as_float(e.z), cim = __int_as_float(e.w);
+            const double xd = (double)e.x, yd = (double)e.y;
+            const double r2 = fma(xd, xd, yd * yd);
+            double s = (double)__builtin_amdgcn_rsqf((float)r2);
+            s = s * fma(-0.5 * r2 * s, s, 1.5);
+            const double zr = xd * s, zi = yd * s;
+            const float fzr = (float)zr, fzi = (float)zi;
+            const double z2r = fma(zr, zr, -zi * zi), z2i = 2.0 * zr * zi;
+            const double z4r = fma(z2r, z2r, -z2i * z2i), z4i = 2.0 * z2r * z2i;
+            const double z8r = fma(z4r, z4r, -z4i * z4i), z8i = 2.0 * z4r * z4i;
+            double ar = 1.0, ai = 0.0;
+            float pr = 1.0f, pi = 0.0f;
+            float gr = c[4 * M], gim = c[4 * M + 1];  // Gb_0
+            float gw = c[4 * M + 2];                   // Re Wb_0
+#pragma unroll
+            for (int m = 1; m <= M; ++m) {
+                if (m % kAnchor == 0) {
+                    const double tr = fma(ar, z8r, -ai * z8i);
+                    ai = fma(ar, z8i, ai * z8r);
+                    ar = tr;
+                    pr = (float)ar;
+                    pi = (float)ai;
+                } else {
+                    const float tr = fmaf(pr, fzr, -pi * fzi);
+                    pi = fmaf(pr, fzi, pi * fzr);
+                    pr = tr;
+                }
+                const float4 sd = *reinterpret_cast<const float4 *>(c + 4 * (m - 1));
+                gr = fmaf(pr, sd.x, fmaf(pi, sd.z, gr));
+                gim = fmaf(pr, sd.y, fmaf(pi, sd.w, gim));
+                if (m <= C) {
+                    const float2 wb = *reinterpret_cast<const float2 *>(c + 4 * M + 2 + 2 * m);
+                    gw = fmaf(pr, wb.x, fmaf(pi, wb.y, gw));
+                }
+            }
+            if (a.jk) {
+                const int o = 4 * M + 2 + 2 * (C + 1);
+                const float p2r = (float)z2r, p2i = (float)z2i;
+                const double z6r = fma(z4r, z2r, -z4i * z2i), z6i = fma(z4r, z2i, z4i * z2r);
+                const float p6r = (float)z6r, p6i = (float)z6i;
+                // 2 conj(c) p6 D6b + 2 conj(c) p2 D2b
+                const float q6r = fmaf(p6r, c[o + 0], -p6i * c[o + 1]);
+                const float q6i = fmaf(p6r, c[o + 1], p6i * c[o + 0]);
+                const float q2r = fmaf(p2r, c[o + 2], -p2i * c[o + 3]);
+                const float q2i = fmaf(p2r, c[o + 3], p2i * c[o + 2]);
+                const float qr = q6r + q2r, qi = q6i + q2i;
+                gr = fmaf(2.0f * cr, qr, fmaf(2.0f * cim, qi, gr));
+                gim = fmaf(2.0f * cr, qi, fmaf(-2.0f * cim, qr, gim));
+                // 2 c Re(DAb p2)
+                const float ra = fmaf(c[o + 4], p2r, -c[o + 5] * p2i);
+                gr = fmaf(2.0f * cr, ra, gr);
+                gim = fmaf(2.0f * cim, ra, gim);
+                // 2 w Re(DWb)
+                gw = fmaf(2.0f * wt, c[o + 6], gw);
+            }
+            if (act) {
+                unsafeAtomicAdd(a.nb_gc + 2 * (size_t)gi, gr);
+                unsafeAtomicAdd(a.nb_gc + 2 * (size_t)gi + 1, gim);
+                unsafeAtomicAdd(a.nb_gw + gi, gw);
+            }
+        });
+    }
+}
+
+__global__ void k_adj_combine(const int *perm, int64_t n, const float *nb_gc, const float *nb_gw,
+                              const float2 *cen_gc, const float *cen_gw, const float *g1, const float *g2,
+                              const float *w, float *out_g1, float *out_g2, float *out_w)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int i = perm[s];
+    const float gcr = nb_gc[2 * s] + cen_gc[s].x;
+    const float gci = nb_gc[2 * s + 1] + cen_gc[s].y;
+    const float gwd = nb_gw[s] + cen_gw[s];
+    const float wi = w[i];
+    out_g1[i] = wi * gcr;
+    out_g2[i] = wi * gci;
+    out_w[i] = gwd + g1[i] * gcr + g2[i] * gci;
+}
+
+__global__ void k_zero_f(float *p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+// grad Upsilon from grad Gamma (Gamma_{mu,n} = Upsilon_{mu,n} / N_0, mu < 4).
+__global__ void k_norm_bwd(const double *ups, const double *ggam, int n_sets, int n_max, int B,
+                           double *gups)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t bb = (int64_t)B * B;
+    const int64_t per_mu = (int64_t)(n_max + 1) * bb;
+    if (t >= (int64_t)n_sets * bb) return;
+    const int64_t set = t / bb, e = t % bb;
+    const double *u = ups + 2 * (set * 5 * per_mu);
+    const double *g = ggam + 2 * (set * 4 * per_mu);
+    double *o = gups + 2 * (set * 5 * per_mu);
+    const double n0 = u[2 * (4 * per_mu + e)];
+    double dn0 = 0.0;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int n = 0; n <= n_max; ++n) {
+            const int64_t k = mu * per_mu + n * bb + e;
+            const double gr = g[2 * k], gi = g[2 * k + 1];
+            if (n0 != 0.0) {
+                const double ur = u[2 * k], ui = u[2 * k + 1];
+                o[2 * k] = gr / n0;
+                o[2 * k + 1] = gi / n0;
+                dn0 -= (gr * ur + gi * ui) / (n0 * n0);
+            } else {
+                o[2 * k] = 0.0;
+                o[2 * k + 1] = 0.0;
+            }
+        }
+    for (int n = 0; n <= n_max; ++n) {
+        const int64_t k = 4 * per_mu + n * bb + e;
+        o[2 * k] = n == 0 ? dn0 : 0.0;
+        o[2 * k + 1] = 0.0;
+    }
+}
+
+struct ScatterVariant {
+    int cap;
+    void (*kernel)(ScatterArgs);
+};
+
+const ScatterVariant kScatter[] = {
+    {4, k_adj_scatter<4>},   {8, k_adj_scatter<8>},   {10, k_adj_scatter<10>}, {12, k_adj_scatter<12>},
+    {16, k_adj_scatter<16>}, {20, k_adj_scatter<20>}, {24, k_adj_scatter<24>}, {30, k_adj_scatter<30>},
+    {32, k_adj_scatter<32>}, {40, k_adj_scatter<40>}, {48, k_adj_scatter<48>}, {64, k_adj_scatter<64>},
+};
+
+}  // namespace
+
+int normalise_backward(t3_plan *plan, const double *ups, const double *ggam, int n_sets, double *gups,
+                       hipStream_t s)
+{
+    const int64_t tot = (int64_t)n_sets * plan->B * plan->B;
+    hipLaunchKernelGGL(k_norm_bwd, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, ups, ggam,
+                       n_sets, plan->n_max, plan->B, gups);
+    T3_HIP_CHECK(hipGetLastError());
+    return T3_OK;
+}
 
 int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float *gg1, float *gg2,
              float *gw, hipStream_t s)
 {
-    (void)plan;
-    (void)cat;
-    (void)grad_ups;
-    (void)gg1;
-    (void)gg2;
-    (void)gw;
-    (void)s;
-    return fail(T3_ERANGE, "t3_backward: not available in this build");
+    T3_TRY(timing_begin_call(plan));
+    T3_TRY(plan->flag.reserve(sizeof(int) * 4));
+    T3_TRY(plan->counter.reserve(sizeof(unsigned long long) * 4));
+    T3_HIP_CHECK(hipMemsetAsync(plan->flag.ptr, 0, sizeof(int) * 4, s));
+    SortedCatalog &sc = plan->cats[0];
+    T3_TRY(build_cells(plan, sc, cat, choose_grid(plan, cat.n), s));
+    T3_TRY(gather_sorted_centres(plan, sc, plan->centres, s));
+    T3_TRY(check_flag(plan, s, "t3_backward"));
+    const int64_t n = cat.n;
+    if (n == 0) return T3_OK;
+
+    const ScatterVariant *sv = nullptr;
+    for (const auto &v : kScatter)
+        if (v.cap >= plan->n_max) {
+            sv = &v;
+            break;
+        }
+    if (!sv) return fail(T3_ERANGE, "t3_backward: n_max above the compiled variants");
+    ChunkLayout L;
+    L.n_max = plan->n_max;
+    L.B = plan->B;
+    L.K = choose_chunk(plan, L);
+    const int CS = coef_size(sv->cap);
+    // scratch: nb_gc [2n], nb_gw [n], cen_gc [2n], cen_gw [n]
+    T3_TRY(plan->misc.reserve(sizeof(float) * 6 * (size_t)n));
+    T3_TRY(plan->misc2.reserve(sizeof(float) * (size_t)L.K * L.B * CS));
+    T3_TRY(plan->chunk.reserve(sizeof(float) * L.floats()));
+    float *nb_gc = plan->misc.as<float>();
+    float *nb_gw = nb_gc + 2 * n;
+    float2 *cen_gc = reinterpret_cast<float2 *>(nb_gw + n);
+    float *cen_gw = reinterpret_cast<float *>(cen_gc + n);
+    hipLaunchKernelGGL(k_zero_f, dim3((unsigned)((6 * n + 255) / 256)), dim3(256), 0, s, nb_gc,
+                       (size_t)(6 * n));
+    T3_HIP_CHECK(hipGetLastError());
+    const bool jk = !(plan->flags & T3_FLAG_KEEP_JK);
+    const int B = plan->B, nm = plan->n_max;
+    const size_t lds = sizeof(double2) * ((size_t)B * ((2 * nm + 3) + (nm + 1) + 4) + 64);
+    if (lds > 64 * 1024)
+        T3_HIP_CHECK(hipFuncSetAttribute((const void *)k_adj_coef,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    for (int64_t c0 = 0; c0 < n; c0 += L.K) {
+        const int nc = (int)((n - c0) < L.K ? (n - c0) : L.K);
+        T3_TRY(timing_mark(plan, 1, true, s));
+        T3_TRY(scan_chunk(plan, sc, plan->centres, c0, nc, L, plan->chunk.as<float>(), nullptr, s));
+        T3_TRY(timing_mark(plan, 1, false, s));
+        T3_TRY(timing_mark(plan, 2, true, s));
+        CoefArgs ca{};
+        ca.planes = plan->chunk.as<float>();
+        ca.ccw = plan->centres.cw.as<float4>() + c0;
+        ca.gups = grad_ups;
+        ca.n_c = nc;
+        ca.K = L.K;
+        ca.B = B;
+        ca.n_max = nm;
+        ca.cap = sv->cap;
+        ca.jk = jk ? 1 : 0;
+        ca.coef = plan->misc2.as<float>();
+        ca.cen_gc = cen_gc + c0;
+        ca.cen_gw = cen_gw + c0;
+        hipLaunchKernelGGL(k_adj_coef, dim3(nc), dim3(64), lds, s, ca);
+        T3_HIP_CHECK(hipGetLastError());
+        T3_TRY(timing_mark(plan, 2, false, s));
+        T3_TRY(timing_mark(plan, 3, true, s));
+        ScatterArgs sa{};
+        sa.sw.npos = sc.pos.as<int2>();
+        sa.sw.ncw = sc.cw.as<float4>();
+        sa.sw.cell_start = sc.cell_start.as<int>();
+        sa.sw.g = sc.grid;
+        sa.cpos = plan->centres.pos.as<int2>() + c0;
+        sa.coef = plan->misc2.as<float>();
+        sa.n_c = nc;
+        sa.B = B;
+        sa.jk = jk ? 1 : 0;
+        sa.nb_gc = nb_gc;
+        sa.nb_gw = nb_gw;
+        for (int b = 0; b <= B; ++b) sa.e2[b] = plan->e2[b];
+        int nwg = (nc + kWaves - 1) / kWaves;
+        nwg = (nwg + 7) & ~7;
+        hipLaunchKernelGGL(sv->kernel, dim3((unsigned)nwg), dim3(64 * kWaves), 0, s, sa);
+        T3_HIP_CHECK(hipGetLastError());
+        T3_TRY(timing_mark(plan, 3, false, s));
+    }
+    hipLaunchKernelGGL(k_adj_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       (const int *)sc.perm.as<int>(), n, (const float *)nb_gc, (const float *)nb_gw,
+                       (const float2 *)cen_gc, (const float *)cen_gw, cat.g1, cat.g2, cat.w, gg1, gg2, gw);
+    T3_HIP_CHECK(hipGetLastError());
+    T3_HIP_CHECK(hipStreamSynchronize(s));
+    T3_TRY(timing_end_call(plan));
+    return T3_OK;
 }
 
 }  // namespace t3

@@ -399,6 +399,15 @@ int t3_normalise_resum(t3_plan *plan, const double *ups, int32_t n_sets, int32_t
     return normalise_resum(plan, ups, n_sets, n_z, n_phi, gamma_n, gamma_phi, (hipStream_t)stream);
 }
 
+int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets, const double *grad_gamma_n,
+                          double *grad_ups, void *stream)
+{
+    if (!plan || !ups || !grad_gamma_n || !grad_ups)
+        return fail(T3_EINVAL, "t3_normalise_backward: null argument");
+    if (n_sets < 1) return fail(T3_EINVAL, "t3_normalise_backward: n_sets must be >= 1");
+    return normalise_backward(plan, ups, grad_gamma_n, n_sets, grad_ups, (hipStream_t)stream);
+}
+
 int t3_stage_times(const t3_plan *plan, double *ms, int64_t *launches)
 {
     if (!plan || !ms) return fail(T3_EINVAL, "t3_stage_times: null argument");

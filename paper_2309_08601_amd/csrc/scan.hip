@@ -5,15 +5,14 @@
 // plus the single-neighbour sums that remove j = k from the products.
 //
 // Mapping (one wavefront per centre, one radial bin at a time):
-//  * the annulus [e_b, e_{b+1}) around the centre is covered by, per cell
-//    row, at most two runs of cells; each run is one contiguous range of the
-//    cell-sorted catalog, computed per centre in FP64;
-//  * 64 lanes test 64 consecutive candidates, in-bin ones are compacted with
-//    a ballot into a 128-entry LDS ring; every time 64 are pending each lane
-//    takes one neighbour through the harmonic recurrence (lane = neighbour);
-//  * per-lane FP32 accumulators hold one bin of one centre; at the end of the
-//    bin a 6-step reduce-scatter leaves each lane a few finished sums, which
-//    it stores into the chunk planes (layout in t3_internal.h).
+//  * the neighbours of the annulus [e_b, e_{b+1}) come from the shared
+//    annulus sweep (sweep.h): row runs of the cell list, coalesced candidate
+//    tests, ballot compaction into an LDS ring, 64 in-bin neighbours per
+//    batch, each lane taking one through the harmonic recurrence;
+//  * per-lane FP32 accumulators hold one bin of one centre; every 32 batches
+//    and at the end of the bin a 6-step reduce-scatter leaves each lane a few
+//    wave totals, which are added to per-lane FP64 partials; at the end of
+//    the bin those are stored into the chunk planes (layout in t3_internal.h).
 //
 // Arithmetic per neighbour: dx, dy are exact lattice integers, r^2 is exact
 // in FP64 and is compared with the same FP64 squared edges as everywhere
@@ -24,22 +23,18 @@
 //     S1 += Re c Re p,  S2 += Im c Im p,  S3 += Re c Im p,  S4 += Im c Re p
 //     G_m = (S1 - S2, S3 + S4),   G_{-m} = (S1 + S2, S4 - S3)
 // which costs 4 FMAs for two orders.
-#include "t3_internal.h"
+#include "sweep.h"
 
 namespace t3 {
 namespace {
 
 constexpr int kWaves = 4;       // wavefronts (centres) per workgroup
-constexpr int kRing = 128;      // LDS ring entries per wavefront
 constexpr int kAnchor = 8;      // FP64 anchor stride of the power recurrence
 constexpr int kMaxBins = 64;
 constexpr int kFlush = 32;      // batches of 64 neighbours per FP32 run before FP64 promotion
 
 struct ScanArgs {
-    const int2 *npos;       // cell-sorted neighbour positions
-    const float4 *ncw;      // (w g1, w g2, w, 0) in the same order
-    const int *cell_start;  // [ncells + 1]
-    CellGrid g;
+    SweepArgs sw;           // cell-sorted neighbour catalog
     const int2 *cpos;       // centre positions (chunk-relative)
     const float4 *ccw;      // centre factors (unused here, kept for symmetry)
     int n_c;                // centres in the chunk
@@ -51,17 +46,6 @@ struct ScanArgs {
     unsigned long long *npairs;
     double e2[kMaxBins + 1];
 };
-
-__device__ __forceinline__ long long floor_div(long long a, long long b)
-{
-    long long q = a / b;
-    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
-}
-
-__device__ __forceinline__ long long ceil_div(long long a, long long b)
-{
-    return -floor_div(-a, b);
-}
 
 // Per-pass register footprint.
 template <int GA, int GB, int WA, int WB, bool EXTRA>
@@ -198,9 +182,9 @@ template <int GA, int GB, int WA, int WB, bool EXTRA>
 __global__ __launch_bounds__(64 * kWaves) void k_scan(ScanArgs a)
 {
     using S = PassShape<GA, GB, WA, WB, EXTRA>;
-    __shared__ int4 q_xyc[kWaves][kRing];  // dx, dy, bits(Re c), bits(Im c)
-    __shared__ float q_w[kWaves][kRing];
-    __shared__ int2 spans[kWaves][128];
+    __shared__ int4 q_xyc[kWaves][kRing];
+    __shared__ int2 q_wi[kWaves][kRing];
+    __shared__ int2 spans[kWaves][2 * kRowsPerBlock + 1];
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -212,12 +196,10 @@ __global__ __launch_bounds__(64 * kWaves) void k_scan(ScanArgs a)
     if (ci >= a.n_c) return;  // whole wavefront leaves together
 
     const int2 cp = a.cpos[ci];
-    const CellGrid g = a.g;
-    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    const SweepLDS lds{q_xyc[wv], q_wi[wv], spans[wv]};
     unsigned long long pairs = 0;
 
     for (int b = 0; b < a.n_bins; ++b) {
-        const double e2lo = a.e2[b], e2hi = a.e2[b + 1];
         float acc[S::V];
 #pragma unroll
         for (int k = 0; k < S::V; ++k) acc[k] = 0.0f;
@@ -226,109 +208,16 @@ __global__ __launch_bounds__(64 * kWaves) void k_scan(ScanArgs a)
         for (int k = 0; k < S::P; ++k) accd[k] = 0.0;
         int batches = 0;  // wave-uniform: batches since the last FP64 promotion
 
-        const long long R = (long long)sqrt(e2hi) + 1;
-        long long row_lo = floor_div((long long)cp.y - R - g.oy, g.cell);
-        long long row_hi = floor_div((long long)cp.y + R - g.oy, g.cell);
-        row_lo = row_lo < 0 ? 0 : row_lo;
-        row_hi = row_hi > g.ncy - 1 ? g.ncy - 1 : row_hi;
-
-        int head = 0, tail = 0;  // wave-uniform ring pointers
-        for (long long r0 = row_lo; r0 <= row_hi; r0 += 64) {
-            // ---- lanes build the (up to) two galaxy ranges of their cell row
-            int2 sa = make_int2(0, 0), sb = make_int2(0, 0);
-            const long long r = r0 + lane;
-            if (r <= row_hi) {
-                const long long y0 = (long long)g.oy + r * g.cell;
-                const long long y1 = y0 + g.cell - 1;
-                const long long py = cp.y, px = cp.x;
-                const long long dyn = py < y0 ? y0 - py : (py > y1 ? py - y1 : 0);
-                const long long d0 = y0 - py < 0 ? py - y0 : y0 - py;
-                const long long d1 = y1 - py < 0 ? py - y1 : y1 - py;
-                const long long dyx = d0 > d1 ? d0 : d1;
-                const double dmin2 = (double)dyn * (double)dyn;
-                const double dmax2 = (double)dyx * (double)dyx;
-                if (dmin2 < e2hi) {
-                    const long long xr = (long long)sqrt(e2hi - dmin2) + 1;
-                    long long c_lo = floor_div(px - xr - g.ox, g.cell);
-                    long long c_hi = floor_div(px + xr - g.ox, g.cell);
-                    c_lo = c_lo < 0 ? 0 : c_lo;
-                    c_hi = c_hi > g.ncx - 1 ? g.ncx - 1 : c_hi;
-                    long long a0 = c_lo, a1 = c_hi, b0 = 1, b1 = 0;
-                    if (e2lo > dmax2) {
-                        const long long xin = (long long)sqrt(e2lo - dmax2) - 1;
-                        if (xin >= 0) {
-                            const long long in_lo = ceil_div(px - xin - g.ox, g.cell);
-                            const long long in_hi = floor_div(px + xin - g.ox + 1, g.cell) - 1;
-                            if (in_lo <= in_hi) {
-                                a1 = c_hi < in_lo - 1 ? c_hi : in_lo - 1;
-                                b0 = c_lo > in_hi + 1 ? c_lo : in_hi + 1;
-                                b1 = c_hi;
-                            }
-                        }
-                    }
-                    const int *cs = a.cell_start + r * g.ncx;
-                    if (a0 <= a1) sa = make_int2(cs[a0], cs[a1 + 1]);
-                    if (b0 <= b1) sb = make_int2(cs[b0], cs[b1 + 1]);
+        pairs += (unsigned long long)sweep_annulus(
+            a.sw, cp, a.e2[b], a.e2[b + 1], lane, lds,
+            [&](const int4 &e, float ew, int, bool) {
+                accumulate<GA, GB, WA, WB, EXTRA>(acc, e.x, e.y, __int_as_float(e.z),
+                                                  __int_as_float(e.w), ew);
+                if (++batches == kFlush) {
+                    flush<GA, GB, WA, WB, EXTRA>(acc, accd, lane);
+                    batches = 0;
                 }
-            }
-            spans[wv][2 * lane] = sa;
-            spans[wv][2 * lane + 1] = sb;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int nsp = 2 * (int)((row_hi - r0 + 1) < 64 ? (row_hi - r0 + 1) : 64);
-            for (int t = 0; t < nsp; ++t) {
-                const int2 sp = spans[wv][t];
-                for (int g0 = sp.x; g0 < sp.y; g0 += 64) {
-                    const int gi = g0 + lane;
-                    const bool valid = gi < sp.y;
-                    int2 p = make_int2(cp.x, cp.y);
-                    if (valid) p = a.npos[gi];
-                    const int dx = p.x - cp.x, dy = p.y - cp.y;
-                    const double r2 = fma((double)dx, (double)dx, (double)dy * (double)dy);
-                    const bool in = valid && r2 >= e2lo && r2 < e2hi;
-                    const unsigned long long m = __ballot(in);
-                    if (in) {
-                        const int slot = (tail + __popcll(m & lt_mask)) & (kRing - 1);
-                        const float4 c = a.ncw[gi];
-                        q_xyc[wv][slot] = make_int4(dx, dy, __float_as_int(c.x), __float_as_int(c.y));
-                        q_w[wv][slot] = c.z;
-                    }
-                    tail += __popcll(m);
-                    if (tail - head >= 64) {
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                        const int slot = (head + lane) & (kRing - 1);
-                        const int4 e = q_xyc[wv][slot];
-                        const float ew = q_w[wv][slot];
-                        accumulate<GA, GB, WA, WB, EXTRA>(acc, e.x, e.y, __int_as_float(e.z),
-                                                          __int_as_float(e.w), ew);
-                        head += 64;
-                        if (++batches == kFlush) {
-                            flush<GA, GB, WA, WB, EXTRA>(acc, accd, lane);
-                            batches = 0;
-                        }
-                        __builtin_amdgcn_wave_barrier();
-                    }
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-        if (tail > head) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const bool act = lane < tail - head;
-            const int slot = (head + lane) & (kRing - 1);
-            int4 e = q_xyc[wv][slot];
-            float ew = q_w[wv][slot];
-            if (!act) e = make_int4(1, 0, 0, 0), ew = 0.0f;
-            accumulate<GA, GB, WA, WB, EXTRA>(acc, e.x, e.y, __int_as_float(e.z),
-                                              __int_as_float(e.w), ew);
-        }
-        pairs += (unsigned long long)(tail);
-
+            });
         flush<GA, GB, WA, WB, EXTRA>(acc, accd, lane);
         // lane holds slots [P*lane, P*lane + P)
 #pragma unroll
@@ -457,10 +346,10 @@ int scan_chunk(t3_plan *plan, const SortedCatalog &sc, const CentreSet &cs, int6
     if (plan->scan_var < 0) T3_TRY(scan_prepare(plan));
     const Variant &var = variants()[plan->scan_var];
     ScanArgs a{};
-    a.npos = sc.pos.as<int2>();
-    a.ncw = sc.cw.as<float4>();
-    a.cell_start = sc.cell_start.as<int>();
-    a.g = sc.grid;
+    a.sw.npos = sc.pos.as<int2>();
+    a.sw.ncw = sc.cw.as<float4>();
+    a.sw.cell_start = sc.cell_start.as<int>();
+    a.sw.g = sc.grid;
     a.cpos = cs.pos.as<int2>() + c0;
     a.ccw = cs.cw.as<float4>() + c0;
     a.n_c = n_c;

@@ -152,6 +152,8 @@ int normalise_resum(t3_plan *plan, const double *ups, int n_sets, int n_z, int n
                     double *gamma_n, double *gamma_phi, hipStream_t s);
 int harmonics_export(t3_plan *plan, const CentreSet &cs, const ChunkLayout &L, const float *planes,
                      int64_t c0, int n_c, float *G, float *W, float *D, hipStream_t s);
+int normalise_backward(t3_plan *plan, const double *ups, const double *ggam, int n_sets, double *gups,
+                       hipStream_t s);
 int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float *gg1, float *gg2,
              float *gw, hipStream_t s);
 

@@ -48,7 +48,8 @@ class T3Error(RuntimeError):
 
 
 EXPORTED = ["t3_plan_create", "t3_plan_destroy", "t3_forward", "t3_forward_tomo", "t3_harmonics",
-            "t3_normalise_resum", "t3_backward", "t3_stage_times", "t3_error_string",
+            "t3_normalise_resum", "t3_normalise_backward", "t3_backward", "t3_stage_times",
+            "t3_error_string",
             "t3_last_error_message", "t3_version"]
 
 
@@ -71,6 +72,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.t3_harmonics.restype = ctypes.c_int
     lib.t3_normalise_resum.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     lib.t3_normalise_resum.restype = ctypes.c_int
+    lib.t3_normalise_backward.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
+    lib.t3_normalise_backward.restype = ctypes.c_int
     lib.t3_backward.argtypes = [vp, P(t3_catalog), vp, vp, vp, vp, vp]
     lib.t3_backward.restype = ctypes.c_int
     lib.t3_stage_times.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
@@ -224,6 +227,16 @@ class Plan:
         _check(_lib.t3_normalise_resum(self._h, _ptr(u), sets, int(n_phi), _ptr(gn), _ptr(gp), _stream()))
         return torch.view_as_complex(gn), (None if gp is None else torch.view_as_complex(gp))
 
+    def normalise_backward(self, ups: torch.Tensor, grad_gamma_n: torch.Tensor) -> torch.Tensor:
+        """dL/dUpsilon (and dL/dN_0) from dL/dGamma_n; real views [..., 2]."""
+        u = torch.view_as_real(ups).contiguous() if ups.is_complex() else ups.contiguous()
+        g = torch.view_as_real(grad_gamma_n).contiguous() if grad_gamma_n.is_complex() else grad_gamma_n.contiguous()
+        lead = u.shape[:-5]
+        sets = int(np.prod(lead)) if len(lead) else 1
+        out = torch.empty_like(u)
+        _check(_lib.t3_normalise_backward(self._h, _ptr(u), sets, _ptr(g), _ptr(out), _stream()))
+        return out
+
     def stage_times(self):
         """(ms[4], launches[4]) of the last forward call (timing plans only):
         cell build, stage 1, stage 2, unused."""
@@ -246,3 +259,31 @@ class Plan:
 
 def version() -> str:
     return _lib.t3_version().decode()
+
+
+class GammaMultipoles(torch.autograd.Function):
+    """Gamma_{mu,n}(b1, b2) = Upsilon_{mu,n} / N_0 (mu = 0..3, n = 0..n_max) as a
+    differentiable function of every galaxy's (g1, g2, w), returned as a real
+    view [4, n_max + 1, B, B, 2].  Forward and backward both run in the HIP
+    library (t3_forward + t3_normalise_resum, t3_normalise_backward +
+    t3_backward); positions are constants."""
+
+    @staticmethod
+    def forward(ctx, g1, g2, w, x, y, plan):
+        cat = DeviceCatalog.__new__(DeviceCatalog)
+        cat.x, cat.y = x.contiguous(), y.contiguous()
+        cat.g1, cat.g2, cat.w = g1.detach().contiguous(), g2.detach().contiguous(), w.detach().contiguous()
+        cat.n = int(x.shape[0])
+        ups, _ = plan.forward(cat)
+        gn, _ = plan.normalise_resum(ups, with_phi=False)
+        ctx.plan = plan
+        ctx.cat = cat
+        ctx.save_for_backward(torch.view_as_real(ups))
+        return torch.view_as_real(gn).clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (ups,) = ctx.saved_tensors
+        gups = ctx.plan.normalise_backward(ups, grad_out.contiguous())
+        gg1, gg2, gw = ctx.plan.backward(ctx.cat, gups)
+        return gg1, gg2, gw, None, None, None

@@ -1,0 +1,168 @@
+"""The hand-written adjoint (t3_normalise_backward + t3_backward) on the GPU.
+
+* elementwise against the FP64 autograd oracle on a small catalog;
+* against central finite differences of the GPU forward (exact for the
+  shears: the loss is quadratic in each gamma_j);
+* on the 500k-galaxy, 7 deg x 7 deg workload (15 bins 1'-60', n_max 20),
+  exact identities that hold at any size:
+    - Gamma is homogeneous of degree 3 in the shears:
+          sum_j g . dL/dg_j = 6 sum omega Re(conj(Gamma - T) Gamma);
+    - Gamma is homogeneous of degree 0 in the weights: sum_j w_j dL/dw_j = 0;
+    - a common phase rotation of every shear, gamma -> gamma e^{i eps},
+      turns Gamma_0 by e^{3 i eps} and Gamma_{1,2,3} by e^{i eps}:
+          sum_j (g1 dL/dg2 - g2 dL/dg1) = sum 2 omega Re(conj(Gamma - T) i k_mu Gamma),
+      k = (3, 1, 1, 1).
+Tolerances: 2e-5 (norm-relative) against the oracle; 1e-4 for the
+full-size identities (FP32 gradients summed over 5e5 galaxies).
+"""
+import numpy as np
+import pytest
+
+from paper_2309_08601_amd.synth import WORKLOADS, make_catalogs, random_catalog
+from _util import box_for
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def t3():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08601_amd import t3 as mod
+    return mod
+
+
+def _loss_torch(gam, T, om):
+    d = gam - T
+    return torch.sum(om * (d.real ** 2 + d.imag ** 2))
+
+
+def _gpu_loss_and_grad(t3, plan, cat, T, om):
+    dev = "cuda"
+    x = torch.from_numpy(cat.x).to(dev)
+    y = torch.from_numpy(cat.y).to(dev)
+    g1 = torch.from_numpy(cat.g1.copy()).to(dev).requires_grad_(True)
+    g2 = torch.from_numpy(cat.g2.copy()).to(dev).requires_grad_(True)
+    w = torch.from_numpy(cat.w.copy()).to(dev).requires_grad_(True)
+    gam = torch.view_as_complex(t3.GammaMultipoles.apply(g1, g2, w, x, y, plan))
+    L = _loss_torch(gam, T.to(dev), om.to(dev))
+    L.backward()
+    return L.detach(), gam.detach(), g1.grad.cpu().numpy(), g2.grad.cpu().numpy(), w.grad.cpu().numpy()
+
+
+def test_normalise_backward_matches_autograd(t3):
+    rng = np.random.default_rng(1)
+    nm, B = 4, 3
+    plan = t3.Plan(np.geomspace(1, 5, B + 1), nm, box_size=1 << 20)
+    ups = torch.from_numpy(rng.standard_normal((5, nm + 1, B, B, 2)))
+    ups[4, 0, :, :, 0] = torch.from_numpy(rng.uniform(1, 2, (B, B)))
+    ups[4, 0, :, :, 1] = 0
+    gg = torch.from_numpy(rng.standard_normal((4, nm + 1, B, B, 2)))
+    got = plan.normalise_backward(ups.cuda(), gg.cuda()).cpu()
+    u = ups.clone().requires_grad_(True)
+    uc = torch.view_as_complex(u)
+    gam = uc[:4] / uc[4, 0].real[None, None]
+    gam_r = torch.view_as_real(gam)
+    (gam_r * gg).sum().backward()
+    assert torch.allclose(got, u.grad, rtol=1e-12, atol=1e-12)
+
+
+def test_backward_matches_fp64_autograd_oracle(t3):
+    from oracle import autodiff as ad
+    cat = random_catalog(1500, 40.0, seed=501)
+    tgt = random_catalog(1500, 40.0, seed=502)
+    edges = np.geomspace(1.0, 12.0, 6)
+    nm = 8
+    pl = ad.pairs(cat.x, cat.y, edges)
+    t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))  # noqa: E731
+    uT, NT = ad.multipoles(tgt.x, tgt.y, t(tgt.g1), t(tgt.g2), t(tgt.w), edges, nm)
+    T = ad.gamma(uT, NT).detach()
+    om = ad.loss_weights(T)
+    g1 = t(cat.g1).requires_grad_(True)
+    g2 = t(cat.g2).requires_grad_(True)
+    w = t(cat.w).requires_grad_(True)
+    u, N = ad.multipoles(cat.x, cat.y, g1, g2, w, edges, nm, pair_list=pl)
+    Lr = ad.loss(ad.gamma(u, N), T, om)
+    Lr.backward()
+    lo, size = box_for(40.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size)
+    L, _, d1, d2, dw = _gpu_loss_and_grad(t3, plan, cat, T, om)
+    assert abs(float(L) - float(Lr)) < 1e-5 * float(Lr)
+    for got, ref, name in ((d1, g1.grad, "g1"), (d2, g2.grad, "g2"), (dw, w.grad, "w")):
+        ref = ref.numpy()
+        e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        m = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"grad {name}: rel-norm {e:.2e}, rel-max {m:.2e}", flush=True)
+        assert e < 2e-5 and m < 1e-4, (name, e, m)
+
+
+def test_backward_matches_finite_differences_of_gpu_forward(t3):
+    cat = random_catalog(2000, 45.0, seed=601)
+    tgt = random_catalog(2000, 45.0, seed=602)
+    edges = np.geomspace(1.0, 14.0, 6)
+    nm = 10
+    lo, size = box_for(45.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size)
+    Tu, _ = plan.forward(t3.DeviceCatalog.from_catalog(tgt))
+    T, _ = plan.normalise_resum(Tu, with_phi=False)
+    T = T.cpu()
+    om = 1.0 / torch.clamp(torch.mean(T.real ** 2 + T.imag ** 2, dim=1, keepdim=True), min=1e-300)
+    om = om.expand_as(T.real).contiguous()
+    L0, _, d1, d2, _ = _gpu_loss_and_grad(t3, plan, cat, T, om)
+
+    def L_of(g1, g2):
+        c = t3.DeviceCatalog(cat.x, cat.y, g1, g2, cat.w)
+        u, _ = plan.forward(c)
+        g, _ = plan.normalise_resum(u, with_phi=False)
+        return float(_loss_torch(g.cpu(), T, om))
+
+    rng = np.random.default_rng(9)
+    h = 0.05
+    for j in rng.choice(cat.n, 12, replace=False):
+        for which, grad in ((0, d1), (1, d2)):
+            a = [cat.g1.astype(np.float64).copy(), cat.g2.astype(np.float64).copy()]
+            ap = [v.copy() for v in a]
+            am = [v.copy() for v in a]
+            ap[which][j] += h
+            am[which][j] -= h
+            fd = (L_of(*[v.astype(np.float32) for v in ap]) - L_of(*[v.astype(np.float32) for v in am])) / (2 * h)
+            g = float(grad[j])
+            scale = np.abs(grad).max()
+            assert abs(fd - g) <= 1e-2 * max(abs(g), 0.05 * scale), (j, which, fd, g)
+
+
+def test_backward_exact_identities_at_500k(t3):
+    wl = WORKLOADS["grad_500k"]
+    cat = make_catalogs(wl)[0]
+    tgt = make_catalogs(wl, seed_offset=100)[0]
+    lo, size = box_for(wl.side)
+    plan = t3.Plan(wl.edges(), wl.n_max, box_lo=lo, box_size=size)
+    Tu, _ = plan.forward(t3.DeviceCatalog.from_catalog(tgt))
+    T, _ = plan.normalise_resum(Tu, with_phi=False)
+    T = T.cpu()
+    om = 1.0 / torch.clamp(torch.mean(T.real ** 2 + T.imag ** 2, dim=1, keepdim=True), min=1e-300)
+    om = om.expand_as(T.real).contiguous()
+    L, gam, d1, d2, dw = _gpu_loss_and_grad(t3, plan, cat, T, om)
+    gam = gam.cpu()
+    D = gam - T
+    g1 = cat.g1.astype(np.float64)
+    g2 = cat.g2.astype(np.float64)
+    w = cat.w.astype(np.float64)
+    # degree 3 in the shears
+    lhs = float(np.dot(g1, d1) + np.dot(g2, d2))
+    rhs = float(6.0 * torch.sum(om * (D.real * gam.real + D.imag * gam.imag)))
+    print(f"shear homogeneity: {lhs:.6e} vs {rhs:.6e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-4 * abs(rhs)
+    # degree 0 in the weights
+    lw = float(np.dot(w, dw))
+    scale = float(np.sum(np.abs(w * dw)))
+    print(f"weight homogeneity: {lw:.3e} (scale {scale:.3e})", flush=True)
+    assert abs(lw) <= 1e-4 * scale
+    # common phase rotation of the shears
+    k = torch.tensor([3.0, 1.0, 1.0, 1.0], dtype=torch.float64)[:, None, None, None]
+    ig = k * torch.complex(-gam.imag, gam.real)
+    rhs2 = float(2.0 * torch.sum(om * (D.real * ig.real + D.imag * ig.imag)))
+    lhs2 = float(np.dot(g1, d2) - np.dot(g2, d1))
+    print(f"phase rotation: {lhs2:.6e} vs {rhs2:.6e}", flush=True)
+    assert abs(lhs2 - rhs2) <= 1e-4 * max(abs(rhs2), 1e-3 * abs(rhs))
