@@ -67,7 +67,8 @@ extern "C" {
 
 /* Precision of the contraction over centres (stage 2). */
 #define T3_PREC_FP32 0    /* FP32 MFMA products, FP32 runs promoted to FP64 */
-#define T3_PREC_BF16X3 1  /* x = hi + lo in bf16; hi*hi + hi*lo + lo*hi     */
+#define T3_PREC_BF16X3 1  /* x = hi + lo in bf16; hi*hi + hi*lo + lo*hi for  */
+                          /* Upsilon_0..3, FP32 for the normaliser N_n      */
 #define T3_PREC_FP16X3 2  /* same in fp16 with power-of-two row scaling     */
 
 #define T3_FLAG_KEEP_JK 1u /* keep the j = k terms (the paper's literal sum) */

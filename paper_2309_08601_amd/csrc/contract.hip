@@ -19,6 +19,8 @@
 //  * FP32:    v_mfma_f32_32x32x2_f32.
 //  * BF16x3:  x = hi + lo with hi = bf16(x), lo = bf16(x - hi); each real
 //             product is hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16.
+//             The normaliser N_n, which divides every Gamma, stays on the
+//             FP32 path (hi + lo in bf16 keeps about 17 bits).
 //  * FP16x3:  as BF16x3 in fp16 after scaling each (operand, bin) row by a
 //             power of two so that its largest entry is near 2^12 (keeps lo
 //             out of the subnormal range); the scales are divided out in FP64.
@@ -40,6 +42,7 @@ struct ContractArgs {
     const float *scale;  // fp16 row exponents [2][5][n_max+1][B] or null
     int n_c, K, B, n_max;
     int slice;           // centres per slice (multiple of 16)
+    int mu0;             // first component of this launch (grid.x covers mu >= mu0)
     double *partial;     // [S][5][n_max+1][B][B][2]
 };
 
@@ -125,7 +128,7 @@ __device__ __forceinline__ float4 load4(const float *planes, int plane, int ib, 
 __global__ __launch_bounds__(64) void k_contract_fp32(ContractArgs a)
 {
     const int lane = threadIdx.x;
-    const int mn = blockIdx.x;
+    const int mn = blockIdx.x + a.mu0 * (a.n_max + 1);
     const int mu = mn / (a.n_max + 1), n = mn % (a.n_max + 1);
     const int sl = blockIdx.y;
     const int i_begin = sl * a.slice;
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(64) void k_contract_split(ContractArgs a)
     using T = typename std::conditional<FP16, _Float16, __bf16>::type;
     using V8 = typename std::conditional<FP16, halfx8, bf16x8>::type;
     const int lane = threadIdx.x;
-    const int mn = blockIdx.x;
+    const int mn = blockIdx.x + a.mu0 * (a.n_max + 1);
     const int mu = mn / (a.n_max + 1), n = mn % (a.n_max + 1);
     const int sl = blockIdx.y;
     const int i_begin = sl * a.slice;
@@ -475,7 +478,12 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
     if (plan->precision == T3_PREC_FP32) {
         hipLaunchKernelGGL(k_contract_fp32, dim3(nmn, S), dim3(64), 0, s, a);
     } else if (plan->precision == T3_PREC_BF16X3) {
-        hipLaunchKernelGGL(k_contract_split<false>, dim3(nmn, S), dim3(64), 0, s, a);
+        const int nu = 4 * (L.n_max + 1);
+        hipLaunchKernelGGL(k_contract_split<false>, dim3(nu, S), dim3(64), 0, s, a);
+        T3_HIP_CHECK(hipGetLastError());
+        ContractArgs an = a;
+        an.mu0 = 4;
+        hipLaunchKernelGGL(k_contract_fp32, dim3(nmn - nu, S), dim3(64), 0, s, an);
     } else {
         T3_TRY(plan->scales.reserve(sizeof(float) * 2 * per / L.B));
         hipLaunchKernelGGL(k_fp16_scales, dim3(nmn, L.B, 2), dim3(256), 0, s, a,

@@ -9,7 +9,7 @@
 //    annulus sweep (sweep.h): row runs of the cell list, coalesced candidate
 //    tests, ballot compaction into an LDS ring, 64 in-bin neighbours per
 //    batch, each lane taking one through the harmonic recurrence;
-//  * per-lane FP32 accumulators hold one bin of one centre; every 32 batches
+//  * per-lane FP32 accumulators hold one bin of one centre; every 64 batches
 //    and at the end of the bin a 6-step reduce-scatter leaves each lane a few
 //    wave totals, which are added to per-lane FP64 partials; at the end of
 //    the bin those are stored into the chunk planes (layout in t3_internal.h).
@@ -31,7 +31,7 @@ namespace {
 constexpr int kWaves = 4;       // wavefronts (centres) per workgroup
 constexpr int kAnchor = 8;      // FP64 anchor stride of the power recurrence
 constexpr int kMaxBins = 64;
-constexpr int kFlush = 32;      // batches of 64 neighbours per FP32 run before FP64 promotion
+constexpr int kFlush = 64;      // batches of 64 neighbours per FP32 run before FP64 promotion
 
 struct ScanArgs {
     SweepArgs sw;           // cell-sorted neighbour catalog
@@ -179,7 +179,10 @@ __device__ __forceinline__ void flush(float (&acc)[V], double (&accd)[P], int la
 }
 
 template <int GA, int GB, int WA, int WB, bool EXTRA>
-__global__ __launch_bounds__(64 * kWaves) void k_scan(ScanArgs a)
+// Two workgroups per CU (2 wavefronts per SIMD): measured faster than one
+// wavefront per SIMD without spills, although the largest variants then
+// spill some registers.
+__global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
 {
     using S = PassShape<GA, GB, WA, WB, EXTRA>;
     __shared__ int4 q_xyc[kWaves][kRing];
