@@ -72,7 +72,10 @@ extern "C" {
 #define T3_PREC_FP16X3 2  /* same in fp16 with power-of-two row scaling     */
 
 #define T3_FLAG_KEEP_JK 1u /* keep the j = k terms (the paper's literal sum) */
-#define T3_FLAG_TIMING 2u  /* record HIP events around each stage (t3_stage_times) */
+#define T3_FLAG_TIMING 2u  /* record HIP events around each stage (t3_stage_times); */
+                           /* also runs the schedule eagerly (no graph)           */
+#define T3_FLAG_NO_GRAPH 4u /* launch the chunk schedule eagerly instead of as one  */
+                            /* captured HIP graph                                  */
 
 typedef struct {
     int32_t n_bins;        /* B >= 1                                         */
@@ -87,6 +90,8 @@ typedef struct {
     int64_t box_size;      /* side in lattice steps, > 0, box_lo + size <= 2^31 */
     double cell_arcmin;    /* spatial-hash cell side; 0 -> automatic          */
     int32_t chunk_centres; /* centres per stage-1/stage-2 chunk; 0 -> auto    */
+    int32_t scan_mode;     /* stage-1 launch: 0 one wavefront per (centre,    */
+                           /* catalog), 1 persistent grid with a work queue   */
 } t3_params;
 
 typedef struct {
@@ -181,6 +186,17 @@ int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets,
  * Synchronises the stream before returning. */
 int t3_backward(t3_plan *plan, const t3_catalog *cat, const double *grad_ups,
                 float *grad_g1, float *grad_g2, float *grad_w, void *stream);
+
+/* Autotuner.  Times the forward pass of this plan on a deterministic sample
+ * of at most sample_per_bin centres of every catalog (cats: HOST array of
+ * n_z catalogs, as for t3_forward_tomo) for a few candidate settings -- cell
+ * size 0.6x / 1x / 1.6x the automatic one, and both stage-1 launch modes --
+ * and keeps the fastest in the plan (cell size, launch mode).  The choice is
+ * cached per process, keyed by (n_bins, n_max, n_z, precision, catalog-size
+ * class); a cached choice is applied without timing.  best_ms (HOST,
+ * optional) receives the best sample time.  Synchronises the stream. */
+int t3_autotune(t3_plan *plan, const t3_catalog *cats, int32_t n_z, int64_t sample_per_bin,
+                double *best_ms, void *stream);
 
 /* Stage timings of the most recent t3_forward / t3_forward_tomo call of a
  * plan created with T3_FLAG_TIMING, from HIP events recorded on the

@@ -477,7 +477,9 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
     for (int64_t c0 = 0; c0 < n; c0 += L.K) {
         const int nc = (int)((n - c0) < L.K ? (n - c0) : L.K);
         T3_TRY(timing_mark(plan, 1, true, s));
-        T3_TRY(scan_chunk(plan, sc, plan->centres, c0, nc, L, plan->chunk.as<float>(), nullptr, s));
+        const SortedCatalog *cl[1] = {&sc};
+        T3_TRY(scan_chunk(plan, cl, nullptr, 1, plan->centres, c0, nc, L, plan->chunk.as<float>(), 0, nullptr,
+                          plan->scan_mode, s));
         T3_TRY(timing_mark(plan, 1, false, s));
         T3_TRY(timing_mark(plan, 2, true, s));
         CoefArgs ca{};

@@ -1,5 +1,9 @@
 // C ABI of the t3pcf library (declared in include/t3pcf.h).
+#include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cstring>
 #include <new>
 
@@ -126,6 +130,104 @@ static ChunkLayout layout_of(const t3_plan *plan)
     return L;
 }
 
+// Forward pass over n_z catalogs: centres of catalog z1 (list or all)
+// against every catalog; output block [z1][z2][z3] (n_z = 1: one block).
+static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const int32_t *const *centres,
+                        const int64_t *n_centres, double *ups_out, int64_t *n_pairs, hipStream_t s)
+{
+    T3_TRY(timing_begin_call(plan));
+    T3_TRY(prepare_small(plan, s));
+    if (plan->scan_var < 0) T3_TRY(scan_prepare(plan));
+    int64_t n_all = 0;
+    for (int z = 0; z < n_z; ++z) n_all += cats[z].n;
+    const CellGrid grid = choose_grid(plan, n_all > 0 ? n_all / n_z : 0);
+    T3_TRY(timing_mark(plan, 0, true, s));
+    for (int z = 0; z < n_z; ++z) T3_TRY(build_cells(plan, plan->cats[z], cats[z], grid, s));
+    for (int z = 0; z < n_z; ++z) {
+        if (n_centres[z] >= 0)
+            T3_TRY(gather_centres(plan, cats[z], centres[z], n_centres[z], plan->csets[z], s));
+        else
+            T3_TRY(gather_sorted_centres(plan, plan->cats[z], plan->csets[z], s));
+    }
+    T3_TRY(timing_mark(plan, 0, false, s));
+    T3_TRY(check_flag(plan, s, n_z > 1 ? "t3_forward_tomo" : "t3_forward"));
+
+    ChunkLayout L = layout_of(plan);
+    if (n_z > 1 && plan->chunk_req <= 0) {
+        // n_z plane sets are live at once: keep them near twice one chunk
+        int K = L.K / n_z * 2;
+        K = K < 256 ? 256 : (K & ~255);
+        L.K = K;
+    }
+    // catalogs densest first (balances the stage-1 work queue)
+    int order[8];
+    for (int z = 0; z < n_z; ++z) order[z] = z;
+    for (int i = 1; i < n_z; ++i)
+        for (int j = i; j > 0 && cats[order[j]].n > cats[order[j - 1]].n; --j) std::swap(order[j], order[j - 1]);
+    const size_t per_set = (size_t)2 * 5 * (plan->n_max + 1) * plan->B * plan->B;
+    const size_t n_out = per_set * (size_t)n_z * n_z * n_z;
+    const size_t zstride = L.floats();
+    // every buffer the schedule touches is reserved before it is recorded
+    T3_TRY(plan->chunk.reserve(sizeof(float) * zstride * (size_t)n_z));
+    T3_TRY(reserve_contract(plan, L, n_z));
+    T3_TRY(plan->queue.reserve(sizeof(unsigned) * 4));
+    const SortedCatalog *cl[8];
+    for (int z = 0; z < n_z; ++z) cl[z] = &plan->cats[z];
+    const bool jk = !(plan->flags & T3_FLAG_KEEP_JK);
+    const bool timing = (plan->flags & T3_FLAG_TIMING) != 0;
+    const bool graph = !timing && !(plan->flags & T3_FLAG_NO_GRAPH);
+
+    auto schedule = [&](hipStream_t q) -> int {
+        T3_TRY(zero_doubles(ups_out, n_out, q));
+        for (int z1 = 0; z1 < n_z; ++z1) {
+            const CentreSet &cs = plan->csets[z1];
+            double *out = ups_out + per_set * (size_t)n_z * n_z * z1;
+            for (int64_t c0 = 0; c0 < cs.n; c0 += L.K) {
+                const int n = (int)((cs.n - c0) < L.K ? (cs.n - c0) : L.K);
+                T3_TRY(timing_mark(plan, 1, true, q));
+                T3_TRY(scan_chunk(plan, cl, order, n_z, cs, c0, n, L, plan->chunk.as<float>(), zstride,
+                                  plan->counter.as<unsigned long long>(), plan->scan_mode, q));
+                T3_TRY(timing_mark(plan, 1, false, q));
+                T3_TRY(timing_mark(plan, 2, true, q));
+                T3_TRY(contract_chunk(plan, cs, c0, n, L, plan->chunk.as<float>(), zstride, n_z, jk, out, q));
+                T3_TRY(timing_mark(plan, 2, false, q));
+            }
+        }
+        return T3_OK;
+    };
+
+    if (graph) {
+        if (!plan->cap_stream) T3_HIP_CHECK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+        // order the capture stream after the set-up work of this call
+        T3_HIP_CHECK(hipStreamSynchronize(s));
+        if (plan->graph_exec) {
+            (void)hipGraphExecDestroy(plan->graph_exec);
+            plan->graph_exec = nullptr;
+        }
+        T3_HIP_CHECK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
+        const int rc = schedule(plan->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(plan->cap_stream, &g);
+        if (rc != T3_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (ec != hipSuccess) return fail(T3_EHIP, std::string("graph capture: ") + hipGetErrorString(ec));
+        const hipError_t ei = hipGraphInstantiate(&plan->graph_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return fail(T3_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        T3_HIP_CHECK(hipGraphLaunch(plan->graph_exec, s));
+    } else {
+        T3_TRY(schedule(s));
+    }
+    unsigned long long pairs = 0;
+    T3_HIP_CHECK(hipMemcpyAsync(&pairs, plan->counter.ptr, sizeof(pairs), hipMemcpyDeviceToHost, s));
+    T3_HIP_CHECK(hipStreamSynchronize(s));
+    T3_TRY(timing_end_call(plan));
+    if (n_pairs) *n_pairs = (int64_t)pairs;
+    return T3_OK;
+}
+
 }  // namespace t3
 
 using namespace t3;
@@ -158,7 +260,7 @@ int t3_plan_create(const t3_params *p, t3_plan **out)
         if (p->n_max < 0 || p->n_max > 64) return fail(T3_ERANGE, "t3_plan_create: n_max must be in [0, 64]");
         if (p->precision < T3_PREC_FP32 || p->precision > T3_PREC_FP16X3)
             return fail(T3_EINVAL, "t3_plan_create: unknown precision");
-        if (p->flags & ~(T3_FLAG_KEEP_JK | T3_FLAG_TIMING))
+        if (p->flags & ~(T3_FLAG_KEEP_JK | T3_FLAG_TIMING | T3_FLAG_NO_GRAPH))
             return fail(T3_EINVAL, "t3_plan_create: unknown flag");
         const double unit = p->lattice_unit == 0.0 ? std::ldexp(1.0, -16) : p->lattice_unit;
         if (!(unit > 0.0) || !std::isfinite(unit)) return fail(T3_EINVAL, "t3_plan_create: bad lattice unit");
@@ -177,6 +279,7 @@ int t3_plan_create(const t3_params *p, t3_plan **out)
         if (p->cell_arcmin < 0.0 || !std::isfinite(p->cell_arcmin))
             return fail(T3_EINVAL, "t3_plan_create: bad cell size");
         if (p->chunk_centres < 0) return fail(T3_EINVAL, "t3_plan_create: bad chunk size");
+        if (p->scan_mode < 0 || p->scan_mode > 1) return fail(T3_EINVAL, "t3_plan_create: bad scan mode");
 
         t3_plan *plan = new (std::nothrow) t3_plan();
         if (!plan) return fail(T3_ENOMEM, "t3_plan_create: host allocation failed");
@@ -190,6 +293,7 @@ int t3_plan_create(const t3_params *p, t3_plan **out)
         plan->box_size = p->box_size;
         plan->cell_arcmin = p->cell_arcmin;
         plan->chunk_req = p->chunk_centres;
+        plan->scan_mode = p->scan_mode;
         plan->edges_lat.resize(p->n_bins + 1);
         plan->e2.resize(p->n_bins + 1);
         for (int b = 0; b <= p->n_bins; ++b) {
@@ -230,6 +334,15 @@ void t3_plan_destroy(t3_plan *plan)
     plan->misc.release();
     plan->misc2.release();
     for (auto e : plan->events) (void)hipEventDestroy(e);
+    for (auto &c : plan->csets) {
+        c.pos.release();
+        c.cw.release();
+    }
+    plan->queue.release();
+    plan->tune_idx.release();
+    plan->tune_out.release();
+    if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
 }
 
@@ -243,39 +356,9 @@ int t3_forward(t3_plan *plan, const t3_catalog *cat, const int32_t *centres, int
             return fail(T3_EINVAL, "t3_forward: n_centres < 0 (all galaxies) needs centres == NULL");
         if (n_centres > 0 && !centres) return fail(T3_EINVAL, "t3_forward: null centre list");
         if (n_centres > (int64_t)0x7fffffff) return fail(T3_EINVAL, "t3_forward: bad centre count");
-        hipStream_t s = (hipStream_t)stream;
-        T3_TRY(timing_begin_call(plan));
-        T3_TRY(prepare_small(plan, s));
-        SortedCatalog &sc = plan->cats[0];
-        T3_TRY(timing_mark(plan, 0, true, s));
-        T3_TRY(build_cells(plan, sc, *cat, choose_grid(plan, cat->n), s));
-        if (n_centres >= 0) T3_TRY(gather_centres(plan, *cat, centres, n_centres, plan->centres, s));
-        else T3_TRY(gather_sorted_centres(plan, sc, plan->centres, s));
-        T3_TRY(timing_mark(plan, 0, false, s));
-        T3_TRY(check_flag(plan, s, "t3_forward"));
-        const ChunkLayout L = layout_of(plan);
-        const size_t n_out = (size_t)2 * 5 * (plan->n_max + 1) * plan->B * plan->B;
-        T3_TRY(zero_doubles(ups_out, n_out, s));
-        T3_TRY(plan->chunk.reserve(sizeof(float) * L.floats()));
-        const int64_t nc = plan->centres.n;
-        const bool jk = !(plan->flags & T3_FLAG_KEEP_JK);
-        for (int64_t c0 = 0; c0 < nc; c0 += L.K) {
-            const int n = (int)((nc - c0) < L.K ? (nc - c0) : L.K);
-            T3_TRY(timing_mark(plan, 1, true, s));
-            T3_TRY(scan_chunk(plan, sc, plan->centres, c0, n, L, plan->chunk.as<float>(),
-                              plan->counter.as<unsigned long long>(), s));
-            T3_TRY(timing_mark(plan, 1, false, s));
-            T3_TRY(timing_mark(plan, 2, true, s));
-            T3_TRY(contract_chunk(plan, plan->centres, c0, n, L, plan->chunk.as<float>(),
-                                  plan->chunk.as<float>(), jk, ups_out, s));
-            T3_TRY(timing_mark(plan, 2, false, s));
-        }
-        unsigned long long pairs = 0;
-        T3_HIP_CHECK(hipMemcpyAsync(&pairs, plan->counter.ptr, sizeof(pairs), hipMemcpyDeviceToHost, s));
-        T3_HIP_CHECK(hipStreamSynchronize(s));
-        T3_TRY(timing_end_call(plan));
-        if (n_pairs) *n_pairs = (int64_t)pairs;
-        return T3_OK;
+        const int32_t *cl[1] = {centres};
+        const int64_t nl[1] = {n_centres};
+        return forward_impl(plan, cat, 1, cl, nl, ups_out, n_pairs, (hipStream_t)stream);
     } catch (...) {
         return fail(T3_EINVAL, "t3_forward: exception");
     }
@@ -289,67 +372,16 @@ int t3_forward_tomo(t3_plan *plan, const t3_catalog *cats, int32_t n_z, const in
         if (n_z < 1 || n_z > 8) return fail(T3_ERANGE, "t3_forward_tomo: n_z must be in [1, 8]");
         for (int z = 0; z < n_z; ++z) T3_TRY(check_catalog(&cats[z], "t3_forward_tomo"));
         if (centres && !n_centres) return fail(T3_EINVAL, "t3_forward_tomo: centres without counts");
-        hipStream_t s = (hipStream_t)stream;
-        T3_TRY(timing_begin_call(plan));
-        T3_TRY(prepare_small(plan, s));
-        int64_t n_all = 0;
-        for (int z = 0; z < n_z; ++z) n_all += cats[z].n;
-        const CellGrid grid = choose_grid(plan, n_all > 0 ? n_all / n_z : 0);
-        T3_TRY(timing_mark(plan, 0, true, s));
-        for (int z = 0; z < n_z; ++z) T3_TRY(build_cells(plan, plan->cats[z], cats[z], grid, s));
-        T3_TRY(timing_mark(plan, 0, false, s));
-        T3_TRY(check_flag(plan, s, "t3_forward_tomo"));
-        ChunkLayout L = layout_of(plan);
-        // n_z chunk buffers at once: shrink K so that they stay near 128 MB x 2
-        if (plan->chunk_req <= 0) {
-            int K = L.K / n_z * 2;
-            K = K < 256 ? 256 : (K & ~255);
-            L.K = K;
+        const int32_t *cl[8];
+        int64_t nl[8];
+        for (int z = 0; z < n_z; ++z) {
+            cl[z] = centres ? centres[z] : nullptr;
+            nl[z] = centres ? n_centres[z] : -1;
+            if (nl[z] < 0 && cl[z]) return fail(T3_EINVAL, "t3_forward_tomo: count < 0 needs a NULL list");
+            if (nl[z] > 0 && !cl[z]) return fail(T3_EINVAL, "t3_forward_tomo: null centre list");
+            if (nl[z] > (int64_t)0x7fffffff) return fail(T3_EINVAL, "t3_forward_tomo: bad centre count");
         }
-        const size_t per_set = (size_t)2 * 5 * (plan->n_max + 1) * plan->B * plan->B;
-        T3_TRY(zero_doubles(ups_out, per_set * (size_t)n_z * n_z * n_z, s));
-        T3_TRY(plan->chunk.reserve(sizeof(float) * L.floats() * (size_t)n_z));
-        float *planes = plan->chunk.as<float>();
-        const bool jk = !(plan->flags & T3_FLAG_KEEP_JK);
-        for (int z1 = 0; z1 < n_z; ++z1) {
-            const int32_t *idx = centres ? centres[z1] : nullptr;
-            const int64_t ncz = centres ? n_centres[z1] : -1;
-            if (ncz < 0 && idx) return fail(T3_EINVAL, "t3_forward_tomo: count < 0 needs a NULL list");
-            if (ncz > 0 && !idx) return fail(T3_EINVAL, "t3_forward_tomo: null centre list");
-            if (ncz >= 0) {
-                if (ncz > (int64_t)0x7fffffff) return fail(T3_EINVAL, "t3_forward_tomo: bad centre count");
-                T3_TRY(gather_centres(plan, cats[z1], idx, ncz, plan->centres, s));
-                T3_TRY(check_flag(plan, s, "t3_forward_tomo"));
-            } else {
-                T3_TRY(gather_sorted_centres(plan, plan->cats[z1], plan->centres, s));
-            }
-            const int64_t nc = plan->centres.n;
-            for (int64_t c0 = 0; c0 < nc; c0 += L.K) {
-                const int n = (int)((nc - c0) < L.K ? (nc - c0) : L.K);
-                T3_TRY(timing_mark(plan, 1, true, s));
-                for (int z = 0; z < n_z; ++z)
-                    T3_TRY(scan_chunk(plan, plan->cats[z], plan->centres, c0, n, L,
-                                      planes + (size_t)z * L.floats(),
-                                      plan->counter.as<unsigned long long>(), s));
-                T3_TRY(timing_mark(plan, 1, false, s));
-                T3_TRY(timing_mark(plan, 2, true, s));
-                for (int z2 = 0; z2 < n_z; ++z2)
-                    for (int z3 = 0; z3 < n_z; ++z3) {
-                        double *dst = ups_out + per_set * (((size_t)z1 * n_z + z2) * n_z + z3);
-                        T3_TRY(contract_chunk(plan, plan->centres, c0, n, L,
-                                              planes + (size_t)z2 * L.floats(),
-                                              planes + (size_t)z3 * L.floats(), jk && z2 == z3,
-                                              dst, s));
-                    }
-                T3_TRY(timing_mark(plan, 2, false, s));
-            }
-        }
-        unsigned long long pairs = 0;
-        T3_HIP_CHECK(hipMemcpyAsync(&pairs, plan->counter.ptr, sizeof(pairs), hipMemcpyDeviceToHost, s));
-        T3_HIP_CHECK(hipStreamSynchronize(s));
-        T3_TRY(timing_end_call(plan));
-        if (n_pairs) *n_pairs = (int64_t)pairs;
-        return T3_OK;
+        return forward_impl(plan, cats, n_z, cl, nl, ups_out, n_pairs, (hipStream_t)stream);
     } catch (...) {
         return fail(T3_EINVAL, "t3_forward_tomo: exception");
     }
@@ -374,8 +406,9 @@ int t3_harmonics(t3_plan *plan, const t3_catalog *cat, const int32_t *centres, i
         T3_TRY(plan->chunk.reserve(sizeof(float) * L.floats()));
         for (int64_t c0 = 0; c0 < n_centres; c0 += L.K) {
             const int n = (int)((n_centres - c0) < L.K ? (n_centres - c0) : L.K);
-            T3_TRY(scan_chunk(plan, sc, plan->centres, c0, n, L, plan->chunk.as<float>(),
-                              plan->counter.as<unsigned long long>(), s));
+            const SortedCatalog *cl[1] = {&sc};
+            T3_TRY(scan_chunk(plan, cl, nullptr, 1, plan->centres, c0, n, L, plan->chunk.as<float>(), 0,
+                              plan->counter.as<unsigned long long>(), plan->scan_mode, s));
             T3_TRY(harmonics_export(plan, plan->centres, L, plan->chunk.as<float>(), c0, n, G_out,
                                     W_out, D_out, s));
         }
@@ -406,6 +439,106 @@ int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets, cons
         return fail(T3_EINVAL, "t3_normalise_backward: null argument");
     if (n_sets < 1) return fail(T3_EINVAL, "t3_normalise_backward: n_sets must be >= 1");
     return normalise_backward(plan, ups, grad_gamma_n, n_sets, grad_ups, (hipStream_t)stream);
+}
+
+int t3_autotune(t3_plan *plan, const t3_catalog *cats, int32_t n_z, int64_t sample_per_bin, double *best_ms,
+                void *stream)
+{
+    try {
+        if (!plan || !cats) return fail(T3_EINVAL, "t3_autotune: null argument");
+        if (n_z < 1 || n_z > 8) return fail(T3_ERANGE, "t3_autotune: n_z must be in [1, 8]");
+        if (sample_per_bin < 1) return fail(T3_EINVAL, "t3_autotune: sample_per_bin must be >= 1");
+        for (int z = 0; z < n_z; ++z) T3_TRY(check_catalog(&cats[z], "t3_autotune"));
+        hipStream_t s = (hipStream_t)stream;
+        int64_t n_all = 0;
+        for (int z = 0; z < n_z; ++z) n_all += cats[z].n;
+        const int64_t n_mean = n_all / n_z;
+        int size_class = 0;
+        for (int64_t v = n_mean; v > 1; v >>= 1) ++size_class;
+        static std::mutex mu;
+        static std::map<std::tuple<int, int, int, int, int, int64_t>, std::pair<double, int>> cache;
+        const auto key = std::make_tuple(plan->B, plan->n_max, n_z, plan->precision, size_class, plan->box_size);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = cache.find(key);
+            if (it != cache.end()) {
+                plan->cell_arcmin = it->second.first;
+                plan->scan_mode = it->second.second;
+                if (best_ms) *best_ms = 0.0;
+                return T3_OK;
+            }
+        }
+        // deterministic stride sample of centres per catalog
+        std::vector<int32_t> idx;
+        std::vector<int64_t> cnt(n_z), off(n_z);
+        for (int z = 0; z < n_z; ++z) {
+            const int64_t n = cats[z].n, k = std::min<int64_t>(n, sample_per_bin);
+            off[z] = (int64_t)idx.size();
+            cnt[z] = k;
+            for (int64_t j = 0; j < k; ++j) idx.push_back((int32_t)((j * n) / k));
+        }
+        T3_TRY(plan->tune_idx.reserve(sizeof(int32_t) * (idx.size() + 1)));
+        T3_HIP_CHECK(hipMemcpy(plan->tune_idx.ptr, idx.data(), sizeof(int32_t) * idx.size(),
+                               hipMemcpyHostToDevice));
+        const int32_t *cl[8];
+        for (int z = 0; z < n_z; ++z) cl[z] = plan->tune_idx.as<int32_t>() + off[z];
+        const size_t n_out = (size_t)2 * 5 * (plan->n_max + 1) * plan->B * plan->B * n_z * n_z * n_z;
+        T3_TRY(plan->tune_out.reserve(sizeof(double) * n_out));
+
+        const double area = (double)plan->box_size * (double)plan->box_size;
+        const double auto_side = std::sqrt(8.0 * area / (double)std::max<int64_t>(n_mean, 1)) * plan->unit;
+        const double keep_cell = plan->cell_arcmin;
+        const int keep_mode = plan->scan_mode;
+        const uint32_t keep_flags = plan->flags;
+        plan->flags = (plan->flags & ~T3_FLAG_TIMING) | T3_FLAG_NO_GRAPH;
+        hipEvent_t e0, e1;
+        T3_HIP_CHECK(hipEventCreate(&e0));
+        T3_HIP_CHECK(hipEventCreate(&e1));
+        double best = 1e300, best_cell = keep_cell;
+        int best_mode = keep_mode, rc = T3_OK;
+        const double factors[3] = {0.6, 1.0, 1.6};
+        for (int mode = 0; mode < 2 && rc == T3_OK; ++mode)
+            for (double f : factors) {
+                plan->cell_arcmin = f * auto_side;
+                plan->scan_mode = mode;
+                double ms_best = 1e300;
+                for (int rep = 0; rep < 2 && rc == T3_OK; ++rep) {
+                    if ((rc = (hipEventRecord(e0, s) == hipSuccess) ? T3_OK : T3_EHIP) != T3_OK) break;
+                    rc = forward_impl(plan, cats, n_z, cl, cnt.data(), plan->tune_out.as<double>(), nullptr, s);
+                    if (rc != T3_OK) break;
+                    float ms = 0.f;
+                    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        rc = fail(T3_EHIP, "t3_autotune: event timing failed");
+                        break;
+                    }
+                    ms_best = std::min(ms_best, (double)ms);
+                }
+                if (rc == T3_OK && ms_best < best) {
+                    best = ms_best;
+                    best_cell = plan->cell_arcmin;
+                    best_mode = mode;
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        plan->flags = keep_flags;
+        if (rc != T3_OK) {
+            plan->cell_arcmin = keep_cell;
+            plan->scan_mode = keep_mode;
+            return rc;
+        }
+        plan->cell_arcmin = best_cell;
+        plan->scan_mode = best_mode;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            cache[key] = std::make_pair(best_cell, best_mode);
+        }
+        if (best_ms) *best_ms = best;
+        return T3_OK;
+    } catch (...) {
+        return fail(T3_EINVAL, "t3_autotune: exception");
+    }
 }
 
 int t3_stage_times(const t3_plan *plan, double *ms, int64_t *launches)

@@ -10,7 +10,7 @@
 //     mu = 4: alpha =  w,  X = W_n,          Y = W_n*
 // A complex product is four real MFMAs: Re += Xr Yr - Xi Yi, Im += Xr Yi + Xi Yr.
 // Each wavefront owns one (mu, n) and one slice of centres; FP32 MFMA runs
-// of at most 256 centres are promoted into FP64 accumulators, and the
+// of at most 64 centres are promoted into FP64 accumulators, and the
 // slices are summed in FP64 in a fixed order (deterministic).  The j = k
 // terms (n-independent, diagonal only) are summed separately in FP64 and
 // subtracted in the final reduction.
@@ -33,18 +33,29 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
-constexpr int kRun = 256;  // centres per FP32 accumulation run
+constexpr int kRun = 64;   // centres per FP32 accumulation run before FP64 promotion
 
+// One launch covers every ordered pair (Z2, Z3) of neighbour catalogs
+// (grid.z = n_z^2; n_z = 1 outside tomography): the b1-side harmonics come
+// from the planes of Z2, the b2-side ones from those of Z3.
 struct ContractArgs {
-    const float *px;     // planes of the b1-side harmonics
-    const float *py;     // planes of the b2-side harmonics
+    const float *planes; // planes of catalog 0; catalog z at planes + z * zstride
+    size_t zstride;
     const float4 *ccw;   // centre factors (w g1, w g2, w, 0), chunk-relative
-    const float *scale;  // fp16 row exponents [2][5][n_max+1][B] or null
-    int n_c, K, B, n_max;
+    const float *scale;  // fp16 row scales [pair][2][5][n_max+1][B] or null
+    int n_c, K, B, n_max, n_z;
     int slice;           // centres per slice (multiple of 16)
+    int S;               // slices
     int mu0;             // first component of this launch (grid.x covers mu >= mu0)
-    double *partial;     // [S][5][n_max+1][B][B][2]
+    double *partial;     // [pair][S][5][n_max+1][B][B][2]
 };
+
+__device__ __forceinline__ void pair_planes(const ContractArgs &a, int pair, const float *&px,
+                                            const float *&py)
+{
+    px = a.planes + (size_t)(pair / a.n_z) * a.zstride;
+    py = a.planes + (size_t)(pair % a.n_z) * a.zstride;
+}
 
 struct Operands {
     int xr, xi, yr, yi;  // plane indices
@@ -131,6 +142,9 @@ __global__ __launch_bounds__(64) void k_contract_fp32(ContractArgs a)
     const int mn = blockIdx.x + a.mu0 * (a.n_max + 1);
     const int mu = mn / (a.n_max + 1), n = mn % (a.n_max + 1);
     const int sl = blockIdx.y;
+    const int pair = blockIdx.z;
+    const float *px, *py;
+    pair_planes(a, pair, px, py);
     const int i_begin = sl * a.slice;
     const int i_end = min(i_begin + a.slice, a.n_c);
     const Operands o = operands(mu, n, a.n_max);
@@ -144,10 +158,10 @@ __global__ __launch_bounds__(64) void k_contract_fp32(ContractArgs a)
     int run = 0;
     for (int i0 = i_begin; i0 < i_end; i0 += 8) {
         const int ib = i0 + 4 * kq;
-        const float4 xr = load4(a.px, o.xr, ib, b, a.K, a.B, i_end);
-        float4 xi = load4(a.px, o.xi, ib, b, a.K, a.B, i_end);
-        const float4 yr = load4(a.py, o.yr, ib, b, a.K, a.B, i_end);
-        float4 yi = load4(a.py, o.yi, ib, b, a.K, a.B, i_end);
+        const float4 xr = load4(px, o.xr, ib, b, a.K, a.B, i_end);
+        float4 xi = load4(px, o.xi, ib, b, a.K, a.B, i_end);
+        const float4 yr = load4(py, o.yr, ib, b, a.K, a.B, i_end);
+        float4 yi = load4(py, o.yi, ib, b, a.K, a.B, i_end);
         const float xa[4] = {xr.x, xr.y, xr.z, xr.w};
         const float xb[4] = {xi.x * o.xs, xi.y * o.xs, xi.z * o.xs, xi.w * o.xs};
         const float ya[4] = {yr.x, yr.y, yr.z, yr.w};
@@ -180,7 +194,7 @@ __global__ __launch_bounds__(64) void k_contract_fp32(ContractArgs a)
         dr[j] += (double)cr[j];
         di[j] += (double)ci[j];
     }
-    double *dst = a.partial + (((size_t)sl * 5 + mu) * (a.n_max + 1) + n) * a.B * a.B * 2;
+    double *dst = a.partial + ((((size_t)pair * a.S + sl) * 5 + mu) * (a.n_max + 1) + n) * a.B * a.B * 2;
     store_tile(dst, a.B, lane, dr, di);
 }
 
@@ -206,21 +220,23 @@ __global__ __launch_bounds__(64) void k_contract_split(ContractArgs a)
     const int mn = blockIdx.x + a.mu0 * (a.n_max + 1);
     const int mu = mn / (a.n_max + 1), n = mn % (a.n_max + 1);
     const int sl = blockIdx.y;
+    const int pair = blockIdx.z;
+    const float *px, *py;
+    pair_planes(a, pair, px, py);
     const int i_begin = sl * a.slice;
     const int i_end = min(i_begin + a.slice, a.n_c);
     const Operands o = operands(mu, n, a.n_max);
     const int b = lane & 31, kq = lane >> 5;
 
-    // power-of-two row scales (FP16 only): X row b1 by 2^-ex, Y row b2 by 2^-ey
+    // power-of-two row scales (FP16 only): X row b1 by sx, Y row b2 by sy
+    const size_t half = (size_t)5 * (a.n_max + 1) * a.B;
+    const float *scale = a.scale ? a.scale + (size_t)pair * 2 * half : nullptr;
     float sx = 1.0f, sy = 1.0f;
-    double unscale = 1.0;
-    if (FP16 && a.scale) {
-        const int nb = a.B;
-        const size_t base = ((size_t)mu * (a.n_max + 1) + n) * nb;
-        const size_t half = (size_t)5 * (a.n_max + 1) * nb;
-        if (b < nb) {
-            sx = a.scale[base + b];
-            sy = a.scale[half + base + b];
+    if (FP16 && scale) {
+        const size_t base = ((size_t)mu * (a.n_max + 1) + n) * a.B;
+        if (b < a.B) {
+            sx = scale[base + b];
+            sy = scale[half + base + b];
         }
     }
 
@@ -234,10 +250,10 @@ __global__ __launch_bounds__(64) void k_contract_split(ContractArgs a)
         float xa[8], xb[8], ya[8], yb[8];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const float4 xr = load4(a.px, o.xr, ib + 4 * h, b, a.K, a.B, i_end);
-            const float4 xi = load4(a.px, o.xi, ib + 4 * h, b, a.K, a.B, i_end);
-            const float4 yr = load4(a.py, o.yr, ib + 4 * h, b, a.K, a.B, i_end);
-            const float4 yi = load4(a.py, o.yi, ib + 4 * h, b, a.K, a.B, i_end);
+            const float4 xr = load4(px, o.xr, ib + 4 * h, b, a.K, a.B, i_end);
+            const float4 xi = load4(px, o.xi, ib + 4 * h, b, a.K, a.B, i_end);
+            const float4 yr = load4(py, o.yr, ib + 4 * h, b, a.K, a.B, i_end);
+            const float4 yi = load4(py, o.yi, ib + 4 * h, b, a.K, a.B, i_end);
             const float xr4[4] = {xr.x, xr.y, xr.z, xr.w}, xi4[4] = {xi.x, xi.y, xi.z, xi.w};
             const float yr4[4] = {yr.x, yr.y, yr.z, yr.w}, yi4[4] = {yi.x, yi.y, yi.z, yi.w};
 #pragma unroll
@@ -309,17 +325,16 @@ __global__ __launch_bounds__(64) void k_contract_split(ContractArgs a)
         dr[j] += (double)cr[j];
         di[j] += (double)ci[j];
     }
-    // undo the row scales: entry (row, col) carries 2^-(ex(row) + ey(col))
-    double *dst = a.partial + (((size_t)sl * 5 + mu) * (a.n_max + 1) + n) * a.B * a.B * 2;
-    if (FP16 && a.scale) {
+    // undo the row scales: entry (row, col) carries sx(row) sy(col)
+    double *dst = a.partial + ((((size_t)pair * a.S + sl) * 5 + mu) * (a.n_max + 1) + n) * a.B * a.B * 2;
+    if (FP16 && scale) {
         const size_t base = ((size_t)mu * (a.n_max + 1) + n) * a.B;
-        const size_t half = (size_t)5 * (a.n_max + 1) * a.B;
         const int col = lane & 31;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int row = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
             if (row < a.B && col < a.B) {
-                const double f = 1.0 / ((double)a.scale[base + row] * (double)a.scale[half + base + col]);
+                const double f = 1.0 / ((double)scale[base + row] * (double)scale[half + base + col]);
                 double2 v;
                 v.x = dr[j] * f;
                 v.y = di[j] * f;
@@ -329,21 +344,24 @@ __global__ __launch_bounds__(64) void k_contract_split(ContractArgs a)
     } else {
         store_tile(dst, a.B, lane, dr, di);
     }
-    (void)unscale;
 }
 
 // Row scales for FP16x3: for every (mu, n) and bin, the power of two that
 // brings max_i |alpha_i X(i, b)| (resp. max |Y(i, b)|) to [2^11, 2^12).
-__global__ __launch_bounds__(256) void k_fp16_scales(ContractArgs a, float *scale)
+__global__ __launch_bounds__(256) void k_fp16_scales(ContractArgs a, float *scale_all)
 {
     const int mn = blockIdx.x;
     const int mu = mn / (a.n_max + 1), n = mn % (a.n_max + 1);
     const int b = blockIdx.y;
-    const int side = blockIdx.z;  // 0: X (with alpha), 1: Y
+    const int side = blockIdx.z & 1;  // 0: X (with alpha), 1: Y
+    const int pair = blockIdx.z >> 1;
+    const float *px, *py;
+    pair_planes(a, pair, px, py);
+    float *scale = scale_all + (size_t)pair * 2 * 5 * (a.n_max + 1) * a.B;
     const Operands o = operands(mu, n, a.n_max);
     float m = 0.0f;
     for (int i = threadIdx.x; i < a.n_c; i += blockDim.x) {
-        const float *pl = side ? a.py : a.px;
+        const float *pl = side ? py : px;
         const int pr = side ? o.yr : o.xr;
         const float re = pl[chunk_offset(pr, i, b, a.K, a.B)];
         const float im = pl[chunk_offset(pr + 1, i, b, a.K, a.B)];
@@ -374,10 +392,12 @@ __global__ __launch_bounds__(256) void k_fp16_scales(ContractArgs a, float *scal
 }
 
 // Diagonal (j = k) sums E_mu(b) = sum_i alpha_i D_mu(i, b) in FP64.
-__global__ __launch_bounds__(256) void k_diag(const float *planes, const float4 *ccw, int n_c,
-                                              int K, int B, int pD, double *E)
+__global__ __launch_bounds__(256) void k_diag(const float *planes0, size_t zstride, const float4 *ccw,
+                                              int n_c, int K, int B, int pD, double *E0)
 {
     const int mu = blockIdx.x, b = blockIdx.y;
+    const float *planes = planes0 + (size_t)blockIdx.z * zstride;
+    double *E = E0 + (size_t)blockIdx.z * 10 * B;
     double sr = 0.0, si = 0.0;
     for (int i = threadIdx.x; i < n_c; i += blockDim.x) {
         float ar, ai;
@@ -411,24 +431,29 @@ __global__ __launch_bounds__(256) void k_diag(const float *planes, const float4 
     }
 }
 
-// out[mu][n][b1][b2] += sum_s partial[s][...] - [b1 == b2] E_mu(b1)
-__global__ void k_reduce(const double *partial, int S, int n_max, int B, const double *E, int jk,
-                         double *out)
+// out[pair][mu][n][b1][b2] += sum_s partial[pair][s][...] - [b1 == b2][Z2 == Z3] E_{Z2,mu}(b1)
+__global__ void k_reduce(const double *partial, int S, int n_max, int B, int n_z, const double *E,
+                         int jk, double *out)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t per = (int64_t)5 * (n_max + 1) * B * B;
-    if (t >= per) return;
-    const int b2 = (int)(t % B);
-    const int b1 = (int)((t / B) % B);
-    const int mu = (int)(t / ((int64_t)(n_max + 1) * B * B));
+    if (t >= per * n_z * n_z) return;
+    const int pair = (int)(t / per);
+    const int64_t e = t % per;
+    const int b2 = (int)(e % B);
+    const int b1 = (int)((e / B) % B);
+    const int mu = (int)(e / ((int64_t)(n_max + 1) * B * B));
+    const double *p = partial + 2 * ((int64_t)pair * S * per + e);
     double re = 0.0, im = 0.0;
     for (int s = 0; s < S; ++s) {
-        re += partial[2 * (s * per + t)];
-        im += partial[2 * (s * per + t) + 1];
+        re += p[2 * s * per];
+        im += p[2 * s * per + 1];
     }
-    if (jk && b1 == b2) {
-        re -= E[2 * (mu * B + b1)];
-        im -= E[2 * (mu * B + b1) + 1];
+    const int z2 = pair / n_z, z3 = pair % n_z;
+    if (jk && z2 == z3 && b1 == b2) {
+        const double *Ez = E + (size_t)z2 * 10 * B;
+        re -= Ez[2 * (mu * B + b1)];
+        im -= Ez[2 * (mu * B + b1) + 1];
     }
     out[2 * t] += re;
     out[2 * t + 1] += im;
@@ -450,56 +475,78 @@ int zero_doubles(double *p, size_t n, hipStream_t s)
     return T3_OK;
 }
 
+// Centres per stage-2 slice: a function of the chunk capacity only, so that
+// every chunk of a call fits the buffers reserved up front.
+int contract_slice(const ChunkLayout &L, int n_z)
+{
+    const int nmn = 5 * (L.n_max + 1);
+    int slice = 512;
+    while (slice > 64 && (int64_t)nmn * n_z * n_z * ((L.K + slice - 1) / slice) < 2048) slice >>= 1;
+    return slice;
+}
+
+int reserve_contract(t3_plan *plan, const ChunkLayout &L, int n_z)
+{
+    const int pairs = n_z * n_z;
+    const int S = (L.K + contract_slice(L, n_z) - 1) / contract_slice(L, n_z);
+    const size_t per = (size_t)5 * (L.n_max + 1) * L.B * L.B;
+    T3_TRY(plan->partial.reserve(sizeof(double) * 2 * per * (size_t)S * pairs));
+    T3_TRY(plan->diag.reserve(sizeof(double) * 2 * 5 * (size_t)L.B * n_z));
+    if (plan->precision == T3_PREC_FP16X3)
+        T3_TRY(plan->scales.reserve(sizeof(float) * 2 * 5 * (size_t)(L.n_max + 1) * L.B * pairs));
+    return T3_OK;
+}
+
 int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, const ChunkLayout &L,
-                   const float *planes_x, const float *planes_y, bool jk, double *ups_out,
-                   hipStream_t s)
+                   const float *planes, size_t zstride, int n_z, bool jk, double *ups_out, hipStream_t s)
 {
     if (n_c <= 0) return T3_OK;
     const int nmn = 5 * (L.n_max + 1);
-    // slice so that the grid has a few thousand wavefronts
-    int slice = 512;
-    while (slice > 64 && (int64_t)nmn * ((n_c + slice - 1) / slice) < 2048) slice >>= 1;
+    const int pairs = n_z * n_z;
+    const int slice = contract_slice(L, n_z);
     const int S = (n_c + slice - 1) / slice;
     const size_t per = (size_t)nmn * L.B * L.B;
-    T3_TRY(plan->partial.reserve(sizeof(double) * 2 * per * (size_t)S));
-    T3_TRY(plan->diag.reserve(sizeof(double) * 2 * 5 * (size_t)L.B));
+    T3_TRY(reserve_contract(plan, L, n_z));  // no-op when reserved before a capture
 
     ContractArgs a{};
-    a.px = planes_x;
-    a.py = planes_y;
+    a.planes = planes;
+    a.zstride = zstride;
     a.ccw = cs.cw.as<float4>() + c0;
     a.scale = nullptr;
     a.n_c = n_c;
     a.K = L.K;
     a.B = L.B;
     a.n_max = L.n_max;
+    a.n_z = n_z;
     a.slice = slice;
+    a.S = S;
+    a.mu0 = 0;
     a.partial = plan->partial.as<double>();
     if (plan->precision == T3_PREC_FP32) {
-        hipLaunchKernelGGL(k_contract_fp32, dim3(nmn, S), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_contract_fp32, dim3(nmn, S, pairs), dim3(64), 0, s, a);
     } else if (plan->precision == T3_PREC_BF16X3) {
         const int nu = 4 * (L.n_max + 1);
-        hipLaunchKernelGGL(k_contract_split<false>, dim3(nu, S), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_contract_split<false>, dim3(nu, S, pairs), dim3(64), 0, s, a);
         T3_HIP_CHECK(hipGetLastError());
         ContractArgs an = a;
         an.mu0 = 4;
-        hipLaunchKernelGGL(k_contract_fp32, dim3(nmn - nu, S), dim3(64), 0, s, an);
+        hipLaunchKernelGGL(k_contract_fp32, dim3(nmn - nu, S, pairs), dim3(64), 0, s, an);
     } else {
-        T3_TRY(plan->scales.reserve(sizeof(float) * 2 * per / L.B));
-        hipLaunchKernelGGL(k_fp16_scales, dim3(nmn, L.B, 2), dim3(256), 0, s, a,
+        hipLaunchKernelGGL(k_fp16_scales, dim3(nmn, L.B, 2 * pairs), dim3(256), 0, s, a,
                            plan->scales.as<float>());
         T3_HIP_CHECK(hipGetLastError());
         a.scale = plan->scales.as<float>();
-        hipLaunchKernelGGL(k_contract_split<true>, dim3(nmn, S), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_contract_split<true>, dim3(nmn, S, pairs), dim3(64), 0, s, a);
     }
     T3_HIP_CHECK(hipGetLastError());
     if (jk) {
-        hipLaunchKernelGGL(k_diag, dim3(5, L.B), dim3(256), 0, s, planes_x, a.ccw, n_c, L.K, L.B,
-                           L.plane_D(0), plan->diag.as<double>());
+        hipLaunchKernelGGL(k_diag, dim3(5, L.B, n_z), dim3(256), 0, s, planes, zstride, a.ccw, n_c, L.K,
+                           L.B, L.plane_D(0), plan->diag.as<double>());
         T3_HIP_CHECK(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s,
-                       (const double *)plan->partial.as<double>(), S, L.n_max, L.B,
+    const size_t tot = per * pairs;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       (const double *)plan->partial.as<double>(), S, L.n_max, L.B, n_z,
                        (const double *)plan->diag.as<double>(), jk ? 1 : 0, ups_out);
     T3_HIP_CHECK(hipGetLastError());
     return T3_OK;

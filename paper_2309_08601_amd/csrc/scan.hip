@@ -31,19 +31,26 @@ namespace {
 constexpr int kWaves = 4;       // wavefronts (centres) per workgroup
 constexpr int kAnchor = 8;      // FP64 anchor stride of the power recurrence
 constexpr int kMaxBins = 64;
+constexpr int kMaxZ = 8;        // neighbour catalogs per launch (tomographic bins)
 constexpr int kFlush = 64;      // batches of 64 neighbours per FP32 run before FP64 promotion
 
+// One launch covers the centres of a chunk against n_z neighbour catalogs
+// (n_z = 1 outside tomography).  Task t in [0, n_z n_c) is centre t % n_c
+// against catalog order[t / n_c] (catalogs ordered densest first).
 struct ScanArgs {
-    SweepArgs sw;           // cell-sorted neighbour catalog
+    SweepArgs sw[kMaxZ];    // cell-sorted neighbour catalogs
+    float *out[kMaxZ];      // chunk planes per neighbour catalog
+    int order[kMaxZ];
+    int n_z;
     const int2 *cpos;       // centre positions (chunk-relative)
-    const float4 *ccw;      // centre factors (unused here, kept for symmetry)
     int n_c;                // centres in the chunk
     int n_bins;
     int n_max;
     int K;                  // chunk capacity (plane layout)
-    float *out;             // chunk planes
     const short *dest;      // slot -> plane (or -1) for this pass
     unsigned long long *npairs;
+    unsigned *queue;        // persistent mode: task counter (zeroed before launch); else null
+    int grab;               // persistent mode: tasks taken per counter increment
     double e2[kMaxBins + 1];
 };
 
@@ -178,30 +185,15 @@ __device__ __forceinline__ void flush(float (&acc)[V], double (&accd)[P], int la
     for (int k = 0; k < S::V; ++k) acc[k] = 0.0f;
 }
 
+// Harmonic sums of one centre against one neighbour catalog, every bin.
 template <int GA, int GB, int WA, int WB, bool EXTRA>
-// Two workgroups per CU (2 wavefronts per SIMD): measured faster than one
-// wavefront per SIMD without spills, although the largest variants then
-// spill some registers.
-__global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
+__device__ __forceinline__ unsigned long long scan_task(const ScanArgs &a, int z, int ci, int lane,
+                                                        const SweepLDS &lds)
 {
     using S = PassShape<GA, GB, WA, WB, EXTRA>;
-    __shared__ int4 q_xyc[kWaves][kRing];
-    __shared__ int2 q_wi[kWaves][kRing];
-    __shared__ int2 spans[kWaves][2 * kRowsPerBlock + 1];
-
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    // XCD-aware order: consecutive centres stay on one XCD (round-robin dispatch)
-    const int nwg = gridDim.x;  // multiple of 8
-    const int per = nwg >> 3;
-    const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    const int ci = wg * kWaves + wv;
-    if (ci >= a.n_c) return;  // whole wavefront leaves together
-
     const int2 cp = a.cpos[ci];
-    const SweepLDS lds{q_xyc[wv], q_wi[wv], spans[wv]};
+    float *out = a.out[z];
     unsigned long long pairs = 0;
-
     for (int b = 0; b < a.n_bins; ++b) {
         float acc[S::V];
 #pragma unroll
@@ -212,7 +204,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
         int batches = 0;  // wave-uniform: batches since the last FP64 promotion
 
         pairs += (unsigned long long)sweep_annulus(
-            a.sw, cp, a.e2[b], a.e2[b + 1], lane, lds,
+            a.sw[z], cp, a.e2[b], a.e2[b + 1], lane, lds,
             [&](const int4 &e, float ew, int, bool) {
                 accumulate<GA, GB, WA, WB, EXTRA>(acc, e.x, e.y, __int_as_float(e.z),
                                                   __int_as_float(e.w), ew);
@@ -227,23 +219,82 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
         for (int k = 0; k < S::P; ++k) {
             const int slot = S::P * lane + k;
             const int pl = a.dest[slot];
-            if (pl >= 0) a.out[chunk_offset(pl, ci, b, a.K, a.n_bins)] = (float)accd[k];
+            if (pl >= 0) out[chunk_offset(pl, ci, b, a.K, a.n_bins)] = (float)accd[k];
         }
+    }
+    return pairs;
+}
+
+// Two workgroups per CU (2 wavefronts per SIMD): measured faster than one
+// wavefront per SIMD without spills, although the largest variants then
+// spill some registers.
+// GENERAL = false: one catalog, one wavefront per centre (the
+// non-tomographic fast path; catalog 0 is a compile-time choice, which keeps
+// register pressure down).  GENERAL = true: n_z catalogs and either launch mode.
+template <int GA, int GB, int WA, int WB, bool EXTRA, bool GENERAL>
+__global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
+{
+    __shared__ int4 q_xyc[kWaves][kRing];
+    __shared__ int2 q_wi[kWaves][kRing];
+    __shared__ int2 spans[kWaves][2 * kRowsPerBlock + 1];
+
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const SweepLDS lds{q_xyc[wv], q_wi[wv], spans[wv]};
+    unsigned long long pairs = 0;
+    if constexpr (!GENERAL) {
+        const int nwg = gridDim.x;  // multiple of 8
+        const int per = nwg >> 3;
+        const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+        const int ci = wg * kWaves + wv;
+        if (ci >= a.n_c) return;  // whole wavefront leaves together
+        pairs = scan_task<GA, GB, WA, WB, EXTRA>(a, 0, ci, lane, lds);
+        if (lane == 0 && a.npairs) atomicAdd(a.npairs, pairs);
+        return;
+    }
+    const int total = a.n_z * a.n_c;
+    int base = 0, end = 0;
+    if (!a.queue) {
+        // one wavefront per task; XCD-aware order: consecutive tasks stay on
+        // one XCD (workgroups are dispatched round-robin over the 8 XCDs)
+        const int nwg = gridDim.x;  // multiple of 8
+        const int per = nwg >> 3;
+        const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+        base = wg * kWaves + wv;
+        end = base + 1 < total ? base + 1 : total;
+    }
+    // persistent mode: take `grab` consecutive tasks per counter increment
+    // until the counter passes the task count (every wavefront reaches that exit)
+    for (;;) {
+        if (a.queue) {
+            int b0 = 0;
+            if (lane == 0) b0 = (int)atomicAdd(a.queue, (unsigned)a.grab);
+            base = __builtin_amdgcn_readfirstlane(b0);
+            end = base + a.grab < total ? base + a.grab : total;
+        }
+        if (base >= total) break;  // wave-uniform
+        for (int t = base; t < end; ++t)
+            pairs += scan_task<GA, GB, WA, WB, EXTRA>(a, a.order[t / a.n_c], t % a.n_c, lane, lds);
+        if (!a.queue) break;
     }
     if (lane == 0 && a.npairs) atomicAdd(a.npairs, pairs);
 }
+
+__global__ void k_zero_u32(unsigned *p) { *p = 0u; }
 
 // --------------------------------------------------------------- host side
 struct PassDesc {
     int ga, gb, wa, wb;
     bool extra;
-    void (*kernel)(ScanArgs);
+    void (*kernel)(ScanArgs);          // single catalog, one wavefront per centre
+    void (*kernel_general)(ScanArgs);  // n_z catalogs, either launch mode
 };
 
 template <int GA, int GB, int WA, int WB, bool EXTRA>
 PassDesc make_pass()
 {
-    return PassDesc{GA, GB, WA, WB, EXTRA, k_scan<GA, GB, WA, WB, EXTRA>};
+    return PassDesc{GA, GB, WA, WB, EXTRA, k_scan<GA, GB, WA, WB, EXTRA, false>,
+                    k_scan<GA, GB, WA, WB, EXTRA, true>};
 }
 
 // Variant table: a single pass for n_max up to the capacity C (orders
@@ -342,31 +393,58 @@ int scan_prepare(t3_plan *plan)
     return T3_OK;
 }
 
-int scan_chunk(t3_plan *plan, const SortedCatalog &sc, const CentreSet &cs, int64_t c0, int n_c,
-               const ChunkLayout &L, float *planes, unsigned long long *npairs, hipStream_t s)
+int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order, int n_z,
+               const CentreSet &cs, int64_t c0, int n_c, const ChunkLayout &L, float *planes,
+               size_t zstride, unsigned long long *npairs, int mode, hipStream_t s)
 {
     if (n_c <= 0) return T3_OK;
+    if (n_z < 1 || n_z > kMaxZ) return fail(T3_ERANGE, "scan: bad catalog count");
     if (plan->scan_var < 0) T3_TRY(scan_prepare(plan));
     const Variant &var = variants()[plan->scan_var];
     ScanArgs a{};
-    a.sw.npos = sc.pos.as<int2>();
-    a.sw.ncw = sc.cw.as<float4>();
-    a.sw.cell_start = sc.cell_start.as<int>();
-    a.sw.g = sc.grid;
+    for (int z = 0; z < n_z; ++z) {
+        const SortedCatalog &sc = *cats[z];
+        a.sw[z].npos = sc.pos.as<int2>();
+        a.sw[z].ncw = sc.cw.as<float4>();
+        a.sw[z].cell_start = sc.cell_start.as<int>();
+        a.sw[z].g = sc.grid;
+        a.out[z] = planes + (size_t)z * zstride;
+        a.order[z] = order ? order[z] : z;
+    }
+    a.n_z = n_z;
     a.cpos = cs.pos.as<int2>() + c0;
-    a.ccw = cs.cw.as<float4>() + c0;
     a.n_c = n_c;
     a.n_bins = L.B;
     a.n_max = L.n_max;
     a.K = L.K;
-    a.out = planes;
     for (int b = 0; b <= L.B; ++b) a.e2[b] = plan->e2[b];
-    int nwg = (n_c + kWaves - 1) / kWaves;
-    nwg = (nwg + 7) & ~7;
+    const int total = n_z * n_c;
+    int nwg;
+    if (mode == 1) {
+        // persistent grid: two workgroups per CU
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        nwg = 2 * cus;
+        T3_TRY(plan->queue.reserve(sizeof(unsigned) * 4));
+        a.queue = plan->queue.as<unsigned>();
+        a.grab = 4;
+    } else {
+        nwg = (total + kWaves - 1) / kWaves;
+        nwg = (nwg + 7) & ~7;
+        a.queue = nullptr;
+        a.grab = 0;
+    }
+    const bool general = n_z > 1 || mode == 1;
     for (int p = 0; p < var.npass; ++p) {
         a.dest = plan->dest.as<short>() + plan->scan_dest_off[p];
         a.npairs = p == 0 ? npairs : nullptr;  // count pairs once
-        hipLaunchKernelGGL(var.pass[p].kernel, dim3((unsigned)nwg), dim3(64 * kWaves), 0, s, a);
+        if (a.queue) {
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, a.queue);
+            T3_HIP_CHECK(hipGetLastError());
+        }
+        hipLaunchKernelGGL(general ? var.pass[p].kernel_general : var.pass[p].kernel, dim3((unsigned)nwg),
+                           dim3(64 * kWaves), 0, s, a);
         T3_HIP_CHECK(hipGetLastError());
     }
     return T3_OK;

@@ -110,7 +110,11 @@ struct t3_plan {
     int device = 0;
 
     t3::SortedCatalog cats[8];
-    t3::CentreSet centres;
+    t3::CentreSet centres;      // centres of t3_harmonics / t3_backward
+    t3::CentreSet csets[8];     // centres per tomographic bin of a forward call
+    int scan_mode = 0;          // 0: one wavefront per task, 1: persistent work queue
+    hipStream_t cap_stream = nullptr;     // graph capture stream (default priority)
+    hipGraphExec_t graph_exec = nullptr;  // last captured forward schedule
     t3::DevBuf chunk;     // stage-1 planes
     t3::DevBuf partial;   // stage-2 FP64 partial tiles
     t3::DevBuf diag;      // FP64 j = k sums per chunk
@@ -118,6 +122,9 @@ struct t3_plan {
     t3::DevBuf dest;      // int16 destination tables of the stage-1 passes
     t3::DevBuf scales;    // fp16 row scales
     t3::DevBuf counter;   // uint64 pair counter
+    t3::DevBuf queue;     // persistent-scan work counter
+    t3::DevBuf tune_idx;  // autotuner centre sample
+    t3::DevBuf tune_out;  // autotuner output
     t3::DevBuf misc;      // adjoint scratch
     t3::DevBuf misc2;
     int scan_var = -1;          // stage-1 variant index (see scan.hip)
@@ -142,11 +149,19 @@ int gather_sorted_centres(t3_plan *plan, const SortedCatalog &sc, CentreSet &cs,
 int check_flag(t3_plan *plan, hipStream_t s, const char *what);
 
 int scan_prepare(t3_plan *plan);
-int scan_chunk(t3_plan *plan, const SortedCatalog &sc, const CentreSet &cs, int64_t c0, int n_c,
-               const ChunkLayout &L, float *planes, unsigned long long *npairs, hipStream_t s);
+// Stage 1 for centres [c0, c0 + n_c) of cs against n_z neighbour catalogs
+// (planes of catalog z at planes + z * zstride).  mode 0: one wavefront per
+// (centre, catalog); mode 1: persistent grid with a work counter.
+int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order, int n_z,
+               const CentreSet &cs, int64_t c0, int n_c, const ChunkLayout &L, float *planes,
+               size_t zstride, unsigned long long *npairs, int mode, hipStream_t s);
 int zero_doubles(double *p, size_t n, hipStream_t s);
+int reserve_contract(t3_plan *plan, const ChunkLayout &L, int n_z);
+int contract_slice(const ChunkLayout &L, int n_z);
+// Stage 2 for every ordered pair (Z2, Z3) of the n_z plane sets
+// (ups_out[pair] += ..., pair = Z2 n_z + Z3).
 int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, const ChunkLayout &L,
-                   const float *planes_x, const float *planes_y, bool jk, double *ups_out,
+                   const float *planes, size_t zstride, int n_z, bool jk, double *ups_out,
                    hipStream_t s);
 int normalise_resum(t3_plan *plan, const double *ups, int n_sets, int n_z, int n_phi,
                     double *gamma_n, double *gamma_phi, hipStream_t s);

@@ -26,6 +26,7 @@ T3_ELATTICE = -5
 PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
 T3_FLAG_KEEP_JK = 1
 T3_FLAG_TIMING = 2
+T3_FLAG_NO_GRAPH = 4
 
 
 class t3_params(ctypes.Structure):
@@ -33,7 +34,8 @@ class t3_params(ctypes.Structure):
                 ("n_max", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("lattice_unit", ctypes.c_double), ("box_lo_x", ctypes.c_int32),
                 ("box_lo_y", ctypes.c_int32), ("box_size", ctypes.c_int64),
-                ("cell_arcmin", ctypes.c_double), ("chunk_centres", ctypes.c_int32)]
+                ("cell_arcmin", ctypes.c_double), ("chunk_centres", ctypes.c_int32),
+                ("scan_mode", ctypes.c_int32)]
 
 
 class t3_catalog(ctypes.Structure):
@@ -48,7 +50,7 @@ class T3Error(RuntimeError):
 
 
 EXPORTED = ["t3_plan_create", "t3_plan_destroy", "t3_forward", "t3_forward_tomo", "t3_harmonics",
-            "t3_normalise_resum", "t3_normalise_backward", "t3_backward", "t3_stage_times",
+            "t3_normalise_resum", "t3_normalise_backward", "t3_backward", "t3_autotune", "t3_stage_times",
             "t3_error_string",
             "t3_last_error_message", "t3_version"]
 
@@ -76,6 +78,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.t3_normalise_backward.restype = ctypes.c_int
     lib.t3_backward.argtypes = [vp, P(t3_catalog), vp, vp, vp, vp, vp]
     lib.t3_backward.restype = ctypes.c_int
+    lib.t3_autotune.argtypes = [vp, P(t3_catalog), ctypes.c_int32, ctypes.c_int64, P(ctypes.c_double), vp]
+    lib.t3_autotune.restype = ctypes.c_int
     lib.t3_stage_times.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
     lib.t3_stage_times.restype = ctypes.c_int
     lib.t3_error_string.argtypes = [ctypes.c_int]
@@ -130,16 +134,18 @@ class Plan:
 
     def __init__(self, edges: Sequence[float], n_max: int, box_lo=(0, 0), box_size: int = 1 << 30,
                  precision: str = "fp32", keep_jk: bool = False, lattice_unit: float = 0.0,
-                 cell_arcmin: float = 0.0, chunk_centres: int = 0, timing: bool = False):
+                 cell_arcmin: float = 0.0, chunk_centres: int = 0, timing: bool = False,
+                 graph: bool = True, scan_mode: int = 0):
         self.edges = np.ascontiguousarray(edges, dtype=np.float64)
         self.B = len(self.edges) - 1
         self.n_max = int(n_max)
         p = t3_params(self.B, self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.n_max,
                       PRECISIONS[precision],
-                      (T3_FLAG_KEEP_JK if keep_jk else 0) | (T3_FLAG_TIMING if timing else 0),
+                      (T3_FLAG_KEEP_JK if keep_jk else 0) | (T3_FLAG_TIMING if timing else 0)
+                      | (0 if graph else T3_FLAG_NO_GRAPH),
                       float(lattice_unit),
                       int(box_lo[0]), int(box_lo[1]), int(box_size), float(cell_arcmin),
-                      int(chunk_centres))
+                      int(chunk_centres), int(scan_mode))
         h = ctypes.c_void_p()
         _check(_lib.t3_plan_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h
@@ -236,6 +242,14 @@ class Plan:
         out = torch.empty_like(u)
         _check(_lib.t3_normalise_backward(self._h, _ptr(u), sets, _ptr(g), _ptr(out), _stream()))
         return out
+
+    def autotune(self, cats, sample_per_bin: int = 20000) -> float:
+        """Pick cell size and stage-1 launch mode by timing a centre sample."""
+        cats = cats if isinstance(cats, (list, tuple)) else [cats]
+        arr = (t3_catalog * len(cats))(*[c.c_struct() for c in cats])
+        best = ctypes.c_double(0.0)
+        _check(_lib.t3_autotune(self._h, arr, len(cats), int(sample_per_bin), ctypes.byref(best), _stream()))
+        return float(best.value)
 
     def stage_times(self):
         """(ms[4], launches[4]) of the last forward call (timing plans only):
