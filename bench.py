@@ -31,6 +31,35 @@ PEAK_FP32_MATRIX = 157.3e12    # MI355X FP32 MFMA
 PEAK_BF16_MATRIX = 2.5e15      # MI355X dense BF16 MFMA
 
 
+def kernel_source_hash() -> str:
+    """SHA-256 of the stage-1 kernel's device sources (the annulus sweep and
+    the scan kernels above the host-side section of scan.hip)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2309_08601_amd", "csrc")
+    h = hashlib.sha256()
+    h.update(open(os.path.join(csrc, "sweep.h"), "rb").read())
+    scan = open(os.path.join(csrc, "scan.hip"), "rb").read()
+    h.update(scan.split(b"// --------------------------------------------------------------- host side")[0])
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per stage-1 launch from the committed counter summary, or
+    None when the kernel sources changed since those counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_scan_field_1m.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    sha = traffic = None
+    for line in text.splitlines():
+        if line.startswith("kernel-source-sha256:"):
+            sha = line.split(":", 1)[1].strip()
+        if line.startswith("traffic-bytes-per-launch:"):
+            traffic = float(line.split(":", 1)[1].strip())
+    return traffic if sha == kernel_source_hash() else None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -51,6 +80,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many forward passes (for profilers), no JSON")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the tomography and gradient workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design "
@@ -164,10 +195,14 @@ def main():
         "split_bf16": {"ms_per_step": 1e3 * tb, "value": pairs_step / tb, "gemm_tflops": bf_gemm_tflops,
                        "stage2_ms": bf_ms[2] / nb},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": profiled_traffic(),
                      "kernel": "k_scan (stage 1)",
                      "flops_per_pair": flops_pair, "launches_per_step": int(launches[1] // K)},
     }
+
+    if not args.no_extras:
+        out["tomography"] = bench_tomo(t3, torch, dev)
+        out["gradient"] = bench_grad(t3, torch, dev)
 
     if not args.no_cpu:
         import oracle
@@ -207,6 +242,78 @@ def main():
         out["errors_vs_oracle"] = errs
         out["errors_vs_oracle"]["sample"] = f"{n_s} centres"
     print(json.dumps(out), flush=True)
+
+
+def bench_tomo(t3, torch, dev):
+    """5 source bins (0.3/0.6/0.8/0.7/0.4 M galaxies), all 125 ordered
+    triples, 20 bins 0.5'-100', n_max 30, FP32: one forward over every centre
+    of every bin, chunk schedule as one HIP graph, autotuned launch."""
+    from paper_2309_08601_amd.synth import LATTICE_UNIT, WORKLOADS, make_catalogs
+    wl = WORKLOADS["tomo_5bin"]
+    cats = make_catalogs(wl)
+    dcs = [t3.DeviceCatalog.from_catalog(c, device=dev) for c in cats]
+    box = int(round(wl.side / LATTICE_UNIT))
+    plan = t3.Plan(wl.edges(), wl.n_max, box_size=box)
+    t0 = time.perf_counter()
+    tune_ms = plan.autotune(dcs, sample_per_bin=4000)
+    t_tune = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, npairs = plan.forward_tomo(dcs)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    # eager run with HIP events for the stage split
+    tp = t3.Plan(wl.edges(), wl.n_max, box_size=box, timing=True, cell_arcmin=0.0)
+    tp.autotune(dcs, sample_per_bin=4000)  # cached choice, no timing
+    _, np2 = tp.forward_tomo(dcs)
+    ms, nl = tp.stage_times()
+    n_c = sum(c.n for c in cats)
+    B, nm, nz = wl.n_bins, wl.n_max, len(cats)
+    gemm_flops = 8.0 * 5 * (nm + 1) * B * B * nz * nz * n_c
+    log(f"[bench] tomography: {npairs} pairs in {t_graph:.2f} s (graph), stages ms {[round(v, 1) for v in ms]}")
+    return {"workload": f"tomo_5bin: 5 bins {'/'.join(str(c.n) for c in cats)} galaxies in 600' x 600', "
+                        f"all 125 ordered triples, 20 log bins 0.5'-100', n_max=30, FP32",
+            "pairs": npairs, "seconds": t_graph, "value": npairs / t_graph, "unit": "galaxy-pairs/s",
+            "gemm_tflops": gemm_flops / (ms[2] / 1e3) / 1e12, "stage_ms": {"cells": ms[0], "stage1": ms[1],
+                                                                             "stage2": ms[2]},
+            "autotune_seconds": t_tune, "autotune_best_sample_ms": tune_ms}
+
+
+def bench_grad(t3, torch, dev):
+    """500k galaxies in 7 deg x 7 deg, 15 bins 1'-60', n_max 20: forward and
+    hand-written backward of the chi^2 loss of Gamma_n against a second-seed
+    target."""
+    from paper_2309_08601_amd.synth import LATTICE_UNIT, WORKLOADS, make_catalogs
+    wl = WORKLOADS["grad_500k"]
+    cat = make_catalogs(wl)[0]
+    tgt = make_catalogs(wl, seed_offset=100)[0]
+    box = int(round(wl.side / LATTICE_UNIT))
+    plan = t3.Plan(wl.edges(), wl.n_max, box_size=box)
+    T, _ = plan.normalise_resum(plan.forward(t3.DeviceCatalog.from_catalog(tgt, device=dev))[0], with_phi=False)
+    om = 1.0 / torch.clamp(torch.mean(T.real ** 2 + T.imag ** 2, dim=1, keepdim=True), min=1e-300)
+    om = om.expand_as(T.real).contiguous()
+    x = torch.from_numpy(cat.x).to(dev)
+    y = torch.from_numpy(cat.y).to(dev)
+    res = {}
+    for rep in range(2):
+        g1 = torch.from_numpy(cat.g1.copy()).to(dev).requires_grad_(True)
+        g2 = torch.from_numpy(cat.g2.copy()).to(dev).requires_grad_(True)
+        w = torch.from_numpy(cat.w.copy()).to(dev).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gam = torch.view_as_complex(t3.GammaMultipoles.apply(g1, g2, w, x, y, plan))
+        d = gam - T
+        L = torch.sum(om * (d.real ** 2 + d.imag ** 2))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res = {"forward_s": t1 - t0, "backward_s": t2 - t1}
+    log(f"[bench] gradient: forward {res['forward_s']:.3f} s, backward {res['backward_s']:.3f} s")
+    res["workload"] = ("grad_500k: 500000 galaxies in 420' x 420', 15 log bins 1'-60', n_max=20; "
+                       "L = sum omega |Gamma_n - T|^2, dL/d(g1, g2, w) of every galaxy")
+    return res
 
 
 if __name__ == "__main__":

@@ -90,8 +90,10 @@ typedef struct {
     int64_t box_size;      /* side in lattice steps, > 0, box_lo + size <= 2^31 */
     double cell_arcmin;    /* spatial-hash cell side; 0 -> automatic          */
     int32_t chunk_centres; /* centres per stage-1/stage-2 chunk; 0 -> auto    */
-    int32_t scan_mode;     /* stage-1 launch: 0 one wavefront per (centre,    */
-                           /* catalog), 1 persistent grid with a work queue   */
+    int32_t scan_mode;     /* stage-1 launch: 0 one wavefront per centre, one */
+                           /* launch per neighbour catalog; 1 one persistent  */
+                           /* launch over all (centre, catalog) tasks with a  */
+                           /* work queue                                      */
 } t3_params;
 
 typedef struct {

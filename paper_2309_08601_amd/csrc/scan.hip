@@ -10,9 +10,10 @@
 //    tests, ballot compaction into an LDS ring, 64 in-bin neighbours per
 //    batch, each lane taking one through the harmonic recurrence;
 //  * per-lane FP32 accumulators hold one bin of one centre; every 64 batches
-//    and at the end of the bin a 6-step reduce-scatter leaves each lane a few
-//    wave totals, which are added to per-lane FP64 partials; at the end of
-//    the bin those are stored into the chunk planes (layout in t3_internal.h).
+//    and at the end of the bin a 6-step reduce-scatter (permlane swaps and
+//    DPP permutations) leaves each lane a few wave totals, which are added to
+//    per-lane FP64 partials; at the end of the bin those are stored into the
+//    chunk planes (layout in t3_internal.h).
 //
 // Arithmetic per neighbour: dx, dy are exact lattice integers, r^2 is exact
 // in FP64 and is compared with the same FP64 squared edges as everywhere
@@ -145,16 +146,57 @@ __device__ __forceinline__ void accumulate(float (&acc)[V], int dx, int dy, floa
     }
 }
 
-// Wave reduction of the per-lane accumulators: S -> G conversion, then a
-// 6-step reduce-scatter (each step exchanges half of the remaining slots
-// with the partner lane), after which lane l holds the wave totals of slots
-// [P l, P l + P).  These are added to the lane's FP64 partials and the FP32
-// accumulators restart from zero.
+// Cross-lane exchange steps of the reduce-scatter.  Each step halves the
+// slots a lane holds: the lane keeps one half and receives its partner's copy
+// of that half.  Bits 5 and 4 use the gfx950 permlane swaps (the swap already
+// leaves each half on the right lanes); bits 3..0 use DPP permutations fused
+// into the add: row_ror:8 (partner l ^ 8), row_half_mirror (partner l ^ 7,
+// which differs in bit 2 and agrees on the bits already reduced), and two
+// quad permutations (l ^ 2, l ^ 1).  Lane l ends with slots [P l, P l + P).
+__device__ __forceinline__ float add_swap32(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float add_swap16(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+constexpr int kDppRowRor8 = 0x128;
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+
+template <int CTRL, int H, int N>
+__device__ __forceinline__ void dpp_step(float (&v)[N], bool hi)
+{
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const float keep = hi ? v[k + H] : v[k];
+        const float send = hi ? v[k] : v[k + H];
+        v[k] = keep + dpp<CTRL>(send);
+    }
+}
+
+// Wave reduction of the per-lane accumulators: S -> G conversion, then the
+// 6-step reduce-scatter above, after which lane l holds the wave totals of
+// slots [P l, P l + P).  These are added to the lane's FP64 partials and the
+// FP32 accumulators restart from zero.
 template <int GA, int GB, int WA, int WB, bool EXTRA, int V, int P>
 __device__ __forceinline__ void flush(float (&acc)[V], double (&accd)[P], int lane)
 {
     using S = PassShape<GA, GB, WA, WB, EXTRA>;
-    float v[S::VP];
+    constexpr int VP = S::VP;
+    float v[VP];
 #pragma unroll
     for (int k = 0; k < S::NG; ++k) {
         const float s1 = acc[4 * k], s2 = acc[4 * k + 1], s3 = acc[4 * k + 2], s4 = acc[4 * k + 3];
@@ -166,19 +208,15 @@ __device__ __forceinline__ void flush(float (&acc)[V], double (&accd)[P], int la
 #pragma unroll
     for (int k = 4 * S::NG; k < S::V; ++k) v[k] = acc[k];
 #pragma unroll
-    for (int k = S::V; k < S::VP; ++k) v[k] = 0.0f;
+    for (int k = S::V; k < VP; ++k) v[k] = 0.0f;
 #pragma unroll
-    for (int st = 0; st < 6; ++st) {
-        const int d = 32 >> st;
-        const int L = S::VP >> st;
-        const bool hi = (lane & d) != 0;
+    for (int k = 0; k < VP / 2; ++k) v[k] = add_swap32(v[k], v[k + VP / 2]);
 #pragma unroll
-        for (int k = 0; k < L / 2; ++k) {
-            const float keep = hi ? v[k + L / 2] : v[k];
-            const float send = hi ? v[k] : v[k + L / 2];
-            v[k] = keep + __shfl_xor(send, d, 64);
-        }
-    }
+    for (int k = 0; k < VP / 4; ++k) v[k] = add_swap16(v[k], v[k + VP / 4]);
+    dpp_step<kDppRowRor8, VP / 8>(v, (lane & 8) != 0);
+    dpp_step<kDppRowHalfMirror, VP / 16>(v, (lane & 4) != 0);
+    dpp_step<kDppQuadXor2, VP / 32>(v, (lane & 2) != 0);
+    dpp_step<kDppQuadXor1, VP / 64>(v, (lane & 1) != 0);
 #pragma unroll
     for (int k = 0; k < S::P; ++k) accd[k] += (double)v[k];
 #pragma unroll
@@ -228,9 +266,10 @@ __device__ __forceinline__ unsigned long long scan_task(const ScanArgs &a, int z
 // Two workgroups per CU (2 wavefronts per SIMD): measured faster than one
 // wavefront per SIMD without spills, although the largest variants then
 // spill some registers.
-// GENERAL = false: one catalog, one wavefront per centre (the
-// non-tomographic fast path; catalog 0 is a compile-time choice, which keeps
-// register pressure down).  GENERAL = true: n_z catalogs and either launch mode.
+// GENERAL = false: one catalog, one wavefront per centre (catalog 0 is a
+// compile-time choice, which keeps register pressure down; tomography issues
+// one such launch per catalog).  GENERAL = true: n_z catalogs in one
+// persistent launch with a work counter.
 template <int GA, int GB, int WA, int WB, bool EXTRA, bool GENERAL>
 __global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
 {
@@ -435,17 +474,28 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
         a.queue = nullptr;
         a.grab = 0;
     }
-    const bool general = n_z > 1 || mode == 1;
     for (int p = 0; p < var.npass; ++p) {
         a.dest = plan->dest.as<short>() + plan->scan_dest_off[p];
         a.npairs = p == 0 ? npairs : nullptr;  // count pairs once
         if (a.queue) {
+            // persistent grid over every (centre, catalog) task
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, a.queue);
             T3_HIP_CHECK(hipGetLastError());
+            hipLaunchKernelGGL(var.pass[p].kernel_general, dim3((unsigned)nwg), dim3(64 * kWaves), 0, s, a);
+            T3_HIP_CHECK(hipGetLastError());
+        } else {
+            // one launch of the single-catalog kernel per catalog, densest first
+            const int nwg1 = (((n_c + kWaves - 1) / kWaves) + 7) & ~7;
+            for (int k = 0; k < n_z; ++k) {
+                ScanArgs a1 = a;
+                const int z = a.order[k];
+                a1.sw[0] = a.sw[z];
+                a1.out[0] = a.out[z];
+                a1.n_z = 1;
+                hipLaunchKernelGGL(var.pass[p].kernel, dim3((unsigned)nwg1), dim3(64 * kWaves), 0, s, a1);
+                T3_HIP_CHECK(hipGetLastError());
+            }
         }
-        hipLaunchKernelGGL(general ? var.pass[p].kernel_general : var.pass[p].kernel, dim3((unsigned)nwg),
-                           dim3(64 * kWaves), 0, s, a);
-        T3_HIP_CHECK(hipGetLastError());
     }
     return T3_OK;
 }

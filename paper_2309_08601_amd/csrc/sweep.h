@@ -39,13 +39,19 @@ struct SweepLDS {
     int2 *span;   // [2 * kRowsPerBlock + 1] (virtual begin, first galaxy)
 };
 
+// floor(a / b) for integers |a| < 2^53, b > 0, in FP64 (cheaper than a 64-bit
+// integer division): an integral quotient is exact, and any other lies at
+// least 1/b from an integer, more than the error |a / b| 2^-53 of one
+// correctly rounded division.
 __device__ __forceinline__ long long floor_div(long long a, long long b)
 {
-    long long q = a / b;
-    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+    return (long long)floor((double)a / (double)b);
 }
 
-__device__ __forceinline__ long long ceil_div(long long a, long long b) { return -floor_div(-a, b); }
+__device__ __forceinline__ long long ceil_div(long long a, long long b)
+{
+    return (long long)ceil((double)a / (double)b);
+}
 
 __device__ __forceinline__ void wave_sync_lds()
 {

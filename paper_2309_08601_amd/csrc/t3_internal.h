@@ -151,7 +151,8 @@ int check_flag(t3_plan *plan, hipStream_t s, const char *what);
 int scan_prepare(t3_plan *plan);
 // Stage 1 for centres [c0, c0 + n_c) of cs against n_z neighbour catalogs
 // (planes of catalog z at planes + z * zstride).  mode 0: one wavefront per
-// (centre, catalog); mode 1: persistent grid with a work counter.
+// centre, one launch per catalog; mode 1: one persistent launch over every
+// (centre, catalog) task with a work counter.
 int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order, int n_z,
                const CentreSet &cs, int64_t c0, int n_c, const ChunkLayout &L, float *planes,
                size_t zstride, unsigned long long *npairs, int mode, hipStream_t s);
