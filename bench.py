@@ -157,20 +157,25 @@ def main():
     gemm_s = stage_ms[2] / K / 1e3
     gemm_tflops = gemm_flops / gemm_s / 1e12
 
-    # split-BF16 contraction: same step, timed separately
-    plan_bf = t3.Plan(edges, nm, box_lo=(0, 0), box_size=box, precision="bf16x3", timing=True)
-    step(plan_bf)
-    torch.cuda.synchronize()
-    bf_ms = np.zeros(4)
-    tb = time.perf_counter()
-    nb = max(1, K // 2)
-    for _ in range(nb):
-        _, npb = step(plan_bf)
-        bf_ms += plan_bf.stage_times()[0]
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - tb) / nb
-    bf_gemm_tflops = gemm_flops / (bf_ms[2] / nb / 1e3) / 1e12
-    log(f"[bench] bf16x3: {1e3 * tb:.1f} ms/step, stage-2 {bf_ms[2] / nb:.2f} ms")
+    # split-precision contractions: the same step, timed separately
+    split = {}
+    for prec in ("bf16x3", "bf16x6", "fp16x3"):
+        plan_s = t3.Plan(edges, nm, box_lo=(0, 0), box_size=box, precision=prec, timing=True)
+        step(plan_s)
+        torch.cuda.synchronize()
+        s_ms = np.zeros(4)
+        ts = time.perf_counter()
+        ns = max(1, K // 2)
+        for _ in range(ns):
+            step(plan_s)
+            s_ms += plan_s.stage_times()[0]
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - ts) / ns
+        split[prec] = {"ms_per_step": 1e3 * ts, "value": pairs_step / ts,
+                       "gemm_tflops": gemm_flops / (s_ms[2] / ns / 1e3) / 1e12, "stage2_ms": s_ms[2] / ns}
+        log(f"[bench] {prec}: {1e3 * ts:.1f} ms/step, stage-2 {s_ms[2] / ns:.2f} ms "
+            f"({split[prec]['gemm_tflops']:.1f} TFLOP/s)")
+        del plan_s
 
     out = {
         "metric": METRIC,
@@ -192,8 +197,7 @@ def main():
         "gemm_tflops": gemm_tflops,
         "stage_ms_per_step": {"cells": stage_ms[0] / K, "stage1_scan": stage_ms[1] / K,
                               "stage2_contract": stage_ms[2] / K},
-        "split_bf16": {"ms_per_step": 1e3 * tb, "value": pairs_step / tb, "gemm_tflops": bf_gemm_tflops,
-                       "stage2_ms": bf_ms[2] / nb},
+        "split_precision": split,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": profiled_traffic(),
                      "kernel": "k_scan (stage 1)",
@@ -229,7 +233,7 @@ def main():
         ref_g = ref_g[:, nm:]
         cidx = torch.from_numpy(idx).to(dev)
         errs = {}
-        for prec in ("fp32", "bf16x3", "fp16x3"):
+        for prec in ("fp32", "bf16x3", "bf16x6", "fp16x3"):
             p = t3.Plan(edges, nm, box_lo=(0, 0), box_size=box, precision=prec)
             ups, npairs = p.forward(dc, cidx)
             assert npairs == o["npairs"], (prec, npairs, o["npairs"])

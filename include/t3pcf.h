@@ -70,6 +70,8 @@ extern "C" {
 #define T3_PREC_BF16X3 1  /* x = hi + lo in bf16; hi*hi + hi*lo + lo*hi for  */
                           /* Upsilon_0..3, FP32 for the normaliser N_n      */
 #define T3_PREC_FP16X3 2  /* same in fp16 with power-of-two row scaling     */
+#define T3_PREC_BF16X6 3  /* x = hi + mid + lo in bf16 (all 24 FP32 bits);  */
+                          /* the six part products of order <= 2; FP32 N_n  */
 
 #define T3_FLAG_KEEP_JK 1u /* keep the j = k terms (the paper's literal sum) */
 #define T3_FLAG_TIMING 2u  /* record HIP events around each stage (t3_stage_times); */

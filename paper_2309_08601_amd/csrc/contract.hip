@@ -1,29 +1,39 @@
 // Stage 2 of the multipole estimator: the contraction over centres
-//     Upsilon_{mu,n}(b1, b2) = sum_i alpha_i X_{mu,n}(i, b1) Y_{mu,n}(i, b2)
+//     Upsilon_{mu,n}(b1, b2) = sum_i X_{mu,n}(i, b1) Y_{mu,n}(i, b2)
 // (Porth et al. 2023, eqs. Upsilon0_Derivation, Upsilon1-3,
 // 3PCF_Normalization), one small complex GEMM (B x B, K = centres) per
-// (mu, n), run on MFMA:
-//     mu = 0: alpha = -c,  X = G_{n-3},      Y = G_{-n-3}
-//     mu = 1: alpha = -c*, X = G_{n-1},      Y = G_{-n-1}
-//     mu = 2: alpha = -c,  X = G_{-n-1}*,    Y = G_{-n-3}
-//     mu = 3: alpha = -c,  X = G_{n-3},      Y = G_{n-1}*
-//     mu = 4: alpha =  w,  X = W_n,          Y = W_n*
+// (mu, n), run on MFMA.  With c = w (g1 + i g2) of the centre:
+//     mu = 0: X = -c  G_{n-3},        Y = G_{-n-3}
+//     mu = 1: X = -c* G_{n-1},        Y = G_{-n-1}
+//     mu = 2: X = -c  conj G_{-n-1},  Y = G_{-n-3}
+//     mu = 3: X = -c  G_{n-3},        Y = conj G_{n-1}
+//     mu = 4: X =  w  W_n,            Y = conj W_n       (normaliser N_n)
 // A complex product is four real MFMAs: Re += Xr Yr - Xi Yi, Im += Xr Yi + Xi Yr.
-// Each wavefront owns one (mu, n) and one slice of centres; FP32 MFMA runs
-// of at most 64 centres are promoted into FP64 accumulators, and the
-// slices are summed in FP64 in a fixed order (deterministic).  The j = k
-// terms (n-independent, diagonal only) are summed separately in FP64 and
-// subtracted in the final reduction.
 //
-// Precision variants (same operands, same FP64 promotion):
+// Work decomposition: a workgroup of four wavefronts owns one n (the four
+// shear components, one wavefront each) or four orders of N, and one slice
+// of centres.  The operands the four products share (mu = 0 and 3 have the
+// same X, mu = 0 and 2 the same Y) are formed once per block of 16 centres:
+// the whole workgroup loads the harmonic planes with coalesced float4 reads,
+// multiplies in the centre factor, splits into hi / lo parts where the
+// precision asks for it, and stores MFMA-ready rows in LDS; the next block's
+// loads are issued before the MFMAs of the current one.  FP32 MFMA runs of
+// 64 centres are promoted into FP64 accumulators, and the slices are summed
+// in FP64 in a fixed order (deterministic).  The j = k terms (n-independent,
+// diagonal only) are summed separately in FP64 and subtracted in the final
+// reduction.
+//
+// Precision variants of the Upsilon products (N_n is always FP32):
 //  * FP32:    v_mfma_f32_32x32x2_f32.
-//  * BF16x3:  x = hi + lo with hi = bf16(x), lo = bf16(x - hi); each real
-//             product is hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16.
-//             The normaliser N_n, which divides every Gamma, stays on the
-//             FP32 path (hi + lo in bf16 keeps about 17 bits).
-//  * FP16x3:  as BF16x3 in fp16 after scaling each (operand, bin) row by a
-//             power of two so that its largest entry is near 2^12 (keeps lo
-//             out of the subnormal range); the scales are divided out in FP64.
+//  * BF16X3:  x = hi + lo, hi = bf16(x), lo = bf16(x - hi) (about 16 bits);
+//             hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16.
+//  * BF16X6:  x = hi + mid + lo (every FP32 bit); the six products whose
+//             part orders sum to at most 2 (dropped terms are below
+//             2^-24 |x y|).
+//  * FP16X3:  as BF16X3 in fp16 (about 22 bits) after scaling each operand
+//             row (array, bin) by a power of two that brings its largest
+//             entry into [2^11, 2^12), keeping lo out of the subnormals; the
+//             scales are divided out in FP64.
 #include "t3_internal.h"
 
 namespace t3 {
@@ -33,20 +43,22 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
+constexpr int kBlk = 16;   // centres staged through LDS per step
 constexpr int kRun = 64;   // centres per FP32 accumulation run before FP64 promotion
+constexpr int kRows = 32;  // tile rows (bins), B <= 32
+constexpr int kNYArr = 6;  // complex operand arrays of the Upsilon kernel
 
 // One launch covers every ordered pair (Z2, Z3) of neighbour catalogs
-// (grid.z = n_z^2; n_z = 1 outside tomography): the b1-side harmonics come
-// from the planes of Z2, the b2-side ones from those of Z3.
+// (grid.z = n_z^2; n_z = 1 outside tomography): the X-side harmonics come
+// from the planes of Z2, the Y-side ones from those of Z3.
 struct ContractArgs {
     const float *planes; // planes of catalog 0; catalog z at planes + z * zstride
     size_t zstride;
     const float4 *ccw;   // centre factors (w g1, w g2, w, 0), chunk-relative
-    const float *scale;  // fp16 row scales [pair][2][5][n_max+1][B] or null
+    const float *scale;  // fp16 row scales [pair][n][kNYArr][kRows] or null
     int n_c, K, B, n_max, n_z;
-    int slice;           // centres per slice (multiple of 16)
+    int slice;           // centres per slice (multiple of kRun)
     int S;               // slices
-    int mu0;             // first component of this launch (grid.x covers mu >= mu0)
     double *partial;     // [pair][S][5][n_max+1][B][B][2]
 };
 
@@ -57,39 +69,21 @@ __device__ __forceinline__ void pair_planes(const ContractArgs &a, int pair, con
     py = a.planes + (size_t)(pair % a.n_z) * a.zstride;
 }
 
-struct Operands {
-    int xr, xi, yr, yi;  // plane indices
-    float xs, ys;        // sign applied to the imaginary parts (conjugation)
-};
+__device__ __forceinline__ int plane_g(int m, int n_max) { return 2 * (m + n_max + 3); }
+__device__ __forceinline__ int plane_w(int m, int n_max) { return 2 * (2 * n_max + 3) + 2 * m; }
 
-__device__ __forceinline__ Operands operands(int mu, int n, int n_max)
+// X-side operands of the Upsilon kernel for centre factor c = (cr, ci):
+//   o0 = -c G_{n-3},  o1 = -c* G_{n-1},  o2 = -c conj G_{-n-1}.
+__device__ __forceinline__ void x_operands(float cr, float ci, float2 g3, float2 g1, float2 gm1,
+                                           float2 (&o)[3])
 {
-    const int n_g = 2 * n_max + 3;
-    auto pg = [&](int m) { return 2 * (m + n_max + 3); };
-    Operands o;
-    int xm, ym;
-    o.xs = 1.0f;
-    o.ys = 1.0f;
-    switch (mu) {
-        case 0: xm = n - 3; ym = -n - 3; break;
-        case 1: xm = n - 1; ym = -n - 1; break;
-        case 2: xm = -n - 1; ym = -n - 3; o.xs = -1.0f; break;
-        case 3: xm = n - 3; ym = n - 1; o.ys = -1.0f; break;
-        default: xm = 0; ym = 0; o.ys = -1.0f; break;
-    }
-    if (mu < 4) {
-        o.xr = pg(xm);
-        o.yr = pg(ym);
-    } else {
-        o.xr = 2 * n_g + 2 * n;
-        o.yr = o.xr;
-    }
-    o.xi = o.xr + 1;
-    o.yi = o.yr + 1;
-    return o;
+    o[0] = make_float2(-fmaf(cr, g3.x, -ci * g3.y), -fmaf(cr, g3.y, ci * g3.x));
+    o[1] = make_float2(-fmaf(cr, g1.x, ci * g1.y), -fmaf(cr, g1.y, -ci * g1.x));
+    o[2] = make_float2(-fmaf(cr, gm1.x, ci * gm1.y), -fmaf(ci, gm1.x, -cr * gm1.y));
 }
 
-// alpha_i for component mu from (w g1, w g2, w).
+// alpha_i of component mu from (w g1, w g2, w): the factor that multiplies
+// the j = k sums.
 __device__ __forceinline__ void alpha_of(int mu, float4 f, float &ar, float &ai)
 {
     if (mu == 4) {
@@ -104,330 +98,552 @@ __device__ __forceinline__ void alpha_of(int mu, float4 f, float &ar, float &ai)
     }
 }
 
+// ------------------------------------------------------------ formats
+// LDS row of one real operand array and bin: the P parts of kBlk centres side
+// by side, plus 16 bytes of padding (one or two parts) so that 16 consecutive
+// lanes reading 16 bytes each at rows r..r+15 hit 16 disjoint groups of four
+// banks.
+template <int PK> struct Fmt;
+template <> struct Fmt<T3_PREC_FP32> {
+    using T = float;
+    static constexpr int parts = 1;
+};
+template <> struct Fmt<T3_PREC_BF16X3> {
+    using T = __bf16;
+    using V = bf16x8;
+    static constexpr int parts = 2;
+};
+template <> struct Fmt<T3_PREC_FP16X3> {
+    using T = _Float16;
+    using V = halfx8;
+    static constexpr int parts = 2;
+};
+template <> struct Fmt<T3_PREC_BF16X6> {
+    using T = __bf16;
+    using V = bf16x8;
+    static constexpr int parts = 3;
+};
+template <int PK>
+constexpr int row_elems()
+{
+    // (three-part rows stay unpadded: two double-buffered workgroups per CU
+    // fit the LDS only that way; the cost is a two-way read conflict)
+    using T = typename Fmt<PK>::T;
+    return (Fmt<PK>::parts * kBlk * (int)sizeof(T) + (Fmt<PK>::parts == 3 ? 0 : 16)) / (int)sizeof(T);
+}
+
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
+
+// Packs the split of two FP32 values: out[p] holds part p of (x0, x1) as
+// two 16-bit values, x = part 0 + part 1 [+ part 2].  Each residual
+// x - part is exact (a subtraction of a rounding of x from x).
+template <int PK>
+__device__ __forceinline__ void split2(float x0, float x1, uint32_t (&out)[Fmt<PK>::parts])
+{
+    using T2 = typename std::conditional<PK == T3_PREC_FP16X3, halfx2, bf16x2>::type;
+#pragma unroll
+    for (int p = 0; p < Fmt<PK>::parts; ++p) {
+        const T2 t = __builtin_convertvector((float2v){x0, x1}, T2);
+        out[p] = __builtin_bit_cast(uint32_t, t);
+        if (p + 1 < Fmt<PK>::parts) {
+            x0 -= (float)t[0];
+            x1 -= (float)t[1];
+        }
+    }
+}
+
+// Writes 4 consecutive centres of one real operand row into LDS (row points
+// at the row's first element; the parts of the row are kBlk elements apart).
+template <int PK>
+__device__ __forceinline__ void put4(typename Fmt<PK>::T *row, float v0, float v1, float v2, float v3)
+{
+    if constexpr (PK == T3_PREC_FP32) {
+        *reinterpret_cast<float4 *>(row) = make_float4(v0, v1, v2, v3);
+    } else {
+        uint32_t lo[Fmt<PK>::parts], hi[Fmt<PK>::parts];
+        split2<PK>(v0, v1, lo);
+        split2<PK>(v2, v3, hi);
+#pragma unroll
+        for (int p = 0; p < Fmt<PK>::parts; ++p)
+            *reinterpret_cast<uint2 *>(row + p * kBlk) = make_uint2(lo[p], hi[p]);
+    }
+}
+
 __device__ __forceinline__ void store_tile(double *dst, int B, int lane, const double (&dr)[16],
-                                           const double (&di)[16], double sx = 1.0)
+                                           const double (&di)[16], const float *sx, const float *sy)
 {
     const int col = lane & 31;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int row = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
         if (row < B && col < B) {
+            const double f = sx ? 1.0 / ((double)sx[row] * (double)sy[col]) : 1.0;
             double2 v;
-            v.x = dr[j] * sx;
-            v.y = di[j] * sx;
+            v.x = dr[j] * f;
+            v.y = di[j] * f;
             *reinterpret_cast<double2 *>(dst + 2 * ((size_t)row * B + col)) = v;
         }
     }
 }
 
-// Loads 4 consecutive centres (ib..ib+3) of bin b for one plane; zeros for
-// bins >= B or centres >= i_end (select, never multiply: stale memory may
-// hold non-finite values).
-__device__ __forceinline__ float4 load4(const float *planes, int plane, int ib, int b, int K, int B,
-                                        int i_end)
+// Keeps the first nv of the four centres of a quad (nv in 0..4).  The hot
+// loop loads from clamped, always valid addresses without branches, so that
+// every load of a block is in flight at once, and masks at first use.
+__device__ __forceinline__ float4 keep(float4 v, int nv)
 {
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (b < B && ib < i_end) {
-        v = *reinterpret_cast<const float4 *>(planes + chunk_offset(plane, ib, b, K, B));
-        if (ib + 1 >= i_end) v.y = 0.f;
-        if (ib + 2 >= i_end) v.z = 0.f;
-        if (ib + 3 >= i_end) v.w = 0.f;
-    }
+    v.x = nv > 0 ? v.x : 0.f;
+    v.y = nv > 1 ? v.y : 0.f;
+    v.z = nv > 2 ? v.z : 0.f;
+    v.w = nv > 3 ? v.w : 0.f;
     return v;
 }
 
-__global__ __launch_bounds__(64) void k_contract_fp32(ContractArgs a)
+__device__ __forceinline__ float comp(const float4 &v, int e)
 {
-    const int lane = threadIdx.x;
-    const int mn = blockIdx.x + a.mu0 * (a.n_max + 1);
-    const int mu = mn / (a.n_max + 1), n = mn % (a.n_max + 1);
-    const int sl = blockIdx.y;
-    const int pair = blockIdx.z;
+    return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+}
+
+__device__ __forceinline__ uint4 xor4(uint4 v, uint32_t m)
+{
+    return make_uint4(v.x ^ m, v.y ^ m, v.z ^ m, v.w ^ m);
+}
+
+// The contraction, software-pipelined over blocks of kBlk centres with two
+// LDS buffers: while the matrix cores run the products of block b from one
+// buffer, the same wavefronts form the operands of block b + 1 (VALU) into
+// the other, and the global loads of block b + 2 are in flight; one barrier
+// per block.
+//  NK = false: four wavefronts = mu 0..3 of one order n.  The staging
+//    threads of waves 0-1 form the X operands (-c G_{n-3}, -c* G_{n-1},
+//    -c conj G_{-n-1}), those of waves 2-3 the Y operands (G_{-n-3},
+//    G_{-n-1}, G_{n-1}), with the same branch-free arithmetic (factor 1 on
+//    the Y side).
+//  NK = true (FP32 only): N of two orders; wavefront 2k + r computes the
+//    real (r = 0) or imaginary (r = 1) part of order 2 grp + k.
+template <int PK, bool NK>
+__global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
+{
+    using F = Fmt<PK>;
+    using T = typename F::T;
+    constexpr int P = F::parts, RS = row_elems<PK>();
+    constexpr int NC = NK ? 4 : 6;  // complex operand arrays per buffer
+    constexpr int NL = NC / 2;      // complex planes per staging thread
+    constexpr int BUF = 2 * NC * kRows * RS;
+    __shared__ __attribute__((aligned(16))) T lds[2 * BUF];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // Workgroups are dispatched round-robin over the 8 XCDs: XCD x runs the
+    // slices x, x + 8, ...; within a slice the catalog pairs vary fastest,
+    // then the order group, so that the workgroups reading the same harmonic
+    // planes (every pair shares its X catalog with n_z - 1 others and its Y
+    // catalog likewise; neighbouring orders share planes) run on one XCD at
+    // about the same time and meet in its L2.
+    const int ngrp = NK ? (a.n_max + 2) / 2 : a.n_max + 1;
+    const int pairs = a.n_z * a.n_z;
+    const int xcd = blockIdx.x & 7;
+    int jx = blockIdx.x >> 3;
+    const int pair = jx % pairs;
+    jx /= pairs;
+    const int grp = jx % ngrp;
+    const int sl = 8 * (jx / ngrp) + xcd;
+    if (sl >= a.S) return;
     const float *px, *py;
     pair_planes(a, pair, px, py);
     const int i_begin = sl * a.slice;
     const int i_end = min(i_begin + a.slice, a.n_c);
-    const Operands o = operands(mu, n, a.n_max);
-    const int b = lane & 31, kq = lane >> 5;
+    const int nm = a.n_max;
+
+    // this wavefront's product X_ia * (conj?) Y_ib
+    int n, mu, ia, ib, ri = 0;
+    bool cj;
+    if constexpr (NK) {
+        n = 2 * grp + (wave >> 1);
+        mu = 4;
+        ia = wave >> 1;
+        ib = 2 + (wave >> 1);
+        ri = wave & 1;
+        cj = true;
+    } else {
+        n = grp;
+        mu = wave;
+        ia = mu == 3 ? 0 : mu;
+        ib = (mu == 0 || mu == 2) ? 3 : (mu == 1 ? 4 : 5);
+        cj = mu == 3;
+    }
+    const bool active = n <= nm;
+
+    // staging role: bin sb, centre quad sq, side sh (0: X from px, 1: Y from py)
+    const int sb = tid & 31, sq = (tid >> 5) & 3;
+    const int sh = __builtin_amdgcn_readfirstlane(tid >> 7);
+    int pl[NL];
+    if constexpr (NK) {
+        pl[0] = plane_w(min(2 * grp, nm), nm);
+        pl[1] = plane_w(min(2 * grp + 1, nm), nm);
+    } else {
+        pl[0] = plane_g(sh ? -grp - 3 : grp - 3, nm);
+        pl[1] = plane_g(sh ? -grp - 1 : grp - 1, nm);
+        pl[2] = plane_g(sh ? grp - 1 : -grp - 1, nm);
+    }
+    const float *src = sh ? py : px;
+    const int bc = min(sb, a.B - 1);
+    unsigned off[NL][2];  // float offset of (plane, centre 0, bin bc)
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) off[k][r] = (unsigned)chunk_offset(pl[k] + r, 0, bc, a.K, a.B);
+    const int i_last = i_end - 1;
+    const int q_last = i_last >> 2;
+    const unsigned qstride = 4u * (unsigned)a.B;  // floats from one centre quad to the next
+    // branch-free operand factors: X side (-c), Y side 1
+    const float ys = sh ? 1.0f : 0.0f, xs = sh ? 0.0f : 1.0f;
+    const float s2 = sh ? 1.0f : -1.0f;  // conj of G_{-n-1} on the X side
+    float sc[3] = {1.f, 1.f, 1.f};        // fp16 row scales of this thread's arrays
+    const float *scl = nullptr;
+    if constexpr (PK == T3_PREC_FP16X3) {
+        scl = a.scale + ((size_t)pair * (nm + 1) + n) * kNYArr * kRows;
+        const float *srow = a.scale + ((size_t)pair * (nm + 1) + grp) * kNYArr * kRows;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sc[k] = srow[(3 * sh + k) * kRows + sb];
+    }
+
+    struct Stage {
+        float4 ld[NL][2];
+        float2 cw[4];  // (Re c, Im c) of the quad's centres, or (w, 0) for N
+        int nv;        // valid centres of this thread's quad
+    };
+    Stage s0, s1;
+    // Every thread loads the centre factors (the Y side ignores them) and
+    // loads them first: with the same loads on every path, in the same
+    // order, the compiler waits only for the stage being used.
+    auto load_block = [&](Stage &st, int i0) {
+        const int q = (i0 >> 2) + sq;
+        const unsigned qo = (unsigned)min(q, q_last) * qstride;
+        st.nv = sb < a.B ? max(0, min(4, i_end - 4 * q)) : 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float4 f = a.ccw[min(4 * q + e, i_last)];
+            st.cw[e] = NK ? make_float2(f.z, 0.f) : make_float2(f.x, f.y);
+        }
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            st.ld[k][0] = *reinterpret_cast<const float4 *>(src + off[k][0] + qo);
+            st.ld[k][1] = *reinterpret_cast<const float4 *>(src + off[k][1] + qo);
+        }
+    };
+
+    auto lrow = [&](int buf, int arr, int part, int row) -> T * {
+        return lds + (size_t)buf * BUF + (size_t)(2 * arr + part) * kRows * RS + (size_t)row * RS;
+    };
+
+    // operands of one staged block into LDS buffer buf
+    auto stage_to_lds = [&](Stage &st, int buf) {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            st.ld[k][0] = keep(st.ld[k][0], st.nv);
+            st.ld[k][1] = keep(st.ld[k][1], st.nv);
+        }
+        float v[4][NL][2];  // [centre][array][re/im]
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if constexpr (NK) {
+                const float w = fmaf(xs, st.cw[e].x, ys);  // w on the X side, 1 on the Y side
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    v[e][k][0] = w * comp(st.ld[k][0], e);
+                    v[e][k][1] = w * comp(st.ld[k][1], e);
+                }
+            } else {
+                const float ar = fmaf(-xs, st.cw[e].x, ys), ai = -xs * st.cw[e].y;
+                const float g0r = comp(st.ld[0][0], e), g0i = comp(st.ld[0][1], e);
+                const float g1r = comp(st.ld[1][0], e), g1i = comp(st.ld[1][1], e);
+                const float g2r = comp(st.ld[2][0], e), g2i = s2 * comp(st.ld[2][1], e);
+                v[e][0][0] = fmaf(ar, g0r, -ai * g0i) * sc[0];
+                v[e][0][1] = fmaf(ar, g0i, ai * g0r) * sc[0];
+                v[e][1][0] = fmaf(ar, g1r, ai * g1i) * sc[1];
+                v[e][1][1] = fmaf(ar, g1i, -ai * g1r) * sc[1];
+                v[e][2][0] = fmaf(ar, g2r, -ai * g2i) * sc[2];
+                v[e][2][1] = fmaf(ar, g2i, ai * g2r) * sc[2];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NL; ++k)
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                put4<PK>(lrow(buf, NL * sh + k, r, sb) + 4 * sq, v[0][k][r], v[1][k][r], v[2][k][r], v[3][k][r]);
+    };
 
     floatx16 cr = {}, ci = {};
     double dr[16], di[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) dr[j] = di[j] = 0.0;
-
     int run = 0;
-    for (int i0 = i_begin; i0 < i_end; i0 += 8) {
-        const int ib = i0 + 4 * kq;
-        const float4 xr = load4(px, o.xr, ib, b, a.K, a.B, i_end);
-        float4 xi = load4(px, o.xi, ib, b, a.K, a.B, i_end);
-        const float4 yr = load4(py, o.yr, ib, b, a.K, a.B, i_end);
-        float4 yi = load4(py, o.yi, ib, b, a.K, a.B, i_end);
-        const float xa[4] = {xr.x, xr.y, xr.z, xr.w};
-        const float xb[4] = {xi.x * o.xs, xi.y * o.xs, xi.z * o.xs, xi.w * o.xs};
-        const float ya[4] = {yr.x, yr.y, yr.z, yr.w};
-        const float yb[4] = {yi.x * o.ys, yi.y * o.ys, yi.z * o.ys, yi.w * o.ys};
+    auto promote = [&]() {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            float al_r = 0.f, al_i = 0.f;
-            if (ib + s < i_end) alpha_of(mu, a.ccw[ib + s], al_r, al_i);
-            const float pr = fmaf(al_r, xa[s], -al_i * xb[s]);
-            const float pi = fmaf(al_r, xb[s], al_i * xa[s]);
-            cr = __builtin_amdgcn_mfma_f32_32x32x2f32(pr, ya[s], cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-pi, yb[s], cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x2f32(pr, yb[s], ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x2f32(pi, ya[s], ci, 0, 0, 0);
+        for (int j = 0; j < 16; ++j) {
+            dr[j] += (double)cr[j];
+            di[j] += (double)ci[j];
+            cr[j] = 0.f;
+            ci[j] = 0.f;
         }
-        run += 8;
+    };
+
+    // this wavefront's MFMAs over the block in LDS buffer buf.  The FP64
+    // promotion of a finished run comes first, so that it reads accumulators
+    // whose MFMAs completed while the staging arithmetic ran.
+    auto mfma_block = [&](int buf) {
+        if (!active) return;
         if (run >= kRun) {
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                dr[j] += (double)cr[j];
-                di[j] += (double)ci[j];
-                cr[j] = 0.f;
-                ci[j] = 0.f;
-            }
+            promote();
             run = 0;
         }
-    }
+        run += kBlk;
+        const int r = lane & 31, kq = lane >> 5;
+        if constexpr (PK == T3_PREC_FP32) {
+            float4 xr[2], xi[2], yr[2], yi[2];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        dr[j] += (double)cr[j];
-        di[j] += (double)ci[j];
-    }
-    double *dst = a.partial + ((((size_t)pair * a.S + sl) * 5 + mu) * (a.n_max + 1) + n) * a.B * a.B * 2;
-    store_tile(dst, a.B, lane, dr, di);
-}
-
-// hi/lo split of 8 values for the split-precision variants.
-template <class T>
-__device__ __forceinline__ void split8(const float (&x)[8], T (&hi)[8], T (&lo)[8])
-{
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        hi[j] = (T)x[j];
-        lo[j] = (T)(x[j] - (float)hi[j]);
-    }
-}
-
-// Split-precision contraction: 16 centres per MFMA (8 per half-wave).
-// Lane (b, kq) holds centres ib = i0 + 8 kq + (0..7).
-template <bool FP16>
-__global__ __launch_bounds__(64) void k_contract_split(ContractArgs a)
-{
-    using T = typename std::conditional<FP16, _Float16, __bf16>::type;
-    using V8 = typename std::conditional<FP16, halfx8, bf16x8>::type;
-    const int lane = threadIdx.x;
-    const int mn = blockIdx.x + a.mu0 * (a.n_max + 1);
-    const int mu = mn / (a.n_max + 1), n = mn % (a.n_max + 1);
-    const int sl = blockIdx.y;
-    const int pair = blockIdx.z;
-    const float *px, *py;
-    pair_planes(a, pair, px, py);
-    const int i_begin = sl * a.slice;
-    const int i_end = min(i_begin + a.slice, a.n_c);
-    const Operands o = operands(mu, n, a.n_max);
-    const int b = lane & 31, kq = lane >> 5;
-
-    // power-of-two row scales (FP16 only): X row b1 by sx, Y row b2 by sy
-    const size_t half = (size_t)5 * (a.n_max + 1) * a.B;
-    const float *scale = a.scale ? a.scale + (size_t)pair * 2 * half : nullptr;
-    float sx = 1.0f, sy = 1.0f;
-    if (FP16 && scale) {
-        const size_t base = ((size_t)mu * (a.n_max + 1) + n) * a.B;
-        if (b < a.B) {
-            sx = scale[base + b];
-            sy = scale[half + base + b];
-        }
-    }
-
-    floatx16 cr = {}, ci = {};
-    double dr[16], di[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) dr[j] = di[j] = 0.0;
-    int run = 0;
-    for (int i0 = i_begin; i0 < i_end; i0 += 16) {
-        const int ib = i0 + 8 * kq;
-        float xa[8], xb[8], ya[8], yb[8];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const float4 xr = load4(px, o.xr, ib + 4 * h, b, a.K, a.B, i_end);
-            const float4 xi = load4(px, o.xi, ib + 4 * h, b, a.K, a.B, i_end);
-            const float4 yr = load4(py, o.yr, ib + 4 * h, b, a.K, a.B, i_end);
-            const float4 yi = load4(py, o.yi, ib + 4 * h, b, a.K, a.B, i_end);
-            const float xr4[4] = {xr.x, xr.y, xr.z, xr.w}, xi4[4] = {xi.x, xi.y, xi.z, xi.w};
-            const float yr4[4] = {yr.x, yr.y, yr.z, yr.w}, yi4[4] = {yi.x, yi.y, yi.z, yi.w};
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int i = ib + 4 * h + s;
-                float al_r = 0.f, al_i = 0.f;
-                if (i < i_end) alpha_of(mu, a.ccw[i], al_r, al_i);
-                const float x_r = xr4[s], x_i = xi4[s] * o.xs;
-                xa[4 * h + s] = fmaf(al_r, x_r, -al_i * x_i) * sx;
-                xb[4 * h + s] = fmaf(al_r, x_i, al_i * x_r) * sx;
-                ya[4 * h + s] = yr4[s] * sy;
-                yb[4 * h + s] = yi4[s] * o.ys * sy;
+            for (int h = 0; h < 2; ++h) {
+                xr[h] = *reinterpret_cast<const float4 *>(lrow(buf, ia, 0, r) + 8 * kq + 4 * h);
+                xi[h] = *reinterpret_cast<const float4 *>(lrow(buf, ia, 1, r) + 8 * kq + 4 * h);
+                yr[h] = *reinterpret_cast<const float4 *>(lrow(buf, ib, 0, r) + 8 * kq + 4 * h);
+                yi[h] = *reinterpret_cast<const float4 *>(lrow(buf, ib, 1, r) + 8 * kq + 4 * h);
             }
-        }
-        T xah[8], xal[8], xbh[8], xbl[8], yah[8], yal[8], ybh[8], ybl[8];
-        split8<T>(xa, xah, xal);
-        split8<T>(xb, xbh, xbl);
-        split8<T>(ya, yah, yal);
-        split8<T>(yb, ybh, ybl);
-        V8 XAH, XAL, XBH, XBL, YAH, YAL, YBH, YBL, NXBH, NXBL;
+            if constexpr (NK) {
+                // conj Y: Re = Xr Yr + Xi Yi, Im = -Xr Yi + Xi Yr (one part per wavefront)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            XAH[j] = xah[j]; XAL[j] = xal[j]; XBH[j] = xbh[j]; XBL[j] = xbl[j];
-            YAH[j] = yah[j]; YAL[j] = yal[j]; YBH[j] = ybh[j]; YBL[j] = ybl[j];
-            NXBH[j] = -xbh[j]; NXBL[j] = -xbl[j];
-        }
-        // Re: xa*ya - xb*yb ; Im: xa*yb + xb*ya ; each as hi*hi + hi*lo + lo*hi
-        if constexpr (FP16) {
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(XAH, YAH, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(XAH, YAL, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(XAL, YAH, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(NXBH, YBH, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(NXBH, YBL, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(NXBL, YBH, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(XAH, YBH, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(XAH, YBL, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(XAL, YBH, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(XBH, YAH, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(XBH, YAL, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(XBL, YAH, ci, 0, 0, 0);
+                for (int s = 0; s < 8; ++s) {
+                    const float ar = comp(xr[s >> 2], s & 3), ai = comp(xi[s >> 2], s & 3);
+                    const float br = comp(yr[s >> 2], s & 3), bi = comp(yi[s >> 2], s & 3);
+                    cr = __builtin_amdgcn_mfma_f32_32x32x2f32(ri ? -ar : ar, ri ? bi : br, cr, 0, 0, 0);
+                    cr = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, ri ? br : bi, cr, 0, 0, 0);
+                }
+            } else {
+                const uint32_t m1 = cj ? 0u : 0x80000000u;  // Re: X_i * (-Y_i) (or + for conj Y)
+                const uint32_t m2 = cj ? 0x80000000u : 0u;  // Im: X_r * Y_i (or - for conj Y)
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const float ar = comp(xr[s >> 2], s & 3), ai = comp(xi[s >> 2], s & 3);
+                    const float br = comp(yr[s >> 2], s & 3), bi = comp(yi[s >> 2], s & 3);
+                    const float x1 = __uint_as_float(__float_as_uint(ai) ^ m1);
+                    const float x2 = __uint_as_float(__float_as_uint(ar) ^ m2);
+                    cr = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, cr, 0, 0, 0);
+                    cr = __builtin_amdgcn_mfma_f32_32x32x2f32(x1, bi, cr, 0, 0, 0);
+                    ci = __builtin_amdgcn_mfma_f32_32x32x2f32(x2, bi, ci, 0, 0, 0);
+                    ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, ci, 0, 0, 0);
+                }
+            }
         } else {
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XAH, YAH, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XAH, YAL, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XAL, YAH, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(NXBH, YBH, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(NXBH, YBL, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(NXBL, YBH, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XAH, YBH, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XAH, YBL, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XAL, YBH, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XBH, YAH, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XBH, YAL, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XBL, YAH, ci, 0, 0, 0);
-        }
-        run += 16;
-        if (run >= kRun) {
+            using V = typename F::V;
+            const uint32_t m1 = cj ? 0u : 0x80008000u;
+            const uint32_t m2 = cj ? 0x80008000u : 0u;
+            // one X part at a time (its four vectors), Y parts re-read from
+            // LDS for every X part: fewer live registers
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                dr[j] += (double)cr[j];
-                di[j] += (double)ci[j];
-                cr[j] = 0.f;
-                ci[j] = 0.f;
+            for (int p = 0; p < P; ++p) {
+                const uint4 xr = *reinterpret_cast<const uint4 *>(lrow(buf, ia, 0, r) + p * kBlk + 8 * kq);
+                const uint4 xi = *reinterpret_cast<const uint4 *>(lrow(buf, ia, 1, r) + p * kBlk + 8 * kq);
+                const V XR = __builtin_bit_cast(V, xr);
+                const V XI = __builtin_bit_cast(V, xi);
+                const V X1 = __builtin_bit_cast(V, xor4(xi, m1));
+                const V X2 = __builtin_bit_cast(V, xor4(xr, m2));
+#pragma unroll
+                for (int q = 0; q + p < P; ++q) {
+                    const V YR = *reinterpret_cast<const V *>(lrow(buf, ib, 0, r) + q * kBlk + 8 * kq);
+                    const V YI = *reinterpret_cast<const V *>(lrow(buf, ib, 1, r) + q * kBlk + 8 * kq);
+                    if constexpr (PK == T3_PREC_FP16X3) {
+                        cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(XR, YR, cr, 0, 0, 0);
+                        cr = __builtin_amdgcn_mfma_f32_32x32x16_f16(X1, YI, cr, 0, 0, 0);
+                        ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(X2, YI, ci, 0, 0, 0);
+                        ci = __builtin_amdgcn_mfma_f32_32x32x16_f16(XI, YR, ci, 0, 0, 0);
+                    } else {
+                        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XR, YR, cr, 0, 0, 0);
+                        cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X1, YI, cr, 0, 0, 0);
+                        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(X2, YI, ci, 0, 0, 0);
+                        ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XI, YR, ci, 0, 0, 0);
+                    }
+                }
             }
-            run = 0;
         }
+    };
+
+    // Pipeline.  i_begin < i_end here (empty slices are never launched);
+    // loads past the end read clamped, valid addresses and are masked (nv = 0).
+    load_block(s0, i_begin);
+    load_block(s1, i_begin + kBlk);
+    stage_to_lds(s0, 0);
+    load_block(s0, i_begin + 2 * kBlk);
+    __syncthreads();
+    for (int i0 = i_begin;; i0 += 2 * kBlk) {
+        mfma_block(0);  // block i0
+        if (i0 + kBlk >= i_end) break;
+        stage_to_lds(s1, 1);  // block i0 + kBlk
+        load_block(s1, i0 + 3 * kBlk);
+        __syncthreads();
+        mfma_block(1);
+        if (i0 + 2 * kBlk >= i_end) break;
+        stage_to_lds(s0, 0);  // block i0 + 2 kBlk
+        load_block(s0, i0 + 4 * kBlk);
+        __syncthreads();
     }
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        dr[j] += (double)cr[j];
-        di[j] += (double)ci[j];
-    }
-    // undo the row scales: entry (row, col) carries sx(row) sy(col)
-    double *dst = a.partial + ((((size_t)pair * a.S + sl) * 5 + mu) * (a.n_max + 1) + n) * a.B * a.B * 2;
-    if (FP16 && scale) {
-        const size_t base = ((size_t)mu * (a.n_max + 1) + n) * a.B;
+    if (!active) return;
+    promote();
+    double *dst = a.partial + ((((size_t)pair * a.S + sl) * 5 + mu) * (nm + 1) + n) * a.B * a.B * 2;
+    if constexpr (NK) {
+        // one part per wavefront: real parts in dr of wave r = 0, imaginary in r = 1
         const int col = lane & 31;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int row = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-            if (row < a.B && col < a.B) {
-                const double f = 1.0 / ((double)scale[base + row] * (double)scale[half + base + col]);
-                double2 v;
-                v.x = dr[j] * f;
-                v.y = di[j] * f;
-                *reinterpret_cast<double2 *>(dst + 2 * ((size_t)row * a.B + col)) = v;
-            }
+            if (row < a.B && col < a.B) dst[2 * ((size_t)row * a.B + col) + ri] = dr[j];
         }
+    } else if constexpr (PK == T3_PREC_FP16X3) {
+        store_tile(dst, a.B, lane, dr, di, scl + ia * kRows, scl + ib * kRows);
     } else {
-        store_tile(dst, a.B, lane, dr, di);
+        store_tile(dst, a.B, lane, dr, di, nullptr, nullptr);
     }
 }
 
-// Row scales for FP16x3: for every (mu, n) and bin, the power of two that
-// brings max_i |alpha_i X(i, b)| (resp. max |Y(i, b)|) to [2^11, 2^12).
-__global__ __launch_bounds__(256) void k_fp16_scales(ContractArgs a, float *scale_all)
+// Row scales for FP16X3, in two steps.  k_fp16_max: for every order n,
+// operand array (the three X and three Y arrays of the Upsilon kernel) and
+// bin, the largest |Re| or |Im| over the chunk's centres, formed with exactly
+// the arithmetic of k_contract; grid.z splits the centres and the partial
+// maxima meet in an integer atomicMax on the float bits (exact and order
+// independent for values >= 0).  k_fp16_scale: the power of two that brings
+// that maximum into [2^11, 2^12).
+constexpr int kScaleSplit = 16;
+
+__global__ __launch_bounds__(256) void k_fp16_max(ContractArgs a, unsigned *mx_all)
 {
-    const int mn = blockIdx.x;
-    const int mu = mn / (a.n_max + 1), n = mn % (a.n_max + 1);
-    const int b = blockIdx.y;
-    const int side = blockIdx.z & 1;  // 0: X (with alpha), 1: Y
-    const int pair = blockIdx.z >> 1;
+    const int n = blockIdx.x, side = blockIdx.y & 1, pair = blockIdx.y >> 1;
     const float *px, *py;
     pair_planes(a, pair, px, py);
-    float *scale = scale_all + (size_t)pair * 2 * 5 * (a.n_max + 1) * a.B;
-    const Operands o = operands(mu, n, a.n_max);
-    float m = 0.0f;
-    for (int i = threadIdx.x; i < a.n_c; i += blockDim.x) {
-        const float *pl = side ? py : px;
-        const int pr = side ? o.yr : o.xr;
-        const float re = pl[chunk_offset(pr, i, b, a.K, a.B)];
-        const float im = pl[chunk_offset(pr + 1, i, b, a.K, a.B)];
-        float v = fmaxf(fabsf(re), fabsf(im));
-        if (!side) {
-            const float4 f = a.ccw[i];
-            const float al = mu == 4 ? fabsf(f.z) : fmaxf(fabsf(f.x), fabsf(f.y));
-            v *= 2.0f * al;
-        }
-        m = fmaxf(m, v);
+    const int nm = a.n_max;
+    const int b = threadIdx.x & 31, g = threadIdx.x >> 5;
+    int pl[3];
+    if (side == 0) {
+        pl[0] = plane_g(n - 3, nm);
+        pl[1] = plane_g(n - 1, nm);
+        pl[2] = plane_g(-n - 1, nm);
+    } else {
+        pl[0] = plane_g(-n - 3, nm);
+        pl[1] = plane_g(-n - 1, nm);
+        pl[2] = plane_g(n - 1, nm);
     }
-    __shared__ float sm[256];
-    sm[threadIdx.x] = m;
+    const float *src = side ? py : px;
+    const int nq = (a.n_c + 3) >> 2;
+    const int per = (nq + kScaleSplit - 1) / kScaleSplit;
+    const int q_end = min(nq, ((int)blockIdx.z + 1) * per);
+    const int bc = min(b, a.B - 1);
+    float m[3] = {0.f, 0.f, 0.f};
+    for (int q = (int)blockIdx.z * per + g; q < q_end; q += 8) {
+        const int i4 = 4 * q;
+        const int nv = b < a.B ? min(4, a.n_c - i4) : 0;
+        float4 re[3], im[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            re[k] = keep(*reinterpret_cast<const float4 *>(src + chunk_offset(pl[k], i4, bc, a.K, a.B)), nv);
+            im[k] = keep(*reinterpret_cast<const float4 *>(src + chunk_offset(pl[k] + 1, i4, bc, a.K, a.B)), nv);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float2 o[3];
+            const float2 g0 = make_float2(comp(re[0], e), comp(im[0], e));
+            const float2 g1 = make_float2(comp(re[1], e), comp(im[1], e));
+            const float2 g2 = make_float2(comp(re[2], e), comp(im[2], e));
+            if (side == 0) {
+                const float4 f = a.ccw[min(i4 + e, a.n_c - 1)];
+                x_operands(f.x, f.y, g0, g1, g2, o);
+            } else {
+                o[0] = g0;
+                o[1] = g1;
+                o[2] = g2;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) m[k] = fmaxf(m[k], fmaxf(fabsf(o[k].x), fabsf(o[k].y)));
+        }
+    }
+    __shared__ float sm[3][8][32];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sm[k][g][b] = m[k];
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + s]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        float sc = 1.0f;
-        const float mx = sm[0];
-        if (mx > 0.0f && isfinite(mx)) {
-            const int e = ilogbf(mx);  // mx in [2^e, 2^{e+1})
-            sc = ldexpf(1.0f, 11 - e);
-        }
-        scale[(size_t)side * 5 * (a.n_max + 1) * a.B + ((size_t)mu * (a.n_max + 1) + n) * a.B + b] = sc;
+    if (threadIdx.x < 96) {
+        const int k = threadIdx.x >> 5;
+        float mx = 0.f;
+        for (int j = 0; j < 8; ++j) mx = fmaxf(mx, sm[k][j][b]);
+        atomicMax(mx_all + (((size_t)pair * (nm + 1) + n) * kNYArr + 3 * side + k) * kRows + b,
+                  __float_as_uint(mx));
     }
 }
 
-// Diagonal (j = k) sums E_mu(b) = sum_i alpha_i D_mu(i, b) in FP64.
-__global__ __launch_bounds__(256) void k_diag(const float *planes0, size_t zstride, const float4 *ccw,
-                                              int n_c, int K, int B, int pD, double *E0)
+__global__ void k_fp16_scale(const unsigned *mx, float *scale, int n)
 {
-    const int mu = blockIdx.x, b = blockIdx.y;
-    const float *planes = planes0 + (size_t)blockIdx.z * zstride;
-    double *E = E0 + (size_t)blockIdx.z * 10 * B;
-    double sr = 0.0, si = 0.0;
-    for (int i = threadIdx.x; i < n_c; i += blockDim.x) {
-        float ar, ai;
-        alpha_of(mu, ccw[i], ar, ai);
-        float dr, di;
-        if (mu == 4) {
-            dr = planes[chunk_offset(pD + 6, i, b, K, B)];
-            di = 0.0f;
-        } else {
-            const int d = mu == 0 ? 0 : (mu == 1 ? 2 : 4);
-            dr = planes[chunk_offset(pD + d, i, b, K, B)];
-            di = planes[chunk_offset(pD + d + 1, i, b, K, B)];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const float m = __uint_as_float(mx[t]);
+    scale[t] = (m > 0.0f && isfinite(m)) ? ldexpf(1.0f, 11 - ilogbf(m)) : 1.0f;  // m in [2^e, 2^{e+1})
+}
+
+__global__ void k_zero_u32(unsigned *p, int n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0u;
+}
+
+// Diagonal (j = k) sums E_mu(b) = sum_i alpha_i D_mu(i, b) in FP64, for all
+// five components.  One workgroup per (bin, catalog, centre range); the
+// kDiagSplit partial sums are added in a fixed order by k_reduce.
+constexpr int kDiagSplit = 16;
+
+__global__ __launch_bounds__(256) void k_diag(const float *planes0, size_t zstride, const float4 *ccw,
+                                              int n_c, int K, int B, int pD, int n_z, double *E0)
+{
+    const int b = blockIdx.x;
+    const float *planes = planes0 + (size_t)blockIdx.y * zstride;
+    double *E = E0 + ((size_t)blockIdx.z * n_z + blockIdx.y) * 10 * B;
+    double acc[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) acc[j] = 0.0;
+    const int nq = (n_c + 3) >> 2;
+    const int per = (nq + kDiagSplit - 1) / kDiagSplit;
+    const int q_end = min(nq, ((int)blockIdx.z + 1) * per);
+    for (int q = (int)blockIdx.z * per + threadIdx.x; q < q_end; q += blockDim.x) {
+        const int i4 = 4 * q;
+        const int nv = min(4, n_c - i4);
+        float4 d[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+            d[k] = keep(*reinterpret_cast<const float4 *>(planes + chunk_offset(pD + k, i4, b, K, B)), nv);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float4 f = ccw[min(i4 + e, n_c - 1)];
+#pragma unroll
+            for (int mu = 0; mu < 5; ++mu) {
+                float ar, ai;
+                alpha_of(mu, f, ar, ai);
+                const int k = mu == 0 ? 0 : (mu == 1 ? 2 : (mu == 4 ? 6 : 4));
+                const double dr = comp(d[k], e);
+                const double di = mu == 4 ? 0.0 : (double)comp(d[k + 1], e);
+                acc[2 * mu] += (double)ar * dr - (double)ai * di;
+                acc[2 * mu + 1] += (double)ar * di + (double)ai * dr;
+            }
         }
-        sr += (double)ar * dr - (double)ai * di;
-        si += (double)ar * di + (double)ai * dr;
     }
-    __shared__ double s_r[256], s_i[256];
-    s_r[threadIdx.x] = sr;
-    s_i[threadIdx.x] = si;
+    __shared__ double sred[10][256];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) sred[j][threadIdx.x] = acc[j];
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            s_r[threadIdx.x] += s_r[threadIdx.x + s];
-            s_i[threadIdx.x] += s_i[threadIdx.x + s];
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+#pragma unroll
+            for (int j = 0; j < 10; ++j) sred[j][threadIdx.x] += sred[j][threadIdx.x + st];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        E[2 * (mu * B + b)] = s_r[0];
-        E[2 * (mu * B + b) + 1] = s_i[0];
+    if (threadIdx.x < 10) {
+        const int mu = threadIdx.x >> 1, part = threadIdx.x & 1;
+        E[2 * (mu * B + b) + part] = sred[threadIdx.x][0];
     }
 }
 
@@ -451,9 +667,14 @@ __global__ void k_reduce(const double *partial, int S, int n_max, int B, int n_z
     }
     const int z2 = pair / n_z, z3 = pair % n_z;
     if (jk && z2 == z3 && b1 == b2) {
-        const double *Ez = E + (size_t)z2 * 10 * B;
-        re -= Ez[2 * (mu * B + b1)];
-        im -= Ez[2 * (mu * B + b1) + 1];
+        double er = 0.0, ei = 0.0;
+        for (int sp = 0; sp < kDiagSplit; ++sp) {
+            const double *Ez = E + ((size_t)sp * n_z + z2) * 10 * B;
+            er += Ez[2 * (mu * B + b1)];
+            ei += Ez[2 * (mu * B + b1) + 1];
+        }
+        re -= er;
+        im -= ei;
     }
     out[2 * t] += re;
     out[2 * t + 1] += im;
@@ -476,13 +697,29 @@ int zero_doubles(double *p, size_t n, hipStream_t s)
 }
 
 // Centres per stage-2 slice: a function of the chunk capacity only, so that
-// every chunk of a call fits the buffers reserved up front.
+// every chunk of a call fits the buffers reserved up front.  The Upsilon
+// kernel runs (n_max + 1) n_z^2 workgroups per slice, two per compute unit at
+// a time (256 CUs); the slice length (a multiple of the FP32 run) minimises
+// rounds x (length + 64), the time of the launch with the cost of writing
+// and reducing one partial tile counted as 64 centres of work, preferring
+// longer slices on ties.
 int contract_slice(const ChunkLayout &L, int n_z)
 {
-    const int nmn = 5 * (L.n_max + 1);
-    int slice = 512;
-    while (slice > 64 && (int64_t)nmn * n_z * n_z * ((L.K + slice - 1) / slice) < 2048) slice >>= 1;
-    return slice;
+    const int64_t per_slice = (int64_t)(L.n_max + 1) * n_z * n_z;
+    const int64_t slots = 2 * 256;
+    int best = kRun;
+    int64_t best_cost = INT64_MAX;
+    for (int slice = kRun; slice <= 4096; slice += kRun) {
+        const int64_t S = (L.K + slice - 1) / slice;
+        const int64_t rounds = (per_slice * S + slots - 1) / slots;
+        const int64_t cost = rounds * (slice + 64);
+        if (cost <= best_cost) {
+            best_cost = cost;
+            best = slice;
+        }
+        if (S == 1) break;
+    }
+    return best;
 }
 
 int reserve_contract(t3_plan *plan, const ChunkLayout &L, int n_z)
@@ -491,9 +728,9 @@ int reserve_contract(t3_plan *plan, const ChunkLayout &L, int n_z)
     const int S = (L.K + contract_slice(L, n_z) - 1) / contract_slice(L, n_z);
     const size_t per = (size_t)5 * (L.n_max + 1) * L.B * L.B;
     T3_TRY(plan->partial.reserve(sizeof(double) * 2 * per * (size_t)S * pairs));
-    T3_TRY(plan->diag.reserve(sizeof(double) * 2 * 5 * (size_t)L.B * n_z));
-    if (plan->precision == T3_PREC_FP16X3)
-        T3_TRY(plan->scales.reserve(sizeof(float) * 2 * 5 * (size_t)(L.n_max + 1) * L.B * pairs));
+    T3_TRY(plan->diag.reserve(sizeof(double) * 2 * 5 * (size_t)L.B * n_z * kDiagSplit));
+    if (plan->precision == T3_PREC_FP16X3)  // maxima (u32) then scales (f32)
+        T3_TRY(plan->scales.reserve(2 * sizeof(float) * (size_t)kNYArr * kRows * (L.n_max + 1) * pairs));
     return T3_OK;
 }
 
@@ -501,11 +738,12 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
                    const float *planes, size_t zstride, int n_z, bool jk, double *ups_out, hipStream_t s)
 {
     if (n_c <= 0) return T3_OK;
-    const int nmn = 5 * (L.n_max + 1);
+    if (L.B > kRows) return T3_ERANGE;
+    if (L.floats() >= ((size_t)1 << 31)) return T3_ERANGE;  // 32-bit plane offsets in k_contract
     const int pairs = n_z * n_z;
     const int slice = contract_slice(L, n_z);
     const int S = (n_c + slice - 1) / slice;
-    const size_t per = (size_t)nmn * L.B * L.B;
+    const size_t per = (size_t)5 * (L.n_max + 1) * L.B * L.B;
     T3_TRY(reserve_contract(plan, L, n_z));  // no-op when reserved before a capture
 
     ContractArgs a{};
@@ -520,28 +758,38 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
     a.n_z = n_z;
     a.slice = slice;
     a.S = S;
-    a.mu0 = 0;
     a.partial = plan->partial.as<double>();
-    if (plan->precision == T3_PREC_FP32) {
-        hipLaunchKernelGGL(k_contract_fp32, dim3(nmn, S, pairs), dim3(64), 0, s, a);
-    } else if (plan->precision == T3_PREC_BF16X3) {
-        const int nu = 4 * (L.n_max + 1);
-        hipLaunchKernelGGL(k_contract_split<false>, dim3(nu, S, pairs), dim3(64), 0, s, a);
-        T3_HIP_CHECK(hipGetLastError());
-        ContractArgs an = a;
-        an.mu0 = 4;
-        hipLaunchKernelGGL(k_contract_fp32, dim3(nmn - nu, S, pairs), dim3(64), 0, s, an);
-    } else {
-        hipLaunchKernelGGL(k_fp16_scales, dim3(nmn, L.B, 2 * pairs), dim3(256), 0, s, a,
-                           plan->scales.as<float>());
-        T3_HIP_CHECK(hipGetLastError());
-        a.scale = plan->scales.as<float>();
-        hipLaunchKernelGGL(k_contract_split<true>, dim3(nmn, S, pairs), dim3(64), 0, s, a);
+    const int S8 = 8 * ((S + 7) / 8);  // slices padded to whole XCD rounds
+    const dim3 gy((unsigned)((L.n_max + 1) * S8 * pairs)), gn((unsigned)((L.n_max + 2) / 2 * S8 * pairs)), blk(256);
+    switch (plan->precision) {
+        case T3_PREC_FP32:
+            hipLaunchKernelGGL((k_contract<T3_PREC_FP32, false>), gy, blk, 0, s, a);
+            break;
+        case T3_PREC_BF16X3:
+            hipLaunchKernelGGL((k_contract<T3_PREC_BF16X3, false>), gy, blk, 0, s, a);
+            break;
+        case T3_PREC_BF16X6:
+            hipLaunchKernelGGL((k_contract<T3_PREC_BF16X6, false>), gy, blk, 0, s, a);
+            break;
+        default: {
+            const int ns = kNYArr * kRows * (L.n_max + 1) * pairs;
+            unsigned *mx = plan->scales.as<unsigned>();
+            float *sc = plan->scales.as<float>() + ns;
+            hipLaunchKernelGGL(k_zero_u32, dim3((ns + 255) / 256), blk, 0, s, mx, ns);
+            hipLaunchKernelGGL(k_fp16_max, dim3(L.n_max + 1, 2 * pairs, kScaleSplit), blk, 0, s, a, mx);
+            hipLaunchKernelGGL(k_fp16_scale, dim3((ns + 255) / 256), blk, 0, s, (const unsigned *)mx, sc, ns);
+            T3_HIP_CHECK(hipGetLastError());
+            a.scale = sc;
+            hipLaunchKernelGGL((k_contract<T3_PREC_FP16X3, false>), gy, blk, 0, s, a);
+            break;
+        }
     }
     T3_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((k_contract<T3_PREC_FP32, true>), gn, blk, 0, s, a);
+    T3_HIP_CHECK(hipGetLastError());
     if (jk) {
-        hipLaunchKernelGGL(k_diag, dim3(5, L.B, n_z), dim3(256), 0, s, planes, zstride, a.ccw, n_c, L.K,
-                           L.B, L.plane_D(0), plan->diag.as<double>());
+        hipLaunchKernelGGL(k_diag, dim3(L.B, n_z, kDiagSplit), dim3(256), 0, s, planes, zstride, a.ccw, n_c,
+                           L.K, L.B, L.plane_D(0), n_z, plan->diag.as<double>());
         T3_HIP_CHECK(hipGetLastError());
     }
     const size_t tot = per * pairs;

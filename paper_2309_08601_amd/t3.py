@@ -23,7 +23,7 @@ T3_ENOMEM = -3
 T3_EHIP = -4
 T3_ELATTICE = -5
 
-PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
+PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp16x3": 2, "bf16x6": 3}
 T3_FLAG_KEEP_JK = 1
 T3_FLAG_TIMING = 2
 T3_FLAG_NO_GRAPH = 4

@@ -117,17 +117,17 @@ def test_forward_field_1m_sampled_centres(t3):
     _check(ups.cpu().numpy(), _pack(o, wl.n_max), FP32_TOL, "field_1m sample")
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
-def test_split_precision(t3, prec):
+@pytest.mark.parametrize("prec,tol", [("bf16x3", SPLIT_TOL), ("fp16x3", SPLIT_TOL), ("bf16x6", FP32_TOL)])
+def test_split_precision(t3, prec, tol):
     _, mp = _oracle()
-    cat = random_catalog(4000, 60.0, seed=55)
+    cat = random_catalog(3999, 60.0, seed=55)  # ragged: the last centre quad holds 3
     edges = np.geomspace(0.7, 20.0, 9)
     nm = 12
     lo, size = box_for(60.0)
     plan = t3.Plan(edges, nm, box_lo=lo, box_size=size, precision=prec)
     ups, _ = plan.forward(t3.DeviceCatalog.from_catalog(cat))
     o = mp.multipoles(cat, edges, nm)
-    _check(ups.cpu().numpy(), _pack(o, nm), SPLIT_TOL, prec)
+    _check(ups.cpu().numpy(), _pack(o, nm), tol, prec)
 
 
 def test_normalise_and_resum(t3):
