@@ -82,6 +82,8 @@ def main():
                     help="only run this many forward passes (for profilers), no JSON")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the tomography and gradient workloads")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "bf16x6", "fp16x3"],
+                    help="stage-2 precision of the --profile-steps passes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design "
@@ -116,8 +118,10 @@ def main():
         torch.cuda.synchronize()
         log("[bench] calibration copy: 268435456 bytes read, 268435456 bytes written")
         del src, dst
+        pplan = plan if args.precision == "fp32" else t3.Plan(
+            edges, wl.n_max, box_lo=(0, 0), box_size=box, precision=args.precision, timing=True)
         for i in range(args.profile_steps):
-            _, npairs = step(plan)
+            _, npairs = step(pplan)
             torch.cuda.synchronize()
             log(f"[bench] profile step {i}: {npairs} pairs")
         return

@@ -117,6 +117,38 @@ def test_forward_field_1m_sampled_centres(t3):
     _check(ups.cpu().numpy(), _pack(o, wl.n_max), FP32_TOL, "field_1m sample")
 
 
+_FIELD_4M = {}
+
+
+def _field_4m_reference():
+    """4M galaxies in 20 deg x 20 deg, 30 bins 0.5'-200', n_max 40 (the
+    precision workload): oracle on a sample of centres, computed once."""
+    if not _FIELD_4M:
+        _, mp = _oracle()
+        wl = WORKLOADS["field_4m"]
+        cat = make_catalogs(wl)[0]
+        idx = centre_sample(cat.n, 160, seed=13)
+        o = mp.multipoles(cat, wl.edges(), wl.n_max, centres=idx)
+        _FIELD_4M.update(wl=wl, cat=cat, idx=idx, npairs=o["npairs"], ref=_pack(o, wl.n_max))
+    return _FIELD_4M
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", FP32_TOL), ("bf16x6", FP32_TOL), ("fp16x3", SPLIT_TOL),
+                                      ("bf16x3", 2 * SPLIT_TOL)])
+def test_forward_field_4m_sampled_centres(t3, prec, tol):
+    """n_max = 40 runs the two-pass stage-1 variant and B = 30 bins nearly
+    fills the 32-row MFMA tiles.  BF16X3 keeps about 16 bits per operand, so
+    its per-(mu, n) error reaches about 1e-5 and the maximum over the 164
+    multipoles of a 160-centre sample is allowed twice that."""
+    r = _field_4m_reference()
+    wl = r["wl"]
+    lo, size = box_for(wl.side)
+    plan = t3.Plan(wl.edges(), wl.n_max, box_lo=lo, box_size=size, precision=prec)
+    ups, npairs = plan.forward(t3.DeviceCatalog.from_catalog(r["cat"]), torch.from_numpy(r["idx"]).cuda())
+    assert npairs == r["npairs"]
+    _check(ups.cpu().numpy(), r["ref"], tol, f"field_4m sample {prec}")
+
+
 @pytest.mark.parametrize("prec,tol", [("bf16x3", SPLIT_TOL), ("fp16x3", SPLIT_TOL), ("bf16x6", FP32_TOL)])
 def test_split_precision(t3, prec, tol):
     _, mp = _oracle()
