@@ -111,3 +111,34 @@ def triplets(x, y, g1, g2, w, edges: Sequence[float], n_max: int,
     if K is not None:
         out.update(ups_phi=ups_phi, N_phi=N_phi)
     return out
+
+
+def triangle_components(pos, gc, projection: str = "x"):
+    """The four natural components of one triangle's shear triple, straight
+    from the projection definitions (Sect. 2.3): gamma(X; zeta) =
+    -gamma_c e^{-2 i zeta} (eq. gammatx_def) with
+
+    * "x":        zeta_1 = (phi_1 + phi_2)/2, zeta_2 = phi_1, zeta_3 = phi_2
+                  (eq. xprojection; phi_k the polar angle of X_{k+1} - X_1);
+    * "centroid": e^{2 i zeta_k} = q_k / q_k^*, q_k the vector from the
+                  centroid to X_k (eqs. centroidprojection, QvecDef).
+
+    pos: [3, 2] float positions X_1..X_3, gc: [3] complex shears.
+    Returns [Gamma_0, Gamma_1, Gamma_2, Gamma_3] for this single triple
+    (eqs. Gamma0_def..Gamma3_def without the ensemble average).
+    """
+    pos = np.asarray(pos, dtype=np.float64)
+    gc = np.asarray(gc, dtype=np.complex128)
+    z = pos[:, 0] + 1j * pos[:, 1]
+    if projection == "x":
+        p1 = np.angle(z[1] - z[0])
+        p2 = np.angle(z[2] - z[0])
+        e2z = np.exp(1j * np.array([p1 + p2, 2.0 * p1, 2.0 * p2]))      # e^{2 i zeta}
+    elif projection == "centroid":
+        q = z - z.mean()
+        e2z = q / np.conj(q)
+    else:
+        raise ValueError(projection)
+    s = -gc / e2z                                                        # -gamma_c e^{-2 i zeta}
+    return np.array([s[0] * s[1] * s[2], np.conj(s[0]) * s[1] * s[2],
+                     s[0] * np.conj(s[1]) * s[2], s[0] * s[1] * np.conj(s[2])])

@@ -368,3 +368,66 @@ def test_zero_mean_on_pure_shape_noise(oracle_lib):
         t = part.mean(0) / (part.std(0, ddof=1) / np.sqrt(len(vals)))
         assert np.abs(t).max() < 5.5
         assert 0.6 < np.mean(t * t) < 1.5
+
+
+def test_centroid_conversion_matches_direct_projection():
+    """The x -> centroid conversion (eqs. X2Centroid0-3 and the rotation
+    factors in theta_1, theta_2, phi) equals projecting every shear along
+    its median direction directly, triangle by triangle (random shapes,
+    orientations and shears)."""
+    from oracle.brute import triangle_components
+    from oracle.projection import centroid_factors
+    rng = np.random.default_rng(2024)
+    worst = 0.0
+    for _ in range(400):
+        pos = rng.normal(size=(3, 2)) * rng.uniform(0.1, 10.0)
+        gc = rng.normal(size=3) + 1j * rng.normal(size=3)
+        gx = triangle_components(pos, gc, "x")
+        gcen = triangle_components(pos, gc, "centroid")
+        v1 = complex(*(pos[1] - pos[0]))
+        v2 = complex(*(pos[2] - pos[0]))
+        f = centroid_factors(abs(v1), abs(v2), np.angle(v2) - np.angle(v1))
+        worst = max(worst, np.max(np.abs(gx * f - gcen)) / np.max(np.abs(gcen)))
+    assert worst < 1e-12, worst
+
+
+def test_centroid_conversion_degenerate_and_equilateral():
+    """Equilateral triangle: the conversion has unit modulus and matches the
+    direct projection; collinear X_1, X_2 = centroid, X_3 = 2 X_2 (q_2 = 0,
+    t2 = 2 t1 at phi = 0, an exactly representable zero denominator) gives
+    the documented 0."""
+    from oracle.brute import triangle_components
+    from oracle.projection import centroid_factors
+    f = centroid_factors(1.0, 1.0, np.pi / 3)
+    assert np.allclose(np.abs(f), 1.0, atol=1e-14)
+    pos = np.array([[0.0, 0.0], [1.0, 0.0], [0.5, np.sqrt(3) / 2]])
+    gc = np.array([0.3 + 0.1j, -0.2 + 0.4j, 0.05 - 0.3j])
+    assert np.allclose(triangle_components(pos, gc, "x") * f, triangle_components(pos, gc, "centroid"),
+                       atol=1e-14)
+    assert np.all(centroid_factors(1.0, 2.0, 0.0) == 0.0)
+
+
+def test_mode_coupling_recovers_band_limited_gamma():
+    """Edge correction on a non-uniform angular distribution: with triplet
+    angles psi_t and weights u_t (clumpy: a strongly non-uniform N(psi)),
+    Upsilon_l = sum_t u_t Gamma(psi_t) e^{-i l psi_t}, N_m = sum_t u_t
+    e^{-i m psi_t} (the projections of eq. Upsilon0_Derivation and its
+    normaliser) and Gamma(psi) = sum_{|n| <= n_max} g_n e^{i n psi}, the
+    truncated system of eq. ModeCoupling is exact, so eq.
+    GammaMultipolesWithEC must return g_n; the plain ratio Upsilon/N_0 must
+    not."""
+    rng = np.random.default_rng(77)
+    nm, B, T = 6, 2, 4000
+    psi = np.concatenate([rng.vonmises(0.8, 3.0, T // 2), rng.uniform(0, 2 * np.pi, T // 2)])
+    u = rng.uniform(0.2, 1.8, T)
+    g = rng.standard_normal((4, 2 * nm + 1, B, B)) + 1j * rng.standard_normal((4, 2 * nm + 1, B, B))
+    ns = np.arange(-nm, nm + 1)
+    gam_t = np.einsum("mnab,nt->mtab", g, np.exp(1j * np.outer(ns, psi)))   # Gamma(psi_t)
+    ups = np.einsum("mtab,lt->mlab", gam_t * u[None, :, None, None], np.exp(-1j * np.outer(ns, psi)))
+    ms = np.arange(-2 * nm, 2 * nm + 1)
+    Nm = np.einsum("t,mt->m", u, np.exp(-1j * np.outer(ms, psi)))
+    N = np.broadcast_to(Nm[:, None, None], (ms.size, B, B)).copy()
+    got = mp.mode_coupling_correct(ups, N, nm)
+    assert _rel(got, g) < 1e-10
+    plain, _ = mp.normalise(ups, N)
+    assert _rel(plain, g) > 1e-2
