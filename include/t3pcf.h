@@ -41,12 +41,17 @@
  * over neighbours j of centre i in bin b (eq. Gn_disc).
  *
  * Multipole output layout ("ups"): complex128 as interleaved (re, im)
- * doubles, row-major [5][n_max+1][B][B] with index 0..3 = Upsilon_0..3 and
- * 4 = N, orders n = 0..n_max.  Negative orders follow from the symmetries
- * of Appendix A: Upsilon_{0,-n}(b1,b2) = Upsilon_{0,n}(b2,b1) (same for 1
- * and N), Upsilon_{2,-n}(b1,b2) = Upsilon_{3,n}(b2,b1).
- * Tomographic output: [n_z][n_z][n_z][5][n_max+1][B][B] indexed
- * (Z1 centres, Z2 = b1-side neighbours, Z3 = b2-side neighbours), eq. tomoGn.
+ * doubles, row-major, one set = 4 (n_max+1) + (w_max+1) blocks of [B][B]:
+ * Upsilon_{mu,n} for mu = 0..3, n = 0..n_max (block mu (n_max+1) + n), then
+ * N_n for n = 0..w_max (block 4 (n_max+1) + n).  w_max = n_max, so a set is
+ * [5][n_max+1][B][B], unless the plan has T3_FLAG_EDGE_CORRECT, which makes
+ * w_max = 2 n_max (the mode-coupling matrix needs N_{l-n}, |l-n| <= 2 n_max).
+ * Negative orders follow from the symmetries of Appendix A:
+ * Upsilon_{0,-n}(b1,b2) = Upsilon_{0,n}(b2,b1) (same for 1), Upsilon_{2,-n}
+ * (b1,b2) = Upsilon_{3,n}(b2,b1), N_{-n}(b1,b2) = N_n(b1,b2)*.
+ * Tomographic output: [n_z][n_z][n_z][set] indexed (Z1 centres, Z2 = b1-side
+ * neighbours, Z3 = b2-side neighbours), eq. tomoGn; the symmetries map a set
+ * to the one with Z2 and Z3 swapped.
  */
 #ifndef T3PCF_H
 #define T3PCF_H
@@ -78,6 +83,9 @@ extern "C" {
                            /* also runs the schedule eagerly (no graph)           */
 #define T3_FLAG_NO_GRAPH 4u /* launch the chunk schedule eagerly instead of as one  */
                             /* captured HIP graph                                  */
+#define T3_FLAG_EDGE_CORRECT 8u /* forward: N_n up to 2 n_max (stage 1 sums W_m to  */
+                                /* 2 n_max); t3_normalise_resum: edge-corrected    */
+                                /* Gamma_n (eq. GammaMultipolesWithEC).  No adjoint. */
 
 typedef struct {
     int32_t n_bins;        /* B >= 1                                         */
@@ -156,10 +164,17 @@ int t3_harmonics(t3_plan *plan, const t3_catalog *cat, const int32_t *centres,
                  void *stream);
 
 /* Normalisation and resummation in FP64 (Sect. 3.4, eq. Gamma0_binned).
- * ups:       DEVICE double [n_sets][5][n_max+1][B][B][2] (t3_forward output,
- *            n_sets = 1, or n_z^3 for tomography).
+ * ups:       DEVICE double, n_sets sets in the t3_forward output layout
+ *            (n_sets = 1, or n_z^3 for tomography).
  * gamma_n:   DEVICE double [n_sets][4][n_max+1][B][B][2]:
- *            Gamma_{mu,n} = Upsilon_{mu,n} / N_0 (0 where N_0 == 0).
+ *            Gamma_{mu,n} = Upsilon_{mu,n} / N_0 (0 where N_0 == 0), or, for
+ *            a plan with T3_FLAG_EDGE_CORRECT, the edge-corrected multipoles
+ *            of eqs. (ModeCoupling), (GammaMultipolesWithEC): for every bin
+ *            pair the (2 n_max + 1)-dimensional Hermitian Toeplitz system
+ *            sum_{|n|<=n_max} N_{l-n} Gamma_{mu,n} = Upsilon_{mu,l},
+ *            |l| <= n_max, solved in FP64 by the Levinson recursion (0 where
+ *            N_0 == 0; a numerically singular system yields non-finite
+ *            entries for that bin pair only, with no error code).
  * gamma_phi: DEVICE double [n_sets][4][B][B][n_phi][2] or NULL:
  *            sum_{|n|<=n_max} Gamma_{mu,n} s_n(Phi_k), with angular bins
  *            Phi_k = [2 pi k / n_phi, 2 pi (k+1) / n_phi) and
@@ -170,6 +185,20 @@ int t3_normalise_resum(t3_plan *plan, const double *ups, int32_t n_sets,
                        int32_t n_phi, double *gamma_n, double *gamma_phi,
                        void *stream);
 
+/* x -> centroid projection of the resummed natural components (Sect. 2.3,
+ * eqs. X2Centroid0-X2Centroid3 with the rotation factors written in
+ * theta_1, theta_2 and phi).  The pointwise conversion is evaluated at one
+ * representative triangle per bin: radii theta[b1], theta[b2] and the
+ * angular-bin centre phi_k = 2 pi (k + 1/2) / n_phi.
+ * gamma_phi_x:    DEVICE double [n_sets][4][B][B][n_phi][2] (t3_normalise_resum);
+ * theta:          HOST double [B] arcmin, or NULL for the centres
+ *                 (edges[b] + edges[b+1]) / 2 of the plan's bins;
+ * gamma_phi_cent: DEVICE double, same layout (may alias gamma_phi_x).
+ * Where a conversion factor's denominator is exactly zero (a collinear
+ * configuration in which a median direction vanishes) the output is 0. */
+int t3_x_to_centroid(t3_plan *plan, const double *gamma_phi_x, int32_t n_sets, int32_t n_phi,
+                     const double *theta, double *gamma_phi_cent, void *stream);
+
 /* Reverse of the normalisation Gamma_{mu,n} = Upsilon_{mu,n} / N_0 (mu < 4).
  * ups: DEVICE [n_sets][5][n_max+1][B][B][2] forward multipoles;
  * grad_gamma_n: DEVICE [n_sets][4][n_max+1][B][B][2] holding dL/dRe and
@@ -177,6 +206,7 @@ int t3_normalise_resum(t3_plan *plan, const double *ups, int32_t n_sets,
  * receives dL/dUpsilon for mu < 4 and dL/dN_0 in the real part of the
  * (mu = 4, n = 0) entries (0 elsewhere).  Bin pairs with N_0 = 0 pass no
  * gradient. */
+/* (Not available for plans with T3_FLAG_EDGE_CORRECT: T3_EINVAL.) */
 int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets,
                           const double *grad_gamma_n, double *grad_ups, void *stream);
 
@@ -188,6 +218,7 @@ int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets,
  * dL/dg2, dL/dw of every galaxy.  Neighbour contributions are summed with
  * FP32 atomics, so results can differ between calls at rounding level.
  * Synchronises the stream before returning. */
+/* (Not available for plans with T3_FLAG_EDGE_CORRECT: T3_EINVAL.) */
 int t3_backward(t3_plan *plan, const t3_catalog *cat, const double *grad_ups,
                 float *grad_g1, float *grad_g2, float *grad_w, void *stream);
 

@@ -454,6 +454,7 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
     if (!sv) return fail(T3_ERANGE, "t3_backward: n_max above the compiled variants");
     ChunkLayout L;
     L.n_max = plan->n_max;
+    L.w_max = plan->w_max;
     L.B = plan->B;
     L.K = choose_chunk(plan, L);
     const int CS = coef_size(sv->cap);

@@ -124,6 +124,7 @@ static ChunkLayout layout_of(const t3_plan *plan)
 {
     ChunkLayout L;
     L.n_max = plan->n_max;
+    L.w_max = plan->w_max;
     L.B = plan->B;
     L.K = 0;
     L.K = choose_chunk(plan, L);
@@ -164,7 +165,7 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
     for (int z = 0; z < n_z; ++z) order[z] = z;
     for (int i = 1; i < n_z; ++i)
         for (int j = i; j > 0 && cats[order[j]].n > cats[order[j - 1]].n; --j) std::swap(order[j], order[j - 1]);
-    const size_t per_set = (size_t)2 * 5 * (plan->n_max + 1) * plan->B * plan->B;
+    const size_t per_set = (size_t)2 * L.out_blocks() * plan->B * plan->B;
     const size_t n_out = per_set * (size_t)n_z * n_z * n_z;
     const size_t zstride = L.floats();
     // every buffer the schedule touches is reserved before it is recorded
@@ -260,7 +261,7 @@ int t3_plan_create(const t3_params *p, t3_plan **out)
         if (p->n_max < 0 || p->n_max > 64) return fail(T3_ERANGE, "t3_plan_create: n_max must be in [0, 64]");
         if (p->precision < T3_PREC_FP32 || p->precision > T3_PREC_BF16X6)
             return fail(T3_EINVAL, "t3_plan_create: unknown precision");
-        if (p->flags & ~(T3_FLAG_KEEP_JK | T3_FLAG_TIMING | T3_FLAG_NO_GRAPH))
+        if (p->flags & ~(T3_FLAG_KEEP_JK | T3_FLAG_TIMING | T3_FLAG_NO_GRAPH | T3_FLAG_EDGE_CORRECT))
             return fail(T3_EINVAL, "t3_plan_create: unknown flag");
         const double unit = p->lattice_unit == 0.0 ? std::ldexp(1.0, -16) : p->lattice_unit;
         if (!(unit > 0.0) || !std::isfinite(unit)) return fail(T3_EINVAL, "t3_plan_create: bad lattice unit");
@@ -285,6 +286,7 @@ int t3_plan_create(const t3_params *p, t3_plan **out)
         if (!plan) return fail(T3_ENOMEM, "t3_plan_create: host allocation failed");
         plan->B = p->n_bins;
         plan->n_max = p->n_max;
+        plan->w_max = (p->flags & T3_FLAG_EDGE_CORRECT) ? 2 * p->n_max : p->n_max;
         plan->precision = p->precision;
         plan->flags = p->flags;
         plan->unit = unit;
@@ -432,11 +434,26 @@ int t3_normalise_resum(t3_plan *plan, const double *ups, int32_t n_sets, int32_t
     return normalise_resum(plan, ups, n_sets, n_z, n_phi, gamma_n, gamma_phi, (hipStream_t)stream);
 }
 
+int t3_x_to_centroid(t3_plan *plan, const double *gamma_phi_x, int32_t n_sets, int32_t n_phi,
+                     const double *theta, double *gamma_phi_cent, void *stream)
+{
+    if (!plan || !gamma_phi_x || !gamma_phi_cent) return fail(T3_EINVAL, "t3_x_to_centroid: null argument");
+    if (n_sets < 1) return fail(T3_EINVAL, "t3_x_to_centroid: n_sets must be >= 1");
+    if (n_phi < 1 || n_phi > 4096) return fail(T3_ERANGE, "t3_x_to_centroid: n_phi must be in [1, 4096]");
+    if (theta)
+        for (int b = 0; b < plan->B; ++b)
+            if (!(theta[b] > 0.0) || !std::isfinite(theta[b]))
+                return fail(T3_EINVAL, "t3_x_to_centroid: theta must be positive and finite");
+    return x_to_centroid(plan, gamma_phi_x, n_sets, n_phi, theta, gamma_phi_cent, (hipStream_t)stream);
+}
+
 int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets, const double *grad_gamma_n,
                           double *grad_ups, void *stream)
 {
     if (!plan || !ups || !grad_gamma_n || !grad_ups)
         return fail(T3_EINVAL, "t3_normalise_backward: null argument");
+    if (plan->flags & T3_FLAG_EDGE_CORRECT)
+        return fail(T3_EINVAL, "t3_normalise_backward: no adjoint of the edge-corrected normalisation");
     if (n_sets < 1) return fail(T3_EINVAL, "t3_normalise_backward: n_sets must be >= 1");
     return normalise_backward(plan, ups, grad_gamma_n, n_sets, grad_ups, (hipStream_t)stream);
 }
@@ -482,7 +499,8 @@ int t3_autotune(t3_plan *plan, const t3_catalog *cats, int32_t n_z, int64_t samp
                                hipMemcpyHostToDevice));
         const int32_t *cl[8];
         for (int z = 0; z < n_z; ++z) cl[z] = plan->tune_idx.as<int32_t>() + off[z];
-        const size_t n_out = (size_t)2 * 5 * (plan->n_max + 1) * plan->B * plan->B * n_z * n_z * n_z;
+        const size_t n_out = (size_t)2 * (4 * (plan->n_max + 1) + plan->w_max + 1) * plan->B * plan->B *
+                             n_z * n_z * n_z;
         T3_TRY(plan->tune_out.reserve(sizeof(double) * n_out));
 
         const double area = (double)plan->box_size * (double)plan->box_size;
@@ -558,6 +576,8 @@ int t3_backward(t3_plan *plan, const t3_catalog *cat, const double *grad_ups, fl
     try {
         if (!plan || !grad_ups || !grad_g1 || !grad_g2 || !grad_w)
             return fail(T3_EINVAL, "t3_backward: null argument");
+        if (plan->flags & T3_FLAG_EDGE_CORRECT)
+            return fail(T3_EINVAL, "t3_backward: no adjoint for plans with T3_FLAG_EDGE_CORRECT");
         T3_TRY(check_catalog(cat, "t3_backward"));
         return backward(plan, *cat, grad_ups, grad_g1, grad_g2, grad_w, (hipStream_t)stream);
     } catch (...) {

@@ -57,9 +57,10 @@ struct ContractArgs {
     const float4 *ccw;   // centre factors (w g1, w g2, w, 0), chunk-relative
     const float *scale;  // fp16 row scales [pair][n][kNYArr][kRows] or null
     int n_c, K, B, n_max, n_z;
+    int w_max;           // largest order of N (n_max, or 2 n_max for mode coupling)
     int slice;           // centres per slice (multiple of kRun)
     int S;               // slices
-    double *partial;     // [pair][S][5][n_max+1][B][B][2]
+    double *partial;     // [pair][S][4 (n_max+1) + w_max + 1][B][B][2]
 };
 
 __device__ __forceinline__ void pair_planes(const ContractArgs &a, int pair, const float *&px,
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
     // planes (every pair shares its X catalog with n_z - 1 others and its Y
     // catalog likewise; neighbouring orders share planes) run on one XCD at
     // about the same time and meet in its L2.
-    const int ngrp = NK ? (a.n_max + 2) / 2 : a.n_max + 1;
+    const int ngrp = NK ? (a.w_max + 2) / 2 : a.n_max + 1;
     const int pairs = a.n_z * a.n_z;
     const int xcd = blockIdx.x & 7;
     int jx = blockIdx.x >> 3;
@@ -273,15 +274,15 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
         ib = (mu == 0 || mu == 2) ? 3 : (mu == 1 ? 4 : 5);
         cj = mu == 3;
     }
-    const bool active = n <= nm;
+    const bool active = n <= (NK ? a.w_max : nm);
 
     // staging role: bin sb, centre quad sq, side sh (0: X from px, 1: Y from py)
     const int sb = tid & 31, sq = (tid >> 5) & 3;
     const int sh = __builtin_amdgcn_readfirstlane(tid >> 7);
     int pl[NL];
     if constexpr (NK) {
-        pl[0] = plane_w(min(2 * grp, nm), nm);
-        pl[1] = plane_w(min(2 * grp + 1, nm), nm);
+        pl[0] = plane_w(min(2 * grp, a.w_max), nm);
+        pl[1] = plane_w(min(2 * grp + 1, a.w_max), nm);
     } else {
         pl[0] = plane_g(sh ? -grp - 3 : grp - 3, nm);
         pl[1] = plane_g(sh ? -grp - 1 : grp - 1, nm);
@@ -489,7 +490,9 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
     }
     if (!active) return;
     promote();
-    double *dst = a.partial + ((((size_t)pair * a.S + sl) * 5 + mu) * (nm + 1) + n) * a.B * a.B * 2;
+    const int nq = 4 * (nm + 1) + a.w_max + 1;               // B x B blocks per slice
+    const int q = mu < 4 ? mu * (nm + 1) + n : 4 * (nm + 1) + n;  // this block
+    double *dst = a.partial + (((size_t)pair * a.S + sl) * nq + q) * a.B * a.B * 2;
     if constexpr (NK) {
         // one part per wavefront: real parts in dr of wave r = 0, imaginary in r = 1
         const int col = lane & 31;
@@ -647,18 +650,20 @@ __global__ __launch_bounds__(256) void k_diag(const float *planes0, size_t zstri
     }
 }
 
-// out[pair][mu][n][b1][b2] += sum_s partial[pair][s][...] - [b1 == b2][Z2 == Z3] E_{Z2,mu}(b1)
-__global__ void k_reduce(const double *partial, int S, int n_max, int B, int n_z, const double *E,
-                         int jk, double *out)
+// out[pair][block][b1][b2] += sum_s partial[pair][s][...] - [b1 == b2][Z2 == Z3] E_{Z2,mu}(b1),
+// blocks mu (n_max+1) + n (Upsilon) and 4 (n_max+1) + n (N, every order)
+__global__ void k_reduce(const double *partial, int S, int n_max, int w_max, int B, int n_z,
+                         const double *E, int jk, double *out)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per = (int64_t)5 * (n_max + 1) * B * B;
+    const int64_t per = (int64_t)(4 * (n_max + 1) + w_max + 1) * B * B;
     if (t >= per * n_z * n_z) return;
     const int pair = (int)(t / per);
     const int64_t e = t % per;
     const int b2 = (int)(e % B);
     const int b1 = (int)((e / B) % B);
-    const int mu = (int)(e / ((int64_t)(n_max + 1) * B * B));
+    const int qb = (int)(e / ((int64_t)B * B));
+    const int mu = qb < 4 * (n_max + 1) ? qb / (n_max + 1) : 4;
     const double *p = partial + 2 * ((int64_t)pair * S * per + e);
     double re = 0.0, im = 0.0;
     for (int s = 0; s < S; ++s) {
@@ -726,7 +731,7 @@ int reserve_contract(t3_plan *plan, const ChunkLayout &L, int n_z)
 {
     const int pairs = n_z * n_z;
     const int S = (L.K + contract_slice(L, n_z) - 1) / contract_slice(L, n_z);
-    const size_t per = (size_t)5 * (L.n_max + 1) * L.B * L.B;
+    const size_t per = (size_t)L.out_blocks() * L.B * L.B;
     T3_TRY(plan->partial.reserve(sizeof(double) * 2 * per * (size_t)S * pairs));
     T3_TRY(plan->diag.reserve(sizeof(double) * 2 * 5 * (size_t)L.B * n_z * kDiagSplit));
     if (plan->precision == T3_PREC_FP16X3)  // maxima (u32) then scales (f32)
@@ -743,7 +748,7 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
     const int pairs = n_z * n_z;
     const int slice = contract_slice(L, n_z);
     const int S = (n_c + slice - 1) / slice;
-    const size_t per = (size_t)5 * (L.n_max + 1) * L.B * L.B;
+    const size_t per = (size_t)L.out_blocks() * L.B * L.B;
     T3_TRY(reserve_contract(plan, L, n_z));  // no-op when reserved before a capture
 
     ContractArgs a{};
@@ -756,11 +761,12 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
     a.B = L.B;
     a.n_max = L.n_max;
     a.n_z = n_z;
+    a.w_max = L.w_max;
     a.slice = slice;
     a.S = S;
     a.partial = plan->partial.as<double>();
     const int S8 = 8 * ((S + 7) / 8);  // slices padded to whole XCD rounds
-    const dim3 gy((unsigned)((L.n_max + 1) * S8 * pairs)), gn((unsigned)((L.n_max + 2) / 2 * S8 * pairs)), blk(256);
+    const dim3 gy((unsigned)((L.n_max + 1) * S8 * pairs)), gn((unsigned)((L.w_max + 2) / 2 * S8 * pairs)), blk(256);
     switch (plan->precision) {
         case T3_PREC_FP32:
             hipLaunchKernelGGL((k_contract<T3_PREC_FP32, false>), gy, blk, 0, s, a);
@@ -794,7 +800,7 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
     }
     const size_t tot = per * pairs;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                       (const double *)plan->partial.as<double>(), S, L.n_max, L.B, n_z,
+                       (const double *)plan->partial.as<double>(), S, L.n_max, L.w_max, L.B, n_z,
                        (const double *)plan->diag.as<double>(), jk ? 1 : 0, ups_out);
     T3_HIP_CHECK(hipGetLastError());
     return T3_OK;

@@ -337,29 +337,38 @@ PassDesc make_pass()
 }
 
 // Variant table: a single pass for n_max up to the capacity C (orders
-// 1..C+3 for G, 1..C for W); two passes beyond 32.
+// 1..C+3 for G, 1..C for W); two passes beyond 32.  wext: the W-only pass
+// over orders C+1..2C, run when the plan needs N_n up to 2 n_max (mode
+// coupling); its power recurrence starts from the FP64 anchor below C+1.
 struct Variant {
     int cap;
     int npass;
     PassDesc pass[2];
+    PassDesc wext;
 };
+
+template <int C>
+PassDesc make_wext()
+{
+    return make_pass<C + 1, C, C + 1, 2 * C, false>();
+}
 
 const std::vector<Variant> &variants()
 {
     static const std::vector<Variant> v = {
-        {2, 1, {make_pass<1, 5, 1, 2, true>()}},
-        {4, 1, {make_pass<1, 7, 1, 4, true>()}},
-        {8, 1, {make_pass<1, 11, 1, 8, true>()}},
-        {10, 1, {make_pass<1, 13, 1, 10, true>()}},
-        {12, 1, {make_pass<1, 15, 1, 12, true>()}},
-        {16, 1, {make_pass<1, 19, 1, 16, true>()}},
-        {20, 1, {make_pass<1, 23, 1, 20, true>()}},
-        {24, 1, {make_pass<1, 27, 1, 24, true>()}},
-        {30, 1, {make_pass<1, 33, 1, 30, true>()}},
-        {32, 1, {make_pass<1, 35, 1, 32, true>()}},
-        {40, 2, {make_pass<1, 22, 1, 20, true>(), make_pass<23, 43, 21, 40, false>()}},
-        {48, 2, {make_pass<1, 26, 1, 24, true>(), make_pass<27, 51, 25, 48, false>()}},
-        {64, 2, {make_pass<1, 34, 1, 32, true>(), make_pass<35, 67, 33, 64, false>()}},
+        {2, 1, {make_pass<1, 5, 1, 2, true>()}, make_wext<2>()},
+        {4, 1, {make_pass<1, 7, 1, 4, true>()}, make_wext<4>()},
+        {8, 1, {make_pass<1, 11, 1, 8, true>()}, make_wext<8>()},
+        {10, 1, {make_pass<1, 13, 1, 10, true>()}, make_wext<10>()},
+        {12, 1, {make_pass<1, 15, 1, 12, true>()}, make_wext<12>()},
+        {16, 1, {make_pass<1, 19, 1, 16, true>()}, make_wext<16>()},
+        {20, 1, {make_pass<1, 23, 1, 20, true>()}, make_wext<20>()},
+        {24, 1, {make_pass<1, 27, 1, 24, true>()}, make_wext<24>()},
+        {30, 1, {make_pass<1, 33, 1, 30, true>()}, make_wext<30>()},
+        {32, 1, {make_pass<1, 35, 1, 32, true>()}, make_wext<32>()},
+        {40, 2, {make_pass<1, 22, 1, 20, true>(), make_pass<23, 43, 21, 40, false>()}, make_wext<40>()},
+        {48, 2, {make_pass<1, 26, 1, 24, true>(), make_pass<27, 51, 25, 48, false>()}, make_wext<48>()},
+        {64, 2, {make_pass<1, 34, 1, 32, true>(), make_pass<35, 67, 33, 64, false>()}, make_wext<64>()},
     };
     return v;
 }
@@ -386,7 +395,7 @@ std::vector<short> dest_table(const PassDesc &p, const ChunkLayout &L)
     }
     for (int k = 0; k < NW; ++k) {
         const int m = p.wa + k;
-        if (m <= nm) {
+        if (m <= L.w_max) {
             d[4 * NG + 2 * k] = (short)L.plane_W(m, 0);
             d[4 * NG + 2 * k + 1] = (short)L.plane_W(m, 1);
         }
@@ -418,11 +427,17 @@ int scan_prepare(t3_plan *plan)
     if (vi < 0) return fail(T3_ERANGE, "n_max above the largest compiled variant");
     ChunkLayout L;
     L.n_max = plan->n_max;
+    L.w_max = plan->w_max;
     L.B = plan->B;
     std::vector<short> all;
     for (int p = 0; p < vars[vi].npass; ++p) {
         plan->scan_dest_off[p] = all.size();
         auto d = dest_table(vars[vi].pass[p], L);
+        all.insert(all.end(), d.begin(), d.end());
+    }
+    if (plan->w_max > vars[vi].cap) {  // W orders beyond the main passes
+        plan->scan_dest_off[vars[vi].npass] = all.size();
+        auto d = dest_table(vars[vi].wext, L);
         all.insert(all.end(), d.begin(), d.end());
     }
     T3_TRY(plan->dest.reserve(all.size() * sizeof(short)));
@@ -474,14 +489,16 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
         a.queue = nullptr;
         a.grab = 0;
     }
-    for (int p = 0; p < var.npass; ++p) {
+    const int npass = var.npass + (plan->w_max > var.cap ? 1 : 0);
+    for (int p = 0; p < npass; ++p) {
+        const PassDesc &pd = p < var.npass ? var.pass[p] : var.wext;
         a.dest = plan->dest.as<short>() + plan->scan_dest_off[p];
         a.npairs = p == 0 ? npairs : nullptr;  // count pairs once
         if (a.queue) {
             // persistent grid over every (centre, catalog) task
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, a.queue);
             T3_HIP_CHECK(hipGetLastError());
-            hipLaunchKernelGGL(var.pass[p].kernel_general, dim3((unsigned)nwg), dim3(64 * kWaves), 0, s, a);
+            hipLaunchKernelGGL(pd.kernel_general, dim3((unsigned)nwg), dim3(64 * kWaves), 0, s, a);
             T3_HIP_CHECK(hipGetLastError());
         } else {
             // one launch of the single-catalog kernel per catalog, densest first
@@ -492,7 +509,7 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
                 a1.sw[0] = a.sw[z];
                 a1.out[0] = a.out[z];
                 a1.n_z = 1;
-                hipLaunchKernelGGL(var.pass[p].kernel, dim3((unsigned)nwg1), dim3(64 * kWaves), 0, s, a1);
+                hipLaunchKernelGGL(pd.kernel, dim3((unsigned)nwg1), dim3(64 * kWaves), 0, s, a1);
                 T3_HIP_CHECK(hipGetLastError());
             }
         }

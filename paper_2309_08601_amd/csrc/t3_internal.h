@@ -45,20 +45,24 @@ struct DevBuf {
 //     ((p * (K/4) + i/4) * B + b) * 4 + (i & 3)
 // so that four consecutive centres of one bin are one 16-byte vector and a
 // row of B bins for those four centres is contiguous (stage-2 operand load).
-// Plane numbering, with n_g = 2 n_max + 3 G orders m = -n_max-3 .. n_max-1:
+// Plane numbering, with n_g = 2 n_max + 3 G orders m = -n_max-3 .. n_max-1
+// and W orders m = 0 .. w_max (w_max = n_max, or 2 n_max when the
+// mode-coupling matrix is wanted):
 //     G_m   : 2 (m + n_max + 3) + {0 re, 1 im}
-//     W_m   : 2 n_g + 2 m + {0, 1},          m = 0 .. n_max
-//     D     : 2 n_g + 2 (n_max + 1) + {0..6} = D6 re, D6 im, D2 re, D2 im,
+//     W_m   : 2 n_g + 2 m + {0, 1},          m = 0 .. w_max
+//     D     : 2 n_g + 2 (w_max + 1) + {0..6} = D6 re, D6 im, D2 re, D2 im,
 //             DA re, DA im, DW
 struct ChunkLayout {
-    int n_max = 0, B = 0, K = 0;
+    int n_max = 0, w_max = 0, B = 0, K = 0;
     int n_g() const { return 2 * n_max + 3; }
     int plane_G(int m, int part) const { return 2 * (m + n_max + 3) + part; }
     int plane_W(int m, int part) const { return 2 * n_g() + 2 * m + part; }
-    int plane_D(int d) const { return 2 * n_g() + 2 * (n_max + 1) + d; }
+    int plane_D(int d) const { return 2 * n_g() + 2 * (w_max + 1) + d; }
     int n_planes() const { return plane_D(0) + 7; }
     size_t plane_stride() const { return (size_t)K * B; }  // floats per plane
     size_t floats() const { return (size_t)n_planes() * plane_stride(); }
+    // output blocks of B x B complex per set: Upsilon_{0..3, n <= n_max}, N_{n <= w_max}
+    int out_blocks() const { return 4 * (n_max + 1) + w_max + 1; }
 };
 
 __host__ __device__ inline size_t chunk_offset(int p, int i, int b, int K, int B)
@@ -99,6 +103,7 @@ struct CentreSet {
 // ---------------------------------------------------------------- plan
 struct t3_plan {
     int B = 0, n_max = 0, precision = 0;
+    int w_max = 0;  // n_max, or 2 n_max with T3_FLAG_EDGE_CORRECT
     uint32_t flags = 0;
     double unit = 0;
     std::vector<double> edges_lat;  // [B+1] edges in lattice steps
@@ -128,7 +133,7 @@ struct t3_plan {
     t3::DevBuf misc;      // adjoint scratch
     t3::DevBuf misc2;
     int scan_var = -1;          // stage-1 variant index (see scan.hip)
-    size_t scan_dest_off[2] = {0, 0};
+    size_t scan_dest_off[3] = {0, 0, 0};  // main passes, then the W extension
 
     // optional stage timing (T3_FLAG_TIMING)
     std::vector<hipEvent_t> events;  // pool, pairs (start, stop)
@@ -166,6 +171,8 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
                    hipStream_t s);
 int normalise_resum(t3_plan *plan, const double *ups, int n_sets, int n_z, int n_phi,
                     double *gamma_n, double *gamma_phi, hipStream_t s);
+int x_to_centroid(t3_plan *plan, const double *in, int n_sets, int n_phi, const double *theta, double *out,
+                  hipStream_t s);
 int harmonics_export(t3_plan *plan, const CentreSet &cs, const ChunkLayout &L, const float *planes,
                      int64_t c0, int n_c, float *G, float *W, float *D, hipStream_t s);
 int normalise_backward(t3_plan *plan, const double *ups, const double *ggam, int n_sets, double *gups,

@@ -27,6 +27,7 @@ PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp16x3": 2, "bf16x6": 3}
 T3_FLAG_KEEP_JK = 1
 T3_FLAG_TIMING = 2
 T3_FLAG_NO_GRAPH = 4
+T3_FLAG_EDGE_CORRECT = 8
 
 
 class t3_params(ctypes.Structure):
@@ -74,6 +75,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.t3_harmonics.restype = ctypes.c_int
     lib.t3_normalise_resum.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     lib.t3_normalise_resum.restype = ctypes.c_int
+    lib.t3_x_to_centroid.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), vp, vp]
+    lib.t3_x_to_centroid.restype = ctypes.c_int
     lib.t3_normalise_backward.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
     lib.t3_normalise_backward.restype = ctypes.c_int
     lib.t3_backward.argtypes = [vp, P(t3_catalog), vp, vp, vp, vp, vp]
@@ -135,14 +138,16 @@ class Plan:
     def __init__(self, edges: Sequence[float], n_max: int, box_lo=(0, 0), box_size: int = 1 << 30,
                  precision: str = "fp32", keep_jk: bool = False, lattice_unit: float = 0.0,
                  cell_arcmin: float = 0.0, chunk_centres: int = 0, timing: bool = False,
-                 graph: bool = True, scan_mode: int = 0):
+                 graph: bool = True, scan_mode: int = 0, edge_correct: bool = False):
         self.edges = np.ascontiguousarray(edges, dtype=np.float64)
         self.B = len(self.edges) - 1
         self.n_max = int(n_max)
+        self.edge_correct = bool(edge_correct)
+        self.w_max = 2 * self.n_max if self.edge_correct else self.n_max
         p = t3_params(self.B, self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.n_max,
                       PRECISIONS[precision],
                       (T3_FLAG_KEEP_JK if keep_jk else 0) | (T3_FLAG_TIMING if timing else 0)
-                      | (0 if graph else T3_FLAG_NO_GRAPH),
+                      | (0 if graph else T3_FLAG_NO_GRAPH) | (T3_FLAG_EDGE_CORRECT if edge_correct else 0),
                       float(lattice_unit),
                       int(box_lo[0]), int(box_lo[1]), int(box_size), float(cell_arcmin),
                       int(chunk_centres), int(scan_mode))
@@ -162,7 +167,22 @@ class Plan:
             pass
 
     def _out_shape(self, sets: int = 1):
+        if self.edge_correct:  # Upsilon blocks then N_0..N_{2 n_max}
+            return (sets, 4 * (self.n_max + 1) + self.w_max + 1, self.B, self.B, 2)
         return (sets, 5, self.n_max + 1, self.B, self.B, 2)
+
+    def _trail(self) -> int:
+        return len(self._out_shape()) - 1  # trailing dims of one set (real view)
+
+    def split_ups(self, ups: torch.Tensor):
+        """(Upsilon [..., 4, n_max+1, B, B], N [..., w_max+1, B, B]) of a
+        forward output (complex)."""
+        nm, B = self.n_max, self.B
+        if not self.edge_correct:
+            return ups[..., :4, :, :, :], ups[..., 4, :, :, :]
+        lead = ups.shape[:-3]
+        u4 = ups[..., :4 * (nm + 1), :, :].reshape(lead + (4, nm + 1, B, B))
+        return u4, ups[..., 4 * (nm + 1):, :, :]
 
     def forward(self, cat: DeviceCatalog, centres: Optional[torch.Tensor] = None,
                 out: Optional[torch.Tensor] = None):
@@ -223,7 +243,7 @@ class Plan:
         """Gamma_{mu,n} = Upsilon/N_0 [.., 4, n_max+1, B, B] and the resummed
         Gamma(b1, b2, Phi_k) [.., 4, B, B, n_phi] (complex128)."""
         u = torch.view_as_real(ups).contiguous() if ups.is_complex() else ups.contiguous()
-        lead = u.shape[:-5]
+        lead = u.shape[:-self._trail()]
         sets = int(np.prod(lead)) if len(lead) else 1
         gn = torch.empty(lead + (4, self.n_max + 1, self.B, self.B, 2), dtype=torch.float64,
                          device=u.device)
@@ -232,6 +252,25 @@ class Plan:
             gp = torch.empty(lead + (4, self.B, self.B, n_phi, 2), dtype=torch.float64, device=u.device)
         _check(_lib.t3_normalise_resum(self._h, _ptr(u), sets, int(n_phi), _ptr(gn), _ptr(gp), _stream()))
         return torch.view_as_complex(gn), (None if gp is None else torch.view_as_complex(gp))
+
+    def x_to_centroid(self, gamma_phi: torch.Tensor, theta: Optional[Sequence[float]] = None) -> torch.Tensor:
+        """x -> centroid projection of a resummed Gamma [..., 4, B, B, n_phi]
+        (complex128), factors at (theta[b1], theta[b2], angular-bin centre);
+        theta defaults to the radial bin centres."""
+        g = torch.view_as_real(gamma_phi).contiguous() if gamma_phi.is_complex() else gamma_phi.contiguous()
+        n_phi = int(g.shape[-2])
+        lead = g.shape[:-5]
+        sets = int(np.prod(lead)) if len(lead) else 1
+        out = torch.empty_like(g)
+        th = None
+        keep = None
+        if theta is not None:
+            keep = np.ascontiguousarray(theta, dtype=np.float64)
+            if keep.shape != (self.B,):
+                raise ValueError("theta needs one radius per bin")
+            th = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        _check(_lib.t3_x_to_centroid(self._h, _ptr(g), sets, n_phi, th, _ptr(out), _stream()))
+        return torch.view_as_complex(out)
 
     def normalise_backward(self, ups: torch.Tensor, grad_gamma_n: torch.Tensor) -> torch.Tensor:
         """dL/dUpsilon (and dL/dN_0) from dL/dGamma_n; real views [..., 2]."""

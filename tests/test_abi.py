@@ -63,7 +63,7 @@ def _params(**kw):
     (dict(n_max=65), -2),
     (dict(n_max=-1), -2),
     (dict(precision=7), -1),
-    (dict(flags=8), -1),
+    (dict(flags=16), -1),
     (dict(box_size=0), -1),
     (dict(box_size=1 << 40), -2),
 ])
@@ -87,3 +87,22 @@ def test_plan_create_and_destroy_ok(lib):
     assert h.value
     t3._lib.t3_plan_destroy(h)
     assert t3._lib.t3_error_string(-5) == b"position outside the lattice box"
+
+
+def test_edge_correct_plan_rejects_adjoint_and_bad_theta(lib):
+    """Argument errors of the edge-correction and centroid entry points are
+    caught before any launch (no GPU needed)."""
+    pytest.importorskip("torch")
+    from paper_2309_08601_amd import t3
+    p, edges = _params(flags=8)
+    h = ctypes.c_void_p()
+    assert t3._lib.t3_plan_create(ctypes.byref(p), ctypes.byref(h)) == 0
+    try:
+        dummy = ctypes.c_void_p(16)
+        assert t3._lib.t3_normalise_backward(h, dummy, 1, dummy, dummy, None) == -1
+        assert b"edge" in t3._lib.t3_last_error_message()
+        bad = (ctypes.c_double * 2)(1.0, -1.0)
+        assert t3._lib.t3_x_to_centroid(h, dummy, 1, 8, bad, dummy, None) == -1
+        assert t3._lib.t3_x_to_centroid(h, dummy, 1, 0, None, dummy, None) == -2
+    finally:
+        t3._lib.t3_plan_destroy(h)

@@ -1,0 +1,151 @@
+"""Edge correction (mode coupling) and the x -> centroid projection on the GPU.
+
+* N_n up to 2 n_max from the extended stage-1 W sums and the N contraction,
+  against the oracle on a catalog with a hole and a density gradient (a
+  strongly non-identity mode-coupling matrix), FP32 bar (R10: N_n with n >= 1
+  relative to ||N_0||);
+* the FP64 Levinson solve fed the oracle's own FP64 multipoles (single and
+  tomographic sets; negative orders come from the swapped sets), against
+  numpy.linalg.solve in the oracle: 1e-10;
+* the edge-corrected Gamma_n end to end against the oracle;
+* the centroid projection against the oracle's conversion: 1e-13.
+"""
+import numpy as np
+import pytest
+
+from paper_2309_08601_amd.synth import random_catalog
+from _util import FP32_TOL, box_for, multipole_errors, rel_fro
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def t3():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08601_amd import t3 as mod
+    return mod
+
+
+def _masked_catalog(n, side, seed):
+    """Uniform catalog thinned by a linear density gradient and a circular
+    hole of radius side/5 at the centre."""
+    cat = random_catalog(n, side, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    x = cat.x.astype(np.float64)
+    y = cat.y.astype(np.float64)
+    xs = (x - x.min()) / (x.max() - x.min())
+    cx, cy = 0.5 * (x.min() + x.max()), 0.5 * (y.min() + y.max())
+    r = 0.2 * (x.max() - x.min())
+    keep = (rng.uniform(size=cat.n) < 0.25 + 0.75 * xs) & ((x - cx) ** 2 + (y - cy) ** 2 > r * r)
+    return cat.subset(np.nonzero(keep)[0])
+
+
+def _pack_ec(ups, N, nm):
+    """oracle ups[4, 2nm+1, B, B], N[4nm+1, B, B] -> GPU set layout [4(nm+1) + 2nm+1, B, B]."""
+    B = ups.shape[-1]
+    u = ups[:, nm:].reshape(4 * (nm + 1), B, B)
+    n = N[2 * nm:]
+    return np.concatenate([u, n], axis=0)
+
+
+@pytest.mark.parametrize("nm", [3, 8, 30, 40])
+def test_extended_normaliser_matches_oracle(t3, nm):
+    from oracle import multipole as mp
+    cat = _masked_catalog(4000, 50.0, seed=900 + nm)
+    edges = np.geomspace(1.0, 14.0, 6)
+    lo, size = box_for(50.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size, edge_correct=True)
+    ups, npairs = plan.forward(t3.DeviceCatalog.from_catalog(cat))
+    o = mp.multipoles(cat, edges, nm, w_max=2 * nm)
+    assert npairs == o["npairs"]
+    u4, Ng = plan.split_ups(ups)
+    u4 = u4.cpu().numpy()
+    Ng = Ng.cpu().numpy()
+    e_u = rel_fro(u4, o["ups"][:, nm:])
+    n_ref = o["N"][2 * nm:]
+    n0 = np.linalg.norm(n_ref[0])
+    e_n = np.linalg.norm((Ng - n_ref).reshape(Ng.shape[0], -1), axis=1) / n0
+    print(f"n_max {nm}: Upsilon {e_u.max():.2e}, N_n/N_0 {e_n.max():.2e} (orders 0..{2 * nm})", flush=True)
+    assert e_u.max() <= FP32_TOL and e_n.max() <= FP32_TOL
+
+
+def test_levinson_matches_oracle_solve_fp64(t3):
+    from oracle import multipole as mp
+    cat = _masked_catalog(3000, 45.0, seed=31)
+    edges = np.geomspace(1.0, 12.0, 5)
+    nm = 7
+    o = mp.multipoles(cat, edges, nm, w_max=2 * nm)
+    ref = mp.mode_coupling_correct(o["ups"], o["N"], nm)[:, nm:]
+    plain, _ = mp.normalise(o["ups"], o["N"][nm:3 * nm + 1])
+    lo, size = box_for(45.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size, edge_correct=True)
+    packed = torch.from_numpy(_pack_ec(o["ups"], o["N"], nm)).cuda()
+    gn, _ = plan.normalise_resum(packed, with_phi=False)
+    e = rel_fro(gn.cpu().numpy(), ref)
+    d = rel_fro(plain[:, nm:], ref)
+    print(f"Levinson vs LU: {e.max():.2e}; the plain ratio differs by up to {d.max():.2e}", flush=True)
+    assert e.max() < 1e-10
+    assert d.max() > 1e-3  # the mask makes the correction matter
+
+
+def test_levinson_tomographic_sets(t3):
+    from oracle import multipole as mp
+    cats = [_masked_catalog(1800, 40.0, seed=41), random_catalog(1500, 40.0, seed=42)]
+    edges = np.geomspace(1.0, 10.0, 4)
+    nm = 5
+    o = mp.multipoles_tomo(cats, edges, nm, w_max=2 * nm)
+    nz = 2
+    packed = np.stack([_pack_ec(o["ups"][s // 4, (s // 2) % 2, s % 2], o["N"][s // 4, (s // 2) % 2, s % 2], nm)
+                       for s in range(nz ** 3)]).reshape((nz, nz, nz) + (4 * (nm + 1) + 2 * nm + 1,) +
+                                                          o["ups"].shape[-2:])
+    lo, size = box_for(40.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size, edge_correct=True)
+    gn, _ = plan.normalise_resum(torch.from_numpy(packed).cuda(), with_phi=False)
+    gn = gn.cpu().numpy()
+    worst = 0.0
+    for z1 in range(nz):
+        for z2 in range(nz):
+            for z3 in range(nz):
+                ref = mp.mode_coupling_correct(o["ups"][z1, z2, z3], o["N"][z1, z2, z3], nm)[:, nm:]
+                worst = max(worst, rel_fro(gn[z1, z2, z3], ref).max())
+    print(f"tomographic Levinson vs LU: {worst:.2e}", flush=True)
+    assert worst < 1e-10
+
+
+def test_edge_corrected_gamma_end_to_end(t3):
+    from oracle import multipole as mp
+    cat = _masked_catalog(4000, 50.0, seed=77)
+    edges = np.geomspace(1.0, 14.0, 6)
+    nm = 8
+    lo, size = box_for(50.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size, edge_correct=True)
+    ups, _ = plan.forward(t3.DeviceCatalog.from_catalog(cat))
+    gn, gp = plan.normalise_resum(ups, n_phi=16)
+    o = mp.multipoles(cat, edges, nm, w_max=2 * nm)
+    ref_all = mp.mode_coupling_correct(o["ups"], o["N"], nm)
+    e = rel_fro(gn.cpu().numpy(), ref_all[:, nm:])
+    ref_phi = mp.resum(ref_all, nm, mp.phi_bin_edges(16))
+    ep = np.sqrt(np.sum(np.abs(gp.cpu().numpy() - ref_phi) ** 2, axis=(1, 2, 3))) / np.sqrt(
+        np.sum(np.abs(ref_phi) ** 2, axis=(1, 2, 3)))
+    print(f"edge-corrected Gamma_n {e.max():.2e}, Gamma(phi) {ep.max():.2e}", flush=True)
+    # FP32 multipoles through the FP64 solve: the mode-coupling matrix of
+    # this mask has a small condition number, so the FP32 bar carries over
+    assert e.max() <= 2 * FP32_TOL and ep.max() <= 2 * FP32_TOL
+
+
+def test_centroid_projection_matches_oracle(t3):
+    from oracle.projection import x_to_centroid, bin_centres, phi_centres
+    rng = np.random.default_rng(5)
+    edges = np.geomspace(1.0, 20.0, 7)
+    B, K, sets = 6, 24, 8
+    plan = t3.Plan(edges, 4, box_size=1 << 22)
+    g = rng.standard_normal((sets, 4, B, B, K)) + 1j * rng.standard_normal((sets, 4, B, B, K))
+    got = plan.x_to_centroid(torch.from_numpy(g).cuda()).cpu().numpy()
+    ref = x_to_centroid(g, bin_centres(edges), phi_centres(K))
+    assert rel_fro(got, ref, axes=(-3, -2, -1)).max() < 1e-13
+    theta = rng.uniform(1.0, 30.0, B)
+    got2 = plan.x_to_centroid(torch.from_numpy(g).cuda(), theta=theta).cpu().numpy()
+    ref2 = x_to_centroid(g, theta, phi_centres(K))
+    assert rel_fro(got2, ref2, axes=(-3, -2, -1)).max() < 1e-13
