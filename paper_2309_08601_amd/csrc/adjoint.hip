@@ -457,6 +457,8 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
     L.w_max = plan->w_max;
     L.B = plan->B;
     L.K = choose_chunk(plan, L);
+    if (plan->chunk_req <= 0 && (int64_t)L.K > n)  // small catalogs, small buffers
+        L.K = (int)std::max<int64_t>(256, ((int64_t)n + 255) & ~(int64_t)255);
     const int CS = coef_size(sv->cap);
     // scratch: nb_gc [2n], nb_gw [n], cen_gc [2n], cen_gw [n]
     T3_TRY(plan->misc.reserve(sizeof(float) * 6 * (size_t)n));

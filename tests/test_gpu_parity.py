@@ -247,3 +247,30 @@ def test_repeatable_bitwise(t3):
     a, _ = plan.forward(dc)
     b, _ = plan.forward(dc)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec,ec", [("fp32", False), ("bf16x6", False), ("fp32", True)])
+def test_many_chunks_ragged(t3, prec, ec):
+    """Chunks of 256 centres over 1999 galaxies (7 full chunks and a ragged
+    one of 207): every chunk's stage-2 partials accumulate into one output."""
+    _, mp = _oracle()
+    cat = random_catalog(1999, 50.0, seed=73)
+    edges = np.geomspace(1.0, 15.0, 7)
+    nm = 9
+    lo, size = box_for(50.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size, precision=prec, chunk_centres=256,
+                   edge_correct=ec)
+    ups, npairs = plan.forward(t3.DeviceCatalog.from_catalog(cat))
+    o = mp.multipoles(cat, edges, nm, w_max=2 * nm if ec else None)
+    assert npairs == o["npairs"]
+    if ec:
+        u4, N = plan.split_ups(ups)
+        wm = 2 * nm
+        ref_u = o["ups"][:, nm:]
+        e = rel_fro(u4.cpu().numpy(), ref_u).max()
+        dn = np.linalg.norm((N.cpu().numpy() - o["N"][wm:]).reshape(wm + 1, -1), axis=1)
+        en = (dn / np.linalg.norm(o["N"][wm])).max()
+        print(f"many chunks, edge-correct layout: Upsilon {e:.2e}, N_n/N_0 {en:.2e}", flush=True)
+        assert e <= FP32_TOL and en <= FP32_TOL
+    else:
+        _check(ups.cpu().numpy(), _pack(o, nm), FP32_TOL, f"many chunks {prec}")
