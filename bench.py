@@ -43,21 +43,25 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic():
+def profiled_traffic(launches_per_step):
     """HBM bytes per stage-1 launch from the committed counter summary, or
-    None when the kernel sources changed since those counters were taken."""
+    None when the kernel sources or the launch shape (launches per step)
+    changed since those counters were taken."""
     path = os.path.join(ROOT, "profiles", "k_scan_field_1m.md")
     try:
         text = open(path).read()
     except OSError:
         return None
-    sha = traffic = None
+    sha = traffic = launches = None
     for line in text.splitlines():
         if line.startswith("kernel-source-sha256:"):
             sha = line.split(":", 1)[1].strip()
         if line.startswith("traffic-bytes-per-launch:"):
             traffic = float(line.split(":", 1)[1].strip())
-    return traffic if sha == kernel_source_hash() else None
+        if line.startswith("launches-per-step:"):
+            launches = int(line.split(":", 1)[1].strip())
+    ok = sha == kernel_source_hash() and launches == launches_per_step
+    return traffic if ok else None
 
 
 def log(msg):
@@ -203,7 +207,7 @@ def main():
                               "stage2_contract": stage_ms[2] / K},
         "split_precision": split,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": profiled_traffic(),
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": profiled_traffic(int(launches[1] // K)),
                      "kernel": "k_scan (stage 1)",
                      "flops_per_pair": flops_pair, "launches_per_step": int(launches[1] // K)},
     }
