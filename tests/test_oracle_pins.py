@@ -431,3 +431,80 @@ def test_mode_coupling_recovers_band_limited_gamma():
     assert _rel(got, g) < 1e-10
     plain, _ = mp.normalise(ups, N)
     assert _rel(plain, g) > 1e-2
+
+
+def _aperture_direct(t1, t2, phi, th, mu, n=601):
+    """2 pi t1 t2 int d^2X prod_k Q_{th_k}(|X_k|) e^{-2i(beta_k - zeta_k)} (conjugated
+    at vertex mu for mu >= 1): one triangle (X_1 = X, X_2 = X + t1, X_3 = X +
+    t2 e^{i phi}) against three apertures centred at the origin, straight from
+    eqs. MapGamma, CrittendenQ and centroidprojection (beta_k the polar angle
+    of X_k seen from the aperture centre, e^{2 i zeta_k} = q_k / q_k^*).  The
+    trapezoid rule on a wide grid is spectrally accurate for these smooth,
+    Gaussian-decaying integrands."""
+    from oracle.aperture import q_filter, q_vectors
+    v1 = t1 + 0j
+    v2 = t2 * np.exp(1j * phi)
+    L = 7.0 * max(th) + max(t1, t2)
+    xs = np.linspace(-L, L, n)
+    h = xs[1] - xs[0]
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    P = X + 1j * Y
+    q = q_vectors(t1, t2, phi)
+    val = np.ones_like(P)
+    for k, Xk in enumerate([P, P + v1, P + v2]):
+        r = np.abs(Xk)
+        e2b = np.where(r > 0, np.conj(Xk) / np.where(r > 0, Xk, 1.0), 0.0)
+        ph = e2b * q[k] / np.conj(q[k])
+        val = val * q_filter(r, th[k]) * (np.conj(ph) if mu == k + 1 else ph)
+    return 2.0 * np.pi * t1 * t2 * np.sum(val) * h * h
+
+
+def test_aperture_filters_match_direct_integration():
+    """F_0..F_3 (eq. 3pcftomap3_helpers and the F_0, F_1 expressions with the
+    filter assignment reading) equal the first-principles aperture integral of
+    a single triangle, for random triangles and aperture radii."""
+    from oracle.aperture import filters
+    rng = np.random.default_rng(8)
+    for _ in range(3):
+        t1, t2 = rng.uniform(0.5, 3.0, 2)
+        phi = rng.uniform(0.2, 2 * np.pi - 0.2)
+        th = rng.uniform(0.6, 2.0, 3)
+        F = filters(t1, t2, phi, *th)
+        for mu in range(4):
+            d = _aperture_direct(t1, t2, phi, th, mu)
+            assert abs(F[mu] - d) <= 1e-9 * abs(d), (mu, F[mu], d)
+
+
+def test_aperture_statistics_parity_and_linear_algebra():
+    """The eight statistics (eqs. MapTrafo8_1-8) invert the four correlators'
+    expansion in Map, Mx: building correlators from given <Map^a Mx^b> values
+    and transforming back returns them; and for a parity-even 3PCF
+    (Gamma(phi) = conj Gamma(-phi) on a symmetric phi grid) the odd-parity
+    statistics <Mx Map^2>-type and <Mx^3> of equal aperture radii vanish."""
+    from oracle.aperture import aperture_stats, correlators
+    rng = np.random.default_rng(9)
+    # algebra: M_k = A_k + i X_k; <M1^(*) M2^(*) M3^(*)> from the 8 real moments
+    mom = rng.standard_normal(8)  # AAA, XAA, AXA, AAX, AXX, XAX, XXA, XXX
+    names = ["AAA", "XAA", "AXA", "AAX", "AXX", "XAX", "XXA", "XXX"]
+    m = dict(zip(names, mom))
+
+    def corr(c1, c2, c3):  # conj flags per factor
+        tot = 0j
+        for a in "AX":
+            for b in "AX":
+                for c in "AX":
+                    f = 1 + 0j
+                    for ch, cf in zip((a, b, c), (c1, c2, c3)):
+                        f *= 1.0 if ch == "A" else (-1j if cf else 1j)
+                    tot += f * m[a + b + c]
+        return tot
+    cs = np.array([corr(0, 0, 0), corr(1, 0, 0), corr(0, 1, 0), corr(0, 0, 1)])
+    assert np.allclose(aperture_stats(cs), mom, atol=1e-13)
+    # parity
+    B, K = 5, 16
+    edges = np.geomspace(1.0, 8.0, B + 1)
+    pe = 2 * np.pi * np.arange(K + 1) / K
+    g = rng.standard_normal((4, B, B, K)) + 1j * rng.standard_normal((4, B, B, K))
+    g = 0.5 * (g + np.conj(g[..., ::-1]))  # phi_k <-> 2 pi - phi_k
+    st = aperture_stats(correlators(g, edges, pe, [(2.0, 2.0, 2.0), (1.5, 1.5, 1.5)]))
+    assert np.max(np.abs(st[:, [1, 2, 3, 7]])) < 1e-12 * np.max(np.abs(st))
