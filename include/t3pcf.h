@@ -199,6 +199,24 @@ int t3_normalise_resum(t3_plan *plan, const double *ups, int32_t n_sets,
 int t3_x_to_centroid(t3_plan *plan, const double *gamma_phi_x, int32_t n_sets, int32_t n_phi,
                      const double *theta, double *gamma_phi_cent, void *stream);
 
+/* Third-order aperture statistics from the centroid-projected 3PCF
+ * (Sect. 4, Appendix C), FP64: the four complex correlators
+ *   <M^3>, <M* M^2>, <M M* M>, <M^2 M*>  (theta_1, theta_2, theta_3)
+ * = int d vartheta_1 d vartheta_2 d phi Gamma_mu^cent F_mu (eqs. MFrom3pcfTheory,
+ * MFrom3pcfTheoryb; exponential filter, eq. CrittendenQ) by the midpoint rule
+ * on the plan's radial bins (centres and widths in arcmin) and the n_phi
+ * angular bins, and the eight real statistics of eqs. MapTrafo8_1-8.
+ * Filter of component mu: the printed F_1 with its distinguished index at
+ * vertex mu (the component conjugated at vertex mu); F_0 as printed.
+ * gamma_phi_cent: DEVICE double [n_sets][4][B][B][n_phi][2] (t3_x_to_centroid);
+ * apertures:      HOST double [n_ap][3] radii in arcmin (> 0), 1 <= n_ap <= 65535;
+ * corr_out:       DEVICE double [n_sets][n_ap][4][2];
+ * stats_out:      DEVICE double [n_sets][n_ap][8] or NULL: <Map^3>, <Mx Map^2>,
+ *                 <Map Mx Map>, <Map^2 Mx>, <Map Mx^2>, <Mx Map Mx>, <Mx^2 Map>, <Mx^3>. */
+int t3_aperture_stats(t3_plan *plan, const double *gamma_phi_cent, int32_t n_sets, int32_t n_phi,
+                      const double *apertures, int32_t n_ap, double *corr_out, double *stats_out,
+                      void *stream);
+
 /* Reverse of the normalisation Gamma_{mu,n} = Upsilon_{mu,n} / N_0 (mu < 4).
  * ups: DEVICE [n_sets][5][n_max+1][B][B][2] forward multipoles;
  * grad_gamma_n: DEVICE [n_sets][4][n_max+1][B][B][2] holding dL/dRe and

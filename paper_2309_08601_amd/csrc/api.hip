@@ -459,6 +459,21 @@ int t3_x_to_centroid(t3_plan *plan, const double *gamma_phi_x, int32_t n_sets, i
     return x_to_centroid(plan, gamma_phi_x, n_sets, n_phi, theta, gamma_phi_cent, (hipStream_t)stream);
 }
 
+int t3_aperture_stats(t3_plan *plan, const double *gamma_phi_cent, int32_t n_sets, int32_t n_phi,
+                      const double *apertures, int32_t n_ap, double *corr_out, double *stats_out, void *stream)
+{
+    if (!plan || !gamma_phi_cent || !apertures || !corr_out)
+        return fail(T3_EINVAL, "t3_aperture_stats: null argument");
+    if (n_sets < 1 || n_ap < 1) return fail(T3_EINVAL, "t3_aperture_stats: n_sets and n_ap must be >= 1");
+    if (n_phi < 1 || n_phi > 4096) return fail(T3_ERANGE, "t3_aperture_stats: n_phi must be in [1, 4096]");
+    if (n_ap > 65535) return fail(T3_ERANGE, "t3_aperture_stats: at most 65535 aperture triples per call");
+    for (int64_t k = 0; k < 3 * (int64_t)n_ap; ++k)
+        if (!(apertures[k] > 0.0) || !std::isfinite(apertures[k]))
+            return fail(T3_EINVAL, "t3_aperture_stats: aperture radii must be positive and finite");
+    return aperture_stats(plan, gamma_phi_cent, n_sets, n_phi, apertures, n_ap, corr_out, stats_out,
+                          (hipStream_t)stream);
+}
+
 int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets, const double *grad_gamma_n,
                           double *grad_ups, void *stream)
 {

@@ -173,6 +173,8 @@ int normalise_resum(t3_plan *plan, const double *ups, int n_sets, int n_z, int n
                     double *gamma_n, double *gamma_phi, hipStream_t s);
 int x_to_centroid(t3_plan *plan, const double *in, int n_sets, int n_phi, const double *theta, double *out,
                   hipStream_t s);
+int aperture_stats(t3_plan *plan, const double *gamma_cent, int n_sets, int n_phi, const double *apertures,
+                   int n_ap, double *corr, double *stats, hipStream_t s);
 int harmonics_export(t3_plan *plan, const CentreSet &cs, const ChunkLayout &L, const float *planes,
                      int64_t c0, int n_c, float *G, float *W, float *D, hipStream_t s);
 int normalise_backward(t3_plan *plan, const double *ups, const double *ggam, int n_sets, double *gups,

@@ -77,6 +77,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.t3_normalise_resum.restype = ctypes.c_int
     lib.t3_x_to_centroid.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), vp, vp]
     lib.t3_x_to_centroid.restype = ctypes.c_int
+    lib.t3_aperture_stats.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32,
+                                      vp, vp, vp]
+    lib.t3_aperture_stats.restype = ctypes.c_int
     lib.t3_normalise_backward.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
     lib.t3_normalise_backward.restype = ctypes.c_int
     lib.t3_backward.argtypes = [vp, P(t3_catalog), vp, vp, vp, vp, vp]
@@ -271,6 +274,24 @@ class Plan:
             th = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         _check(_lib.t3_x_to_centroid(self._h, _ptr(g), sets, n_phi, th, _ptr(out), _stream()))
         return torch.view_as_complex(out)
+
+    def aperture_stats(self, gamma_cent: torch.Tensor, apertures):
+        """Correlators [..., n_ap, 4] (complex128: <M^3>, <M* M^2>, <M M* M>,
+        <M^2 M*>) and statistics [..., n_ap, 8] (<Map^3>, <Mx Map^2>,
+        <Map Mx Map>, <Map^2 Mx>, <Map Mx^2>, <Mx Map Mx>, <Mx^2 Map>, <Mx^3>)
+        from a centroid-projected Gamma [..., 4, B, B, n_phi]; apertures
+        [n_ap, 3] radii in arcmin."""
+        g = torch.view_as_real(gamma_cent).contiguous() if gamma_cent.is_complex() else gamma_cent.contiguous()
+        n_phi = int(g.shape[-2])
+        lead = g.shape[:-5]
+        sets = int(np.prod(lead)) if len(lead) else 1
+        ap = np.ascontiguousarray(apertures, dtype=np.float64).reshape(-1, 3)
+        corr = torch.empty(lead + (ap.shape[0], 4, 2), dtype=torch.float64, device=g.device)
+        stats = torch.empty(lead + (ap.shape[0], 8), dtype=torch.float64, device=g.device)
+        _check(_lib.t3_aperture_stats(self._h, _ptr(g), sets, n_phi,
+                                      ap.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ap.shape[0],
+                                      _ptr(corr), _ptr(stats), _stream()))
+        return torch.view_as_complex(corr), stats
 
     def normalise_backward(self, ups: torch.Tensor, grad_gamma_n: torch.Tensor) -> torch.Tensor:
         """dL/dUpsilon (and dL/dN_0) from dL/dGamma_n; real views [..., 2]."""

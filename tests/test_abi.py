@@ -106,3 +106,21 @@ def test_edge_correct_plan_rejects_adjoint_and_bad_theta(lib):
         assert t3._lib.t3_x_to_centroid(h, dummy, 1, 0, None, dummy, None) == -2
     finally:
         t3._lib.t3_plan_destroy(h)
+
+
+def test_aperture_stats_argument_errors(lib):
+    pytest.importorskip("torch")
+    from paper_2309_08601_amd import t3
+    p, edges = _params()
+    h = ctypes.c_void_p()
+    assert t3._lib.t3_plan_create(ctypes.byref(p), ctypes.byref(h)) == 0
+    try:
+        dummy = ctypes.c_void_p(16)
+        good = (ctypes.c_double * 3)(1.0, 2.0, 3.0)
+        bad = (ctypes.c_double * 3)(1.0, 0.0, 3.0)
+        assert t3._lib.t3_aperture_stats(h, dummy, 1, 8, None, 1, dummy, None, None) == -1
+        assert t3._lib.t3_aperture_stats(h, dummy, 1, 8, bad, 1, dummy, None, None) == -1
+        assert t3._lib.t3_aperture_stats(h, dummy, 1, 0, good, 1, dummy, None, None) == -2
+        assert t3._lib.t3_aperture_stats(h, dummy, 1, 8, good, 0, dummy, None, None) == -1
+    finally:
+        t3._lib.t3_plan_destroy(h)
