@@ -508,3 +508,80 @@ def test_aperture_statistics_parity_and_linear_algebra():
     g = 0.5 * (g + np.conj(g[..., ::-1]))  # phi_k <-> 2 pi - phi_k
     st = aperture_stats(correlators(g, edges, pe, [(2.0, 2.0, 2.0), (1.5, 1.5, 1.5)]))
     assert np.max(np.abs(st[:, [1, 2, 3, 7]])) < 1e-12 * np.max(np.abs(st))
+
+
+def test_sphere_rotation_and_shear_transport():
+    """Patch rotation (Appendix B): the centre goes to (0, 0), great-circle
+    distances are preserved, and the shear rotation angle psi equals the
+    change of the position angle of a short displacement carried through the
+    rotation (finite-difference transport of a tangent vector, an independent
+    computation of the same angle)."""
+    from oracle.sphere import rotation, shear_angle, unit_vectors
+    rng = np.random.default_rng(21)
+    for _ in range(5):
+        ra0, dec0 = rng.uniform(0, 2 * np.pi), rng.uniform(-1.2, 1.2)
+        R = rotation(ra0, dec0)
+        assert np.allclose(unit_vectors(ra0, dec0) @ R.T, [1.0, 0.0, 0.0], atol=1e-14)
+        ra = ra0 + rng.uniform(-0.1, 0.1, 50)
+        dec = np.clip(dec0 + rng.uniform(-0.1, 0.1, 50), -1.5, 1.5)
+        v = unit_vectors(ra, dec)
+        w = v @ R.T
+        d0 = np.linalg.norm(v[:, None] - v[None], axis=-1)   # chords: well conditioned
+        d1 = np.linalg.norm(w[:, None] - w[None], axis=-1)
+        assert np.max(np.abs(d0 - d1)) < 1e-14
+        psi = shear_angle(v, R)
+        # carry a displacement of position angle pa through R and measure its
+        # position angle at the image point
+        pa = rng.uniform(0, 2 * np.pi, 50)
+        eps = 1e-6
+        east = np.stack([-np.sin(ra), np.cos(ra), np.zeros_like(ra)], -1)
+        north = np.stack([-np.sin(dec) * np.cos(ra), -np.sin(dec) * np.sin(ra), np.cos(dec)], -1)
+        t = np.sin(pa)[:, None] * east + np.cos(pa)[:, None] * north
+        p2 = v + eps * t
+        p2 /= np.linalg.norm(p2, axis=-1, keepdims=True)
+        q1, q2 = v @ R.T, p2 @ R.T
+        lam1, bet1 = np.arctan2(q1[:, 1], q1[:, 0]), np.arcsin(q1[:, 2])
+        lam2, bet2 = np.arctan2(q2[:, 1], q2[:, 0]), np.arcsin(q2[:, 2])
+        pa2 = np.arctan2((lam2 - lam1) * np.cos(bet1), bet2 - bet1)
+        dpa = np.angle(np.exp(1j * (pa2 - pa - psi)))
+        assert np.max(np.abs(dpa)) < 1e-5
+        # a spin-2 quantity built from the displacement's polar angle in the
+        # local (east, north) frame, before and after transport, changes by
+        # the factor the patch mapping applies to shears
+        from oracle.sphere import project
+        g_before = np.exp(2j * (np.pi / 2 - pa))
+        g_after = np.exp(2j * (np.pi / 2 - pa2))
+        deg = np.degrees
+        patch = (deg(ra0) - 1.0, deg(ra0) + 1.0, deg(dec0) - 1.0, deg(dec0) + 1.0, 10.0)
+        _, _, h1, h2, _, _ = project(deg(ra), deg(dec), g_before.real, g_before.imag, patch, 2.0 ** -16)
+        assert np.max(np.abs((h1 + 1j * h2) - g_after)) < 1e-5
+
+
+def test_patch_sum_with_one_projection_equals_whole_catalog():
+    """eq. PatchGamma with the overlap rule: when every patch uses the same
+    projection, the sum over patches (centres from the core, neighbours from
+    the core extended by theta_max) is exactly the multipoles of the whole
+    projected catalog -- the cores partition the centres and the extension
+    holds every neighbour within theta_max."""
+    from paper_2309_08601_amd.synth import Catalog
+    from oracle.sphere import multipoles_patches, project
+    rng = np.random.default_rng(5)
+    n = 900
+    ra = rng.uniform(30.0, 31.2, n)
+    dec = rng.uniform(20.0, 21.2, n)
+    g1 = rng.normal(0, 0.3, n)
+    g2 = rng.normal(0, 0.3, n)
+    w = rng.uniform(0.5, 1.5, n)
+    edges = np.geomspace(0.5, 8.0, 5)
+    patches = [(30.0, 30.6, 20.0, 20.6), (30.6, 31.2, 20.0, 20.6), (30.0, 30.6, 20.6, 21.2),
+               (30.6, 31.2, 20.6, 21.2)]
+    centre = (30.6, 20.6)
+    unit = 2.0 ** -16
+    cores = [project(ra, dec, g1, g2, p + (8.0,), unit, centre)[4] for p in patches]
+    assert np.all(np.sum(cores, axis=0) == 1)  # the cores partition the catalog
+    o = multipoles_patches(ra, dec, g1, g2, w, patches, 8.0, edges, 5, unit, centre=centre)
+    x, y, h1, h2, _, _ = project(ra, dec, g1, g2, patches[0] + (8.0,), unit, centre)
+    whole = mp.multipoles(Catalog(x.astype(np.int32), y.astype(np.int32), h1.astype(np.float32),
+                                  h2.astype(np.float32), w.astype(np.float32)), edges, 5)
+    assert o["npairs"] == whole["npairs"]
+    assert _rel(o["ups"], whole["ups"]) < 1e-12 and _rel(o["N"], whole["N"]) < 1e-12
