@@ -115,6 +115,21 @@ typedef struct {
     const float *w;       /* DEVICE [n] weights                              */
 } t3_catalog;
 
+/* A catalog on the sphere (Appendix B). */
+typedef struct {
+    int64_t n;            /* number of galaxies (>= 0)                       */
+    const double *ra;     /* DEVICE [n] right ascension, degrees             */
+    const double *dec;    /* DEVICE [n] declination, degrees, |dec| < 89     */
+    const float *g1;      /* DEVICE [n] shear in the local (east, north)     */
+    const float *g2;      /* DEVICE [n]   frame, angles from east to north   */
+    const float *w;       /* DEVICE [n] weights                              */
+} t3_sphere_catalog;
+
+/* A patch: the RA/Dec rectangle [ra_lo, ra_hi) x [dec_lo, dec_hi), degrees. */
+typedef struct {
+    double ra_lo, ra_hi, dec_lo, dec_hi;
+} t3_patch;
+
 typedef struct t3_plan t3_plan;
 
 /* Create a plan: validates parameters, derives squared edges and the
@@ -150,6 +165,27 @@ int t3_forward(t3_plan *plan, const t3_catalog *cat, const int32_t *centres,
 int t3_forward_tomo(t3_plan *plan, const t3_catalog *cats, int32_t n_z,
                     const int32_t *const *centres, const int64_t *n_centres,
                     double *ups_out, int64_t *n_pairs, void *stream);
+
+/* Multipoles of a curved-sky catalog from flat patches (Appendix B,
+ * eq. PatchGamma): for every patch, the sphere is rotated so that the patch
+ * centre lies at (RA, Dec) = (0, 0), shears are rotated by the change of
+ * reference direction (gamma' = gamma e^{-2 i psi}, psi the angle from the
+ * local north to the image of the original north, towards east), positions
+ * are mapped by the sinusoidal projection x = lambda cos(beta), y = beta
+ * (arcmin, x east, y north) onto the plan's lattice, and the flat estimator
+ * runs with the patch's core galaxies as centres against every galaxy of
+ * the patch extended by theta_max (theta_max / cos(Dec) in RA); the results
+ * are summed over patches.  Patches whose cores tile the footprint count
+ * every centre once.
+ * The plan's box must hold every projected extended patch, centred on 0
+ * (e.g. box_lo = -box_size / 2); positions outside it give T3_ELATTICE.
+ * patches: HOST [n_patches], each side <= 30 degrees; theta_max_arcmin must
+ * be >= the plan's largest bin edge.  ups_out: t3_forward layout.  n_pairs:
+ * HOST, the ordered pairs summed over patches.  Synchronises the stream
+ * (patch sizes are read back to size the flat catalogs). */
+int t3_forward_sphere(t3_plan *plan, const t3_sphere_catalog *cat, const t3_patch *patches,
+                      int32_t n_patches, double theta_max_arcmin, double *ups_out, int64_t *n_pairs,
+                      void *stream);
 
 /* Stage 1 alone, for inspection: the harmonic sums of eq. (Gn_disc) for
  * the given centres against the neighbour catalog.

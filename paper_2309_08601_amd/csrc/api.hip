@@ -459,6 +459,50 @@ int t3_x_to_centroid(t3_plan *plan, const double *gamma_phi_x, int32_t n_sets, i
     return x_to_centroid(plan, gamma_phi_x, n_sets, n_phi, theta, gamma_phi_cent, (hipStream_t)stream);
 }
 
+int t3_forward_sphere(t3_plan *plan, const t3_sphere_catalog *cat, const t3_patch *patches, int32_t n_patches,
+                      double theta_max_arcmin, double *ups_out, int64_t *n_pairs, void *stream)
+{
+    try {
+        if (!plan || !cat || !patches || !ups_out || !n_pairs)
+            return fail(T3_EINVAL, "t3_forward_sphere: null argument");
+        if (n_patches < 1) return fail(T3_EINVAL, "t3_forward_sphere: need at least one patch");
+        if (cat->n < 0 || cat->n > (int64_t)0x7fffffff)
+            return fail(T3_EINVAL, "t3_forward_sphere: catalog size out of range");
+        if (cat->n > 0 && (!cat->ra || !cat->dec || !cat->g1 || !cat->g2 || !cat->w))
+            return fail(T3_EINVAL, "t3_forward_sphere: null catalog array");
+        if (!(theta_max_arcmin > 0.0) || !std::isfinite(theta_max_arcmin))
+            return fail(T3_EINVAL, "t3_forward_sphere: theta_max must be positive");
+        if (theta_max_arcmin < plan->edges_lat[plan->B] * plan->unit)
+            return fail(T3_EINVAL, "t3_forward_sphere: theta_max below the largest bin edge");
+        for (int k = 0; k < n_patches; ++k) {
+            const t3_patch &p = patches[k];
+            if (!(p.ra_lo < p.ra_hi) || !(p.dec_lo < p.dec_hi) || p.ra_hi - p.ra_lo > 30.0 ||
+                p.dec_hi - p.dec_lo > 30.0 || p.dec_lo < -89.0 || p.dec_hi > 89.0)
+                return fail(T3_EINVAL, "t3_forward_sphere: bad patch (sides <= 30 deg, |dec| <= 89)");
+        }
+        hipStream_t s = (hipStream_t)stream;
+        const size_t per = (size_t)2 * (4 * (plan->n_max + 1) + plan->w_max + 1) * plan->B * plan->B;
+        T3_TRY(zero_doubles(ups_out, per, s));
+        T3_TRY(plan->sph_out.reserve(sizeof(double) * per));
+        int64_t total = 0;
+        for (int k = 0; k < n_patches; ++k) {
+            t3_catalog view{};
+            const int32_t *core = nullptr;
+            int64_t n_core = 0;
+            T3_TRY(sphere_patch(plan, *cat, patches[k], theta_max_arcmin, &view, &core, &n_core, s));
+            if (n_core == 0) continue;
+            int64_t np = 0;
+            T3_TRY(forward_impl(plan, &view, 1, &core, &n_core, plan->sph_out.as<double>(), &np, s));
+            T3_TRY(add_doubles(ups_out, plan->sph_out.as<double>(), per, s));
+            total += np;
+        }
+        *n_pairs = total;
+        return T3_OK;
+    } catch (...) {
+        return fail(T3_EINVAL, "t3_forward_sphere: exception");
+    }
+}
+
 int t3_aperture_stats(t3_plan *plan, const double *gamma_phi_cent, int32_t n_sets, int32_t n_phi,
                       const double *apertures, int32_t n_ap, double *corr_out, double *stats_out, void *stream)
 {

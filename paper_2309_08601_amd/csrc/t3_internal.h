@@ -132,6 +132,7 @@ struct t3_plan {
     t3::DevBuf tune_out;  // autotuner output
     t3::DevBuf misc;      // adjoint scratch
     t3::DevBuf misc2;
+    t3::DevBuf sph_a, sph_b, sph_out;  // sphere patches: projection, compaction, per-patch output
     int scan_var = -1;          // stage-1 variant index (see scan.hip)
     size_t scan_dest_off[3] = {0, 0, 0};  // main passes, then the W extension
 
@@ -175,6 +176,9 @@ int x_to_centroid(t3_plan *plan, const double *in, int n_sets, int n_phi, const 
                   hipStream_t s);
 int aperture_stats(t3_plan *plan, const double *gamma_cent, int n_sets, int n_phi, const double *apertures,
                    int n_ap, double *corr, double *stats, hipStream_t s);
+int sphere_patch(t3_plan *plan, const t3_sphere_catalog &cat, const t3_patch &p, double theta_max_arcmin,
+                 t3_catalog *view, const int32_t **core, int64_t *n_core, hipStream_t s);
+int add_doubles(double *dst, const double *src, size_t n, hipStream_t s);
 int harmonics_export(t3_plan *plan, const CentreSet &cs, const ChunkLayout &L, const float *planes,
                      int64_t c0, int n_c, float *G, float *W, float *D, hipStream_t s);
 int normalise_backward(t3_plan *plan, const double *ups, const double *ggam, int n_sets, double *gups,

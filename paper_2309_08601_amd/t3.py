@@ -44,6 +44,16 @@ class t3_catalog(ctypes.Structure):
                 ("g1", ctypes.c_void_p), ("g2", ctypes.c_void_p), ("w", ctypes.c_void_p)]
 
 
+class t3_sphere_catalog(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ra", ctypes.c_void_p), ("dec", ctypes.c_void_p),
+                ("g1", ctypes.c_void_p), ("g2", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+
+
+class t3_patch(ctypes.Structure):
+    _fields_ = [("ra_lo", ctypes.c_double), ("ra_hi", ctypes.c_double), ("dec_lo", ctypes.c_double),
+                ("dec_hi", ctypes.c_double)]
+
+
 class T3Error(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"t3pcf error {code}: {msg}")
@@ -71,6 +81,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.t3_forward_tomo.argtypes = [vp, P(t3_catalog), ctypes.c_int32, P(vp), P(ctypes.c_int64), vp,
                                     P(ctypes.c_int64), vp]
     lib.t3_forward_tomo.restype = ctypes.c_int
+    lib.t3_forward_sphere.argtypes = [vp, P(t3_sphere_catalog), P(t3_patch), ctypes.c_int32, ctypes.c_double, vp,
+                                      P(ctypes.c_int64), vp]
+    lib.t3_forward_sphere.restype = ctypes.c_int
     lib.t3_harmonics.argtypes = [vp, P(t3_catalog), vp, ctypes.c_int64, vp, vp, vp, vp]
     lib.t3_harmonics.restype = ctypes.c_int
     lib.t3_normalise_resum.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
@@ -226,6 +239,23 @@ class Plan:
         npairs = ctypes.c_int64(0)
         _check(_lib.t3_forward_tomo(self._h, arr, nz, cptr, cnt, _ptr(out), ctypes.byref(npairs),
                                     _stream()))
+        return torch.view_as_complex(out), int(npairs.value)
+
+    def forward_sphere(self, ra: torch.Tensor, dec: torch.Tensor, g1: torch.Tensor, g2: torch.Tensor,
+                       w: torch.Tensor, patches, theta_max: float, out: Optional[torch.Tensor] = None):
+        """Curved-sky catalog (device tensors: ra, dec float64 degrees; g1, g2,
+        w float32) through flat patches [(ra_lo, ra_hi, dec_lo, dec_hi), ...]
+        with theta_max (arcmin) overlap; multipoles summed over patches."""
+        arrs = [ra.to(torch.float64).contiguous(), dec.to(torch.float64).contiguous(),
+                g1.to(torch.float32).contiguous(), g2.to(torch.float32).contiguous(),
+                w.to(torch.float32).contiguous()]
+        cs = t3_sphere_catalog(int(arrs[0].numel()), *[a.data_ptr() for a in arrs])
+        pa = (t3_patch * len(patches))(*[t3_patch(*map(float, p)) for p in patches])
+        if out is None:
+            out = torch.empty(self._out_shape()[1:], dtype=torch.float64, device=arrs[0].device)
+        npairs = ctypes.c_int64(0)
+        _check(_lib.t3_forward_sphere(self._h, ctypes.byref(cs), pa, len(patches), float(theta_max), _ptr(out),
+                                      ctypes.byref(npairs), _stream()))
         return torch.view_as_complex(out), int(npairs.value)
 
     def harmonics(self, cat: DeviceCatalog, centres: torch.Tensor):

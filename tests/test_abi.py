@@ -124,3 +124,22 @@ def test_aperture_stats_argument_errors(lib):
         assert t3._lib.t3_aperture_stats(h, dummy, 1, 8, good, 0, dummy, None, None) == -1
     finally:
         t3._lib.t3_plan_destroy(h)
+
+
+def test_forward_sphere_argument_errors(lib):
+    pytest.importorskip("torch")
+    from paper_2309_08601_amd import t3
+    p, edges = _params()  # edges 1', 2', 4'
+    h = ctypes.c_void_p()
+    assert t3._lib.t3_plan_create(ctypes.byref(p), ctypes.byref(h)) == 0
+    try:
+        cat = t3.t3_sphere_catalog(0, None, None, None, None, None)
+        ok = (t3.t3_patch * 1)(t3.t3_patch(10.0, 12.0, 0.0, 2.0))
+        bad = (t3.t3_patch * 1)(t3.t3_patch(10.0, 50.0, 0.0, 2.0))
+        out = ctypes.c_void_p(16)
+        npairs = ctypes.c_int64(0)
+        assert t3._lib.t3_forward_sphere(h, ctypes.byref(cat), bad, 1, 10.0, out, ctypes.byref(npairs), None) == -1
+        assert t3._lib.t3_forward_sphere(h, ctypes.byref(cat), ok, 1, 2.0, out, ctypes.byref(npairs), None) == -1
+        assert t3._lib.t3_forward_sphere(h, ctypes.byref(cat), ok, 0, 10.0, out, ctypes.byref(npairs), None) == -1
+    finally:
+        t3._lib.t3_plan_destroy(h)

@@ -585,3 +585,31 @@ def test_patch_sum_with_one_projection_equals_whole_catalog():
                                   h2.astype(np.float32), w.astype(np.float32)), edges, 5)
     assert o["npairs"] == whole["npairs"]
     assert _rel(o["ups"], whole["ups"]) < 1e-12 and _rel(o["N"], whole["N"]) < 1e-12
+
+
+def test_patch_projection_is_equal_area():
+    """The sinusoidal projection (Appendix B) preserves area: a small
+    spherical triangle (area from the Van Oosterom-Strackee solid-angle
+    formula) and its projected lattice triangle agree, also far from the
+    patch's central meridian and equator, where a dropped cos(beta) or a
+    swapped axis would be off by several per cent."""
+    from oracle.sphere import ARCMIN, project, rotation, unit_vectors
+    rng = np.random.default_rng(33)
+    ra0, dec0 = 47.0, -23.0
+    R = rotation(np.radians(ra0), np.radians(dec0))
+    patch = (ra0 - 1.0, ra0 + 1.0, dec0 - 1.0, dec0 + 1.0, 10.0)
+    for lam, bet in [(0.0, 0.0), (0.25, 0.05), (-0.2, 0.3), (0.3, -0.35)]:
+        s = 1e-3
+        pts = np.array([[lam, bet]] * 3) + s * rng.uniform(-1, 1, (3, 2))
+        w = unit_vectors(pts[:, 0], pts[:, 1])           # rotated frame
+        v = w @ R                                         # back to the sky (R orthogonal)
+        ra = np.degrees(np.arctan2(v[:, 1], v[:, 0]))
+        dec = np.degrees(np.arcsin(v[:, 2]))
+        x, y, *_ = project(ra, dec, np.zeros(3), np.zeros(3), patch, 2.0 ** -16)
+        x = x * 2.0 ** -16
+        y = y * 2.0 ** -16
+        flat = 0.5 * abs((x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0]))
+        a, b, c = w
+        tan_half = abs(np.dot(a, np.cross(b, c))) / (1 + a @ b + b @ c + c @ a)
+        sph = 2 * np.arctan(tan_half) / ARCMIN ** 2
+        assert abs(flat / sph - 1) < 1e-3, (lam, bet, flat / sph)
