@@ -187,6 +187,31 @@ int t3_forward_sphere(t3_plan *plan, const t3_sphere_catalog *cat, const t3_patc
                       int32_t n_patches, double theta_max_arcmin, double *ups_out, int64_t *n_pairs,
                       void *stream);
 
+/* Combined discrete / grid-based multipoles (Sect. 3.2-3.3, eqs.
+ * UpsilonmuGrid and CombinedEstimatorRegridding; Appendix A).
+ * levels: HOST int32 [B], non-decreasing: 0 = discrete bin (galaxy pairs);
+ *   l = 1..8 = grid bin on square pixels of side delta * 2^(l-1) lattice
+ *   steps anchored at the plan box corner (nested resolutions).  A grid
+ *   pixel carries the sums of w gamma and w of its galaxies (FP64, rounded
+ *   once to FP32) at its corner; G_m, W_m of a grid bin are the harmonic
+ *   sums over non-empty pixels around each non-empty pixel (the
+ *   convolution of the gridded values with the bin kernels).  A block
+ *   (b1, b2) is the sum over galaxies of the centre factor times the
+ *   harmonics, those of a grid bin taken at the galaxy's pixel: for two
+ *   bins of one grid level this is the grid estimator over pixels; across
+ *   levels it is the finer side's w gamma G summed into the coarser pixels
+ *   and contracted with the coarse harmonics.  Diagonal blocks of a grid
+ *   bin remove the degenerate pairs of one neighbour pixel (the discrete
+ *   estimator's j = k reading, applied to the pixel catalog) unless
+ *   T3_FLAG_KEEP_JK.
+ * delta: base pixel side in lattice steps, >= 1; for every level used,
+ *   side <= box_size and box_size / side <= 8192.  Every galaxy is a centre.
+ * ups_out: t3_forward layout.  n_pairs: HOST, optional: galaxy pairs of the
+ *   discrete bins plus pixel pairs of the grid bins.  Synchronises the
+ *   stream (pixel counts are read back to size the pixel catalogs). */
+int t3_forward_grid(t3_plan *plan, const t3_catalog *cat, int64_t delta, const int32_t *levels,
+                    double *ups_out, int64_t *n_pairs, void *stream);
+
 /* Stage 1 alone, for inspection: the harmonic sums of eq. (Gn_disc) for
  * the given centres against the neighbour catalog.
  * centres: DEVICE int32 [n_centres] indices into cat.

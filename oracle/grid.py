@@ -100,10 +100,13 @@ def _rows_at(units_x, units_y, coarse: PixelCatalog, box_lo):
 
 
 def _regrid(rows, values, n_rows):
-    """Sum of per-unit values [n_units, ...] into their coarse pixels."""
-    out = np.zeros((n_rows,) + values.shape[1:], dtype=values.dtype)
-    np.add.at(out, rows, values)
-    return out
+    """Sum of per-unit values [n_units, ...] into their coarse pixels: the
+    product with the 0/1 membership matrix M[P, u] = [unit u lies in P]."""
+    from scipy.sparse import csr_matrix
+    n_units = rows.shape[0]
+    M = csr_matrix((np.ones(n_units), (rows, np.arange(n_units))), shape=(n_rows, n_units))
+    flat = values.reshape(n_units, -1)
+    return np.asarray(M @ flat).reshape((n_rows,) + values.shape[1:])
 
 
 def _cross_blocks(cf, wf, hf, rows, hL, n_rows, n_max, w_max, fine_is_b1):
@@ -112,11 +115,18 @@ def _cross_blocks(cf, wf, hf, rows, hL, n_rows, n_max, w_max, fine_is_b1):
     Returns ups[4, 2 n_max + 1, Bf, BL] (fine_is_b1) or [.., BL, Bf], and N."""
     gf = lambda m: m - hf["m_lo"]  # noqa: E731
     gl = lambda m: m - hL["m_lo"]  # noqa: E731
-    Gf, GL, Wf, WL = hf["G"], hL["G"], hf["W"], hL["W"]
-    c = cf.astype(np.complex128)
-    cc = np.conj(c)
-    R = lambda v: _regrid(rows, v, n_rows)  # noqa: E731
-    Bf, BL = Gf.shape[1], GL.shape[1]
+    c = cf.astype(np.complex128)[:, None, None]
+    # the finer side's products with the centre factor, summed into the
+    # level-L pixels (every order at once)
+    Ac = _regrid(rows, c * hf["G"], n_rows)                  # sum c G
+    Acc = _regrid(rows, np.conj(c) * hf["G"], n_rows)        # sum c* G
+    Acj = _regrid(rows, c * np.conj(hf["G"]), n_rows)        # sum c conj G
+    Aw = _regrid(rows, wf[:, None, None] * hf["W"], n_rows)  # sum w W
+    Bf, BL = hf["G"].shape[1], hL["G"].shape[1]
+    # order axis first: every [pixel, bin] slice below is contiguous
+    first = lambda a: np.ascontiguousarray(np.moveaxis(a, 2, 0))  # noqa: E731
+    Ac, Acc, Acj, Aw = first(Ac), first(Acc), first(Acj), first(Aw)
+    GL, WL = first(hL["G"]), first(hL["W"])
     shp = (Bf, BL) if fine_is_b1 else (BL, Bf)
     ups = np.zeros((4, 2 * n_max + 1) + shp, np.complex128)
     N = np.zeros((2 * w_max + 1,) + shp, np.complex128)
@@ -124,21 +134,21 @@ def _cross_blocks(cf, wf, hf, rows, hL, n_rows, n_max, w_max, fine_is_b1):
         k = n + n_max
         if fine_is_b1:
             # sum_P [sum_{u in P} X(u, b1)] Y(P, b2), X carrying the centre factor
-            ups[0, k] = -R(c[:, None] * Gf[:, :, gf(n - 3)]).T @ GL[:, :, gl(-n - 3)]
-            ups[1, k] = -R(cc[:, None] * Gf[:, :, gf(n - 1)]).T @ GL[:, :, gl(-n - 1)]
-            ups[2, k] = -R(c[:, None] * np.conj(Gf[:, :, gf(-n - 1)])).T @ GL[:, :, gl(-n - 3)]
-            ups[3, k] = -R(c[:, None] * Gf[:, :, gf(n - 3)]).T @ np.conj(GL[:, :, gl(n - 1)])
+            ups[0, k] = -Ac[gf(n - 3)].T @ GL[gl(-n - 3)]
+            ups[1, k] = -Acc[gf(n - 1)].T @ GL[gl(-n - 1)]
+            ups[2, k] = -Acj[gf(-n - 1)].T @ GL[gl(-n - 3)]
+            ups[3, k] = -Ac[gf(n - 3)].T @ np.conj(GL[gl(n - 1)])
         else:
             # sum_P X'(P, b1) [sum_{u in P} c_u Y(u, b2)], X' without the centre factor
-            ups[0, k] = -GL[:, :, gl(n - 3)].T @ R(c[:, None] * Gf[:, :, gf(-n - 3)])
-            ups[1, k] = -GL[:, :, gl(n - 1)].T @ R(cc[:, None] * Gf[:, :, gf(-n - 1)])
-            ups[2, k] = -np.conj(GL[:, :, gl(-n - 1)]).T @ R(c[:, None] * Gf[:, :, gf(-n - 3)])
-            ups[3, k] = -GL[:, :, gl(n - 3)].T @ R(c[:, None] * np.conj(Gf[:, :, gf(n - 1)]))
+            ups[0, k] = -GL[gl(n - 3)].T @ Ac[gf(-n - 3)]
+            ups[1, k] = -GL[gl(n - 1)].T @ Acc[gf(-n - 1)]
+            ups[2, k] = -np.conj(GL[gl(-n - 1)]).T @ Ac[gf(-n - 3)]
+            ups[3, k] = -GL[gl(n - 3)].T @ Acj[gf(n - 1)]
     for n in range(-w_max, w_max + 1):
         if fine_is_b1:
-            N[n + w_max] = R(wf[:, None] * Wf[:, :, n + hf["w_max"]]).T @ np.conj(WL[:, :, n + hL["w_max"]])
+            N[n + w_max] = Aw[n + hf["w_max"]].T @ np.conj(WL[n + hL["w_max"]])
         else:
-            N[n + w_max] = WL[:, :, n + hL["w_max"]].T @ R(wf[:, None] * np.conj(Wf[:, :, n + hf["w_max"]]))
+            N[n + w_max] = WL[n + hL["w_max"]].T @ np.conj(Aw[n + hf["w_max"]])
     return ups, N
 
 

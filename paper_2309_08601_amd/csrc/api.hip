@@ -353,6 +353,10 @@ void t3_plan_destroy(t3_plan *plan)
     plan->queue.release();
     plan->tune_idx.release();
     plan->tune_out.release();
+    plan->sph_a.release();
+    plan->sph_b.release();
+    plan->sph_out.release();
+    for (auto &lv : plan->grid) lv.release();
     if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
@@ -500,6 +504,34 @@ int t3_forward_sphere(t3_plan *plan, const t3_sphere_catalog *cat, const t3_patc
         return T3_OK;
     } catch (...) {
         return fail(T3_EINVAL, "t3_forward_sphere: exception");
+    }
+}
+
+int t3_forward_grid(t3_plan *plan, const t3_catalog *cat, int64_t delta, const int32_t *levels, double *ups_out,
+                    int64_t *n_pairs, void *stream)
+{
+    try {
+        if (!plan || !levels || !ups_out) return fail(T3_EINVAL, "t3_forward_grid: null argument");
+        T3_TRY(check_catalog(cat, "t3_forward_grid"));
+        if (delta < 1 || delta > plan->box_size)
+            return fail(T3_EINVAL, "t3_forward_grid: delta must be in [1, box_size] lattice steps");
+        for (int b = 0; b < plan->B; ++b) {
+            const int l = levels[b];
+            if (l < 0 || l > kMaxGridLevels)
+                return fail(T3_EINVAL, "t3_forward_grid: levels must be in [0, 8]");
+            if (b > 0 && l < levels[b - 1]) return fail(T3_EINVAL, "t3_forward_grid: levels must not decrease");
+            if (l > 0) {
+                const int64_t side = delta << (l - 1);
+                if (side > plan->box_size)
+                    return fail(T3_ERANGE, "t3_forward_grid: pixel side of a level exceeds the box");
+                if ((plan->box_size + side - 1) / side > 8192)
+                    return fail(T3_ERANGE, "t3_forward_grid: more than 8192 pixels along the box (coarser delta "
+                                           "or a smaller box)");
+            }
+        }
+        return forward_grid(plan, *cat, delta, levels, ups_out, n_pairs, (hipStream_t)stream);
+    } catch (...) {
+        return fail(T3_EINVAL, "t3_forward_grid: exception");
     }
 }
 

@@ -153,6 +153,8 @@ __global__ void k_fill_int(int *__restrict__ p, int64_t n, int v)
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+}  // namespace
+
 int fill_int(int *p, int64_t n, int v, hipStream_t s)
 {
     if (n <= 0) return T3_OK;
@@ -176,8 +178,6 @@ int exclusive_scan(int *data, int64_t n, DevBuf &tmp, hipStream_t s)
     T3_HIP_CHECK(hipGetLastError());
     return T3_OK;
 }
-
-}  // namespace
 
 CellGrid choose_grid(const t3_plan *plan, int64_t n_gal)
 {

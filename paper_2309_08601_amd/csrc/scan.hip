@@ -45,7 +45,8 @@ struct ScanArgs {
     int n_z;
     const int2 *cpos;       // centre positions (chunk-relative)
     int n_c;                // centres in the chunk
-    int n_bins;
+    int n_bins;             // bins swept (squared edges e2[0 .. n_bins])
+    int B_out;              // bins of the plane layout (swept bin b is stored as bin b)
     int n_max;
     int K;                  // chunk capacity (plane layout)
     const short *dest;      // slot -> plane (or -1) for this pass
@@ -257,7 +258,7 @@ __device__ __forceinline__ unsigned long long scan_task(const ScanArgs &a, int z
         for (int k = 0; k < S::P; ++k) {
             const int slot = S::P * lane + k;
             const int pl = a.dest[slot];
-            if (pl >= 0) out[chunk_offset(pl, ci, b, a.K, a.n_bins)] = (float)accd[k];
+            if (pl >= 0) out[chunk_offset(pl, ci, b, a.K, a.B_out)] = (float)accd[k];
         }
     }
     return pairs;
@@ -449,9 +450,11 @@ int scan_prepare(t3_plan *plan)
 
 int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order, int n_z,
                const CentreSet &cs, int64_t c0, int n_c, const ChunkLayout &L, float *planes,
-               size_t zstride, unsigned long long *npairs, int mode, hipStream_t s)
+               size_t zstride, unsigned long long *npairs, int mode, hipStream_t s, int b0, int nb)
 {
     if (n_c <= 0) return T3_OK;
+    if (nb < 0) nb = L.B;
+    if (b0 < 0 || nb < 1 || nb > L.B || b0 + nb > plan->B) return fail(T3_ERANGE, "scan: bad bin range");
     if (n_z < 1 || n_z > kMaxZ) return fail(T3_ERANGE, "scan: bad catalog count");
     if (plan->scan_var < 0) T3_TRY(scan_prepare(plan));
     const Variant &var = variants()[plan->scan_var];
@@ -468,10 +471,11 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
     a.n_z = n_z;
     a.cpos = cs.pos.as<int2>() + c0;
     a.n_c = n_c;
-    a.n_bins = L.B;
+    a.n_bins = nb;
+    a.B_out = L.B;
     a.n_max = L.n_max;
     a.K = L.K;
-    for (int b = 0; b <= L.B; ++b) a.e2[b] = plan->e2[b];
+    for (int b = 0; b <= nb; ++b) a.e2[b] = plan->e2[b0 + b];
     const int total = n_z * n_c;
     int nwg;
     if (mode == 1) {

@@ -98,6 +98,28 @@ struct CentreSet {
     DevBuf cw;   // float4[n]
 };
 
+// One resolution of the grid-based estimator: its non-empty pixels as a
+// catalog and the stage-1 planes of its bins at every pixel.
+constexpr int kMaxGridLevels = 8;
+struct GridLevel {
+    int b_lo = 0, nb = 0;   // bins [b_lo, b_lo + nb) use this level
+    int64_t side = 0;       // pixel side, lattice steps
+    int64_t n_pix = 0;      // non-empty pixels
+    SortedCatalog by_pix;   // galaxies sorted by pixel (cell = pixel)
+    DevBuf pix_id;          // int [ncells + 1]: exclusive scan of the non-empty flags
+    DevBuf pix_xy;          // int32 x [n_pix], y [n_pix]: pixel corners
+    DevBuf pix_sum;         // double [n_pix][3]: sum w g1, sum w g2, sum w
+    DevBuf pix_gw;          // float g1 [n_pix], g2 [n_pix], w [n_pix] (catalog view)
+    DevBuf gal_pix;         // int [n_gal]: galaxy (input order) -> pixel
+    SortedCatalog pix;      // the pixel catalog, cell-sorted for the sweep
+    CentreSet pix_centres;  // every pixel, in pix's sorted order
+    DevBuf slot_of_pix;     // int [n_pix]: pixel -> sorted slot in pix
+    DevBuf cen_slot;        // int [n_gal]: galaxy (sorted slot) -> sorted pixel slot
+    DevBuf planes;          // stage-1 planes of every pixel, layout L
+    ChunkLayout L;
+    void release();
+};
+
 }  // namespace t3
 
 // ---------------------------------------------------------------- plan
@@ -133,6 +155,7 @@ struct t3_plan {
     t3::DevBuf misc;      // adjoint scratch
     t3::DevBuf misc2;
     t3::DevBuf sph_a, sph_b, sph_out;  // sphere patches: projection, compaction, per-patch output
+    t3::GridLevel grid[t3::kMaxGridLevels];  // grid-based estimator, level l at grid[l - 1]
     int scan_var = -1;          // stage-1 variant index (see scan.hip)
     size_t scan_dest_off[3] = {0, 0, 0};  // main passes, then the W extension
 
@@ -158,10 +181,15 @@ int scan_prepare(t3_plan *plan);
 // Stage 1 for centres [c0, c0 + n_c) of cs against n_z neighbour catalogs
 // (planes of catalog z at planes + z * zstride).  mode 0: one wavefront per
 // centre, one launch per catalog; mode 1: one persistent launch over every
-// (centre, catalog) task with a work counter.
+// (centre, catalog) task with a work counter.  Only the plan's bins
+// [b0, b0 + nb) are swept (nb < 0: all L.B of them); swept bin k is stored
+// as bin k of the layout L (L.B >= nb).
 int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order, int n_z,
                const CentreSet &cs, int64_t c0, int n_c, const ChunkLayout &L, float *planes,
-               size_t zstride, unsigned long long *npairs, int mode, hipStream_t s);
+               size_t zstride, unsigned long long *npairs, int mode, hipStream_t s, int b0 = 0,
+               int nb = -1);
+int fill_int(int *p, int64_t n, int v, hipStream_t s);
+int exclusive_scan(int *data, int64_t n, DevBuf &tmp, hipStream_t s);  // in place, n <= 2^30
 int zero_doubles(double *p, size_t n, hipStream_t s);
 int reserve_contract(t3_plan *plan, const ChunkLayout &L, int n_z);
 int contract_slice(const ChunkLayout &L, int n_z);
@@ -179,6 +207,8 @@ int aperture_stats(t3_plan *plan, const double *gamma_cent, int n_sets, int n_ph
 int sphere_patch(t3_plan *plan, const t3_sphere_catalog &cat, const t3_patch &p, double theta_max_arcmin,
                  t3_catalog *view, const int32_t **core, int64_t *n_core, hipStream_t s);
 int add_doubles(double *dst, const double *src, size_t n, hipStream_t s);
+int forward_grid(t3_plan *plan, const t3_catalog &cat, int64_t delta, const int32_t *levels, double *ups_out,
+                 int64_t *n_pairs, hipStream_t s);
 int harmonics_export(t3_plan *plan, const CentreSet &cs, const ChunkLayout &L, const float *planes,
                      int64_t c0, int n_c, float *G, float *W, float *D, hipStream_t s);
 int normalise_backward(t3_plan *plan, const double *ups, const double *ggam, int n_sets, double *gups,

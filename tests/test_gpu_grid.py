@@ -1,0 +1,102 @@
+"""Grid-based and combined estimators on the GPU (Sect. 3.2-3.3, Appendix A)
+against the oracle's regrid-then-contract evaluation of every block.
+
+Cases: mixed discrete / multi-resolution levels, unused levels between used
+ones, every bin on one grid, edge correction (N to 2 n_max), n_max = 30,
+ragged chunks (the gather across chunk offsets), all-discrete levels equal
+to the plain forward pass, and a field-shaped case with the bins and level
+rule of the 1M-galaxy field on a 50k-galaxy catalog.  The pixel anchor is
+the plan box corner, offset from the catalog by an odd number of steps."""
+import numpy as np
+import pytest
+
+from paper_2309_08601_amd.synth import LATTICE_UNIT, random_catalog
+from _util import FP32_TOL, rel_fro
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def t3():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08601_amd import t3 as mod
+    return mod
+
+
+def _pack(ups, N, nm, wm):
+    B = ups.shape[-1]
+    return np.concatenate([ups[:, nm:].reshape(4 * (nm + 1), B, B), N[wm:]], axis=0)
+
+
+def _compare(t3, plan, cat, edges, nm, delta, levels, ec, box_lo, label):
+    from oracle import grid as og
+    ups, npairs = plan.forward_grid(t3.DeviceCatalog.from_catalog(cat), delta, levels)
+    wm = 2 * nm if ec else nm
+    o = og.multipoles_combined(cat, edges, nm, delta, levels, box_lo=box_lo, w_max=wm)
+    ref = _pack(o["ups"], o["N"], nm, wm)
+    got = ups.cpu().numpy().reshape(ref.shape)
+    u_err = rel_fro(got[:4 * (nm + 1)], ref[:4 * (nm + 1)]).max()
+    n0 = np.linalg.norm(ref[4 * (nm + 1)])
+    n_err = np.max([np.linalg.norm(got[4 * (nm + 1) + k] - ref[4 * (nm + 1) + k]) / n0 for k in range(wm + 1)])
+    print(f"{label}: levels {levels}, {npairs} pairs, Upsilon {u_err:.2e}, N_n/N_0 {n_err:.2e}", flush=True)
+    assert npairs == o["npairs"]
+    assert u_err <= FP32_TOL and n_err <= FP32_TOL
+    return ups
+
+
+CASES = [
+    ("mixed", [0, 0, 1, 1, 2, 3], 6, False),
+    ("gap", [0, 0, 2, 2, 2, 4], 4, False),
+    ("all_grid", [1, 1, 1, 1, 1, 1], 5, False),
+    ("edge_correct", [0, 0, 1, 1, 2, 3], 5, True),
+    ("nmax30", [0, 0, 0, 1, 1, 2], 30, False),
+]
+
+
+@pytest.mark.parametrize("label,levels,nm,ec", CASES, ids=[c[0] for c in CASES])
+def test_combined_matches_oracle(t3, label, levels, nm, ec):
+    cat = random_catalog(5000, 50.0, seed=1200 + nm)
+    edges = np.geomspace(1.0, 14.0, 7)
+    box_lo = (-12345, -6789)
+    plan = t3.Plan(edges, nm, box_lo=box_lo, box_size=1 << 23, edge_correct=ec)
+    _compare(t3, plan, cat, edges, nm, int(0.25 / LATTICE_UNIT), levels, ec, box_lo, label)
+
+
+def test_combined_ragged_chunks(t3):
+    """256-centre chunks over 3001 galaxies: the last chunk is partial and
+    the gather runs at every chunk offset."""
+    cat = random_catalog(3001, 40.0, seed=77)
+    edges = np.geomspace(1.0, 12.0, 6)
+    box_lo = (-333, 0)
+    plan = t3.Plan(edges, 8, box_lo=box_lo, box_size=1 << 23, chunk_centres=256)
+    _compare(t3, plan, cat, edges, 8, int(0.5 / LATTICE_UNIT), [0, 1, 1, 2, 2], False, box_lo, "ragged")
+
+
+def test_all_discrete_levels_equal_forward(t3):
+    cat = random_catalog(4000, 40.0, seed=91)
+    edges = np.geomspace(1.0, 12.0, 6)
+    plan = t3.Plan(edges, 10, box_lo=(0, 0), box_size=1 << 23)
+    dc = t3.DeviceCatalog.from_catalog(cat)
+    a, na = plan.forward(dc)
+    b, nb = plan.forward_grid(dc, 1 << 14, [0] * 5)
+    assert na == nb
+    rel = (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(a)).item()
+    assert rel < 1e-12, rel
+
+
+def test_combined_field_shaped(t3):
+    """The 1M field's bins (20 log bins 0.5'-100', n_max = 30) and level rule
+    (Delta_1 = 0.25', grid where the lower edge >= 20 Delta_l: levels 1-4
+    above 5') on 15k galaxies of its shear and weight model in a 150' x 150'
+    field."""
+    import dataclasses
+    from paper_2309_08601_amd.synth import WORKLOADS, make_catalogs
+    wl = dataclasses.replace(WORKLOADS["field_1m"], side=150.0)
+    cat = make_catalogs(wl, n_override=[15_000])[0]
+    edges = wl.edges()
+    levels = t3.grid_levels(edges, 0.25)
+    assert max(levels) == 4 and levels.count(0) == 9
+    plan = t3.Plan(edges, wl.n_max, box_lo=(0, 0), box_size=1 << 24)
+    _compare(t3, plan, cat, edges, wl.n_max, int(0.25 / LATTICE_UNIT), levels, False, (0, 0), "field-shaped")
