@@ -132,6 +132,11 @@ typedef struct {
 
 typedef struct t3_plan t3_plan;
 
+/* Routes of t3_forward_grid for a grid level. */
+#define T3_GRID_AUTO 0
+#define T3_GRID_DIRECT 1
+#define T3_GRID_FFT 2
+
 /* Create a plan: validates parameters, derives squared edges and the
  * cell grid, and picks the stage-1 kernel variant for n_max.  No device
  * memory is allocated here.  *out is set only on success. */
@@ -206,11 +211,16 @@ int t3_forward_sphere(t3_plan *plan, const t3_sphere_catalog *cat, const t3_patc
  *   T3_FLAG_KEEP_JK.
  * delta: base pixel side in lattice steps, >= 1; for every level used,
  *   side <= box_size and box_size / side <= 8192.  Every galaxy is a centre.
+ * method: how a level's harmonics are computed: T3_GRID_DIRECT (pair sums
+ *   over the non-empty pixels), T3_GRID_FFT (FFT convolution on a dense
+ *   grid of the occupied pixels, sides products of 2, 3, 5 up to 8192; FP32
+ *   transforms) or T3_GRID_AUTO (a cost model picks per level).
  * ups_out: t3_forward layout.  n_pairs: HOST, optional: galaxy pairs of the
- *   discrete bins plus pixel pairs of the grid bins.  Synchronises the
- *   stream (pixel counts are read back to size the pixel catalogs). */
+ *   discrete bins plus pixel pairs of the levels summed pairwise (FFT
+ *   levels add none).  Synchronises the stream (pixel counts and extents
+ *   are read back to size the pixel catalogs and grids). */
 int t3_forward_grid(t3_plan *plan, const t3_catalog *cat, int64_t delta, const int32_t *levels,
-                    double *ups_out, int64_t *n_pairs, void *stream);
+                    int32_t method, double *ups_out, int64_t *n_pairs, void *stream);
 
 /* Stage 1 alone, for inspection: the harmonic sums of eq. (Gn_disc) for
  * the given centres against the neighbour catalog.

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libt3pcf.so")
-SOURCES = ["api.hip", "cells.hip", "scan.hip", "contract.hip", "finish.hip", "adjoint.hip", "aperture.hip", "sphere.hip", "grid.hip"]
+SOURCES = ["api.hip", "cells.hip", "scan.hip", "contract.hip", "finish.hip", "adjoint.hip", "aperture.hip", "sphere.hip", "grid.hip", "fft.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -507,12 +507,14 @@ int t3_forward_sphere(t3_plan *plan, const t3_sphere_catalog *cat, const t3_patc
     }
 }
 
-int t3_forward_grid(t3_plan *plan, const t3_catalog *cat, int64_t delta, const int32_t *levels, double *ups_out,
-                    int64_t *n_pairs, void *stream)
+int t3_forward_grid(t3_plan *plan, const t3_catalog *cat, int64_t delta, const int32_t *levels, int32_t method,
+                    double *ups_out, int64_t *n_pairs, void *stream)
 {
     try {
         if (!plan || !levels || !ups_out) return fail(T3_EINVAL, "t3_forward_grid: null argument");
         T3_TRY(check_catalog(cat, "t3_forward_grid"));
+        if (method != T3_GRID_AUTO && method != T3_GRID_DIRECT && method != T3_GRID_FFT)
+            return fail(T3_EINVAL, "t3_forward_grid: unknown method");
         if (delta < 1 || delta > plan->box_size)
             return fail(T3_EINVAL, "t3_forward_grid: delta must be in [1, box_size] lattice steps");
         for (int b = 0; b < plan->B; ++b) {
@@ -529,7 +531,7 @@ int t3_forward_grid(t3_plan *plan, const t3_catalog *cat, int64_t delta, const i
                                            "or a smaller box)");
             }
         }
-        return forward_grid(plan, *cat, delta, levels, ups_out, n_pairs, (hipStream_t)stream);
+        return forward_grid(plan, *cat, delta, levels, method, ups_out, n_pairs, (hipStream_t)stream);
     } catch (...) {
         return fail(T3_EINVAL, "t3_forward_grid: exception");
     }

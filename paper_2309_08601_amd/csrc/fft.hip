@@ -1,0 +1,531 @@
+// Grid harmonics by FFT convolution (Porth et al. 2023, Sect. 3.2: the
+// G_n^Delta and W_n^Delta of a grid are convolutions of the gridded w gamma
+// and w with the bin kernels g_{n;Theta}, computed with FFTs).
+//
+// One level of the combined estimator: the non-empty pixels' values are
+// placed on a dense grid covering the occupied pixels plus a zero margin of
+// the largest separation R (in pixels) of the level's bins, so that the
+// circular convolution equals the linear one on the occupied part; the grid
+// sides are products of 2, 3 and 5 (at most 8192).  Fields: c = sum w gamma,
+// w, c^2, |c|^2, w^2 (the last three for the j = k sums).  For each bin and
+// order m the kernel K(d) = e^{i m phi(d)} [|d| in bin] (d the offset from the
+// centre pixel to the neighbour pixel, bin membership from the same FP64
+// squared separations as the pair sums) is placed at -d (a correlation),
+// transformed, multiplied with each field's spectrum that needs order m, and
+// transformed back; the values at the non-empty pixels are written into the
+// level's stage-1 planes.
+//
+// 2-D transforms: rows by a Stockham FFT in LDS (one workgroup per row, radix
+// 2, 3, 4, 5 or 8 per stage, twiddles from an FP64-computed table), then a
+// tiled transpose, then rows again; the spectrum stays transposed, and the
+// inverse runs the same three steps back.  FP32 arithmetic.
+#include "t3_internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace t3 {
+namespace {
+
+constexpr int kFftThreads = 256;
+constexpr int kFftMax = 8192;   // largest side (64 KiB of LDS per row)
+constexpr int kMaxStages = 16;
+
+struct RowPlan {
+    int n = 0;                  // transform length
+    int ns = 0;                 // stages
+    int radix[kMaxStages];
+    const float2 *tw = nullptr; // e^{-2 pi i k / n}, k < n
+};
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// (s i) z for s = +-1
+__device__ __forceinline__ float2 rot_i(float2 z, float s) { return make_float2(-s * z.y, s * z.x); }
+
+// In-register DFT of size R: X_k = sum_j v_j e^{s 2 pi i j k / R} (s = -1
+// forward, +1 inverse), written out from the definition.
+template <int R> struct Dft;
+template <> struct Dft<2> {
+    __device__ static void run(float2 *v, float)
+    {
+        const float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+template <> struct Dft<3> {
+    __device__ static void run(float2 *v, float s)
+    {
+        const float c = -0.5f, sn = 0.86602540378443864676f;  // cos, sin of 2 pi / 3
+        const float2 b = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+        const float2 t = make_float2(v[0].x + c * b.x, v[0].y + c * b.y);
+        const float2 u = rot_i(cscale(d, sn), s);
+        v[0] = cadd(v[0], b);
+        v[1] = cadd(t, u);
+        v[2] = csub(t, u);
+    }
+};
+template <> struct Dft<4> {
+    __device__ static void run(float2 *v, float s)
+    {
+        const float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+        const float2 a2 = cadd(v[1], v[3]), a3 = rot_i(csub(v[1], v[3]), s);
+        v[0] = cadd(a0, a2);
+        v[2] = csub(a0, a2);
+        v[1] = cadd(a1, a3);
+        v[3] = csub(a1, a3);
+    }
+};
+template <> struct Dft<5> {
+    __device__ static void run(float2 *v, float s)
+    {
+        const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;  // cos 2pi/5, 4pi/5
+        const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;   // sin 2pi/5, 4pi/5
+        const float2 b1 = cadd(v[1], v[4]), b2 = cadd(v[2], v[3]);
+        const float2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+        const float2 t1 = make_float2(v[0].x + c1 * b1.x + c2 * b2.x, v[0].y + c1 * b1.y + c2 * b2.y);
+        const float2 t2 = make_float2(v[0].x + c2 * b1.x + c1 * b2.x, v[0].y + c2 * b1.y + c1 * b2.y);
+        const float2 u1 = rot_i(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y), s);
+        const float2 u2 = rot_i(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y), s);
+        v[0] = cadd(v[0], cadd(b1, b2));
+        v[1] = cadd(t1, u1);
+        v[4] = csub(t1, u1);
+        v[2] = cadd(t2, u2);
+        v[3] = csub(t2, u2);
+    }
+};
+template <> struct Dft<8> {
+    __device__ static void run(float2 *v, float s)
+    {
+        float2 e[4] = {v[0], v[2], v[4], v[6]};
+        float2 o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4>::run(e, s);
+        Dft<4>::run(o, s);
+        const float h = 0.70710678118654752440f;
+        // o_k times e^{s 2 pi i k / 8}
+        o[1] = make_float2(h * (o[1].x - s * o[1].y), h * (o[1].y + s * o[1].x));
+        o[2] = rot_i(o[2], s);
+        o[3] = make_float2(h * (-o[3].x - s * o[3].y), h * (-o[3].y + s * o[3].x));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = cadd(e[k], o[k]);
+            v[k + 4] = csub(e[k], o[k]);
+        }
+    }
+};
+
+// One Stockham stage of radix R over buf[0, n) (sub-transforms of size ns
+// so far): butterfly j takes buf[j + r n/R], twiddles by
+// e^{s 2 pi i r (j mod ns) / (ns R)}, and writes buf[(j / ns) ns R + j mod ns + r ns].
+// Every thread first loads all of its butterflies, then the workgroup
+// synchronises and stores (one buffer serves as source and destination).
+template <int R>
+__device__ __forceinline__ void stage(float2 *buf, const RowPlan &p, int ns, float s)
+{
+    constexpr int MB = (kFftMax / R + kFftThreads - 1) / kFftThreads;
+    const int nb = p.n / R;
+    float2 v[MB][R];
+#pragma unroll
+    for (int q = 0; q < MB; ++q) {
+        const int j = threadIdx.x + q * kFftThreads;
+        if (j < nb) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = buf[j + r * nb];
+        }
+    }
+    __syncthreads();
+    const int tw_step = p.n / (ns * R);
+#pragma unroll
+    for (int q = 0; q < MB; ++q) {
+        const int j = threadIdx.x + q * kFftThreads;
+        if (j < nb) {
+            const int k = j % ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = p.tw[(r * k * tw_step) % p.n];
+                w.y *= -s;  // table holds e^{-2 pi i t / n}; s = +1 conjugates
+                v[q][r] = cmul(v[q][r], make_float2(w.x, w.y));
+            }
+            Dft<R>::run(v[q], s);
+            const int base = (j / ns) * ns * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[base + r * ns] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+__device__ void fft_lds(float2 *buf, const RowPlan &p, float s)
+{
+    int ns = 1;
+    for (int st = 0; st < p.ns; ++st) {
+        const int R = p.radix[st];
+        switch (R) {
+            case 2: stage<2>(buf, p, ns, s); break;
+            case 3: stage<3>(buf, p, ns, s); break;
+            case 4: stage<4>(buf, p, ns, s); break;
+            case 5: stage<5>(buf, p, ns, s); break;
+            default: stage<8>(buf, p, ns, s); break;
+        }
+        ns *= R;
+    }
+}
+
+// ---------------------------------------------------------------- loaders / storers
+struct LoadGrid {   // src[row * n + i]
+    const float2 *src;
+    __device__ float2 operator()(int row, int i, int n) const { return src[(size_t)row * n + i]; }
+};
+struct LoadProduct {  // a[row * n + i] b[row * n + i]
+    const float2 *a, *b;
+    __device__ float2 operator()(int row, int i, int n) const
+    {
+        const size_t o = (size_t)row * n + i;
+        return cmul(a[o], b[o]);
+    }
+};
+// Kernel of order m and bin [e2lo, e2hi) on a grid of nx x ny pixels of side
+// `side` lattice steps; grid point (x, y) holds K(-signed(x), -signed(y)).
+struct LoadKernel {
+    int nx, ny, rx, ry, m;
+    double side, e2lo, e2hi;
+    __device__ float2 operator()(int row, int i, int) const
+    {
+        const int sx = i <= nx / 2 ? i : i - nx;
+        const int sy = row <= ny / 2 ? row : row - ny;
+        const int dx = -sx, dy = -sy;
+        if (dx > rx || dx < -rx || dy > ry || dy < -ry) return make_float2(0.f, 0.f);
+        const double ddx = (double)dx * side, ddy = (double)dy * side;
+        const double r2 = fma(ddx, ddx, ddy * ddy);
+        if (!(r2 >= e2lo && r2 < e2hi)) return make_float2(0.f, 0.f);
+        const double r = sqrt((double)dx * dx + (double)dy * dy);
+        double zr = dx / r, zi = m < 0 ? -dy / r : dy / r;
+        double pr = 1.0, pi = 0.0;
+        for (int e = m < 0 ? -m : m; e > 0; e >>= 1) {  // z^|m| by squaring, FP64
+            if (e & 1) {
+                const double t = pr * zr - pi * zi;
+                pi = pr * zi + pi * zr;
+                pr = t;
+            }
+            const double t = zr * zr - zi * zi;
+            zi = 2.0 * zr * zi;
+            zr = t;
+        }
+        return make_float2((float)pr, (float)pi);
+    }
+};
+struct StoreGrid {
+    float2 *dst;
+    __device__ void operator()(int row, int i, int n, float2 v) const { dst[(size_t)row * n + i] = v; }
+};
+// Values at the non-empty pixels into stage-1 planes (layout K, nb).
+struct StorePlanes {
+    const int *slot;   // [ny_occ][nx_occ] sorted pixel slot or -1
+    int nx_occ, ny_occ;
+    float *planes;
+    int p_re, p_im;    // planes (p_im < 0: real part only)
+    int K, nb, b;
+    float scale;
+    __device__ void operator()(int row, int i, int, float2 v) const
+    {
+        if (row >= ny_occ || i >= nx_occ) return;
+        const int sl = slot[(size_t)row * nx_occ + i];
+        if (sl < 0) return;
+        planes[chunk_offset(p_re, sl, b, K, nb)] = v.x * scale;
+        if (p_im >= 0) planes[chunk_offset(p_im, sl, b, K, nb)] = v.y * scale;
+    }
+};
+
+// One workgroup per row: load, transform in LDS, store.  rows[] maps block ->
+// row when given (kernel generation touches only the rows that can be non-zero).
+template <class Load, class Store>
+__global__ __launch_bounds__(kFftThreads) void k_fft_rows(RowPlan p, float s, Load ld, Store st, int row0,
+                                                          int row_gap, int gap_len)
+{
+    extern __shared__ float2 lds[];
+    int row = row0 + (int)blockIdx.x;
+    if (gap_len > 0 && row >= row_gap) row += gap_len;
+    for (int i = threadIdx.x; i < p.n; i += kFftThreads) lds[i] = ld(row, i, p.n);
+    __syncthreads();
+    fft_lds(lds, p, s);
+    for (int i = threadIdx.x; i < p.n; i += kFftThreads) st(row, i, p.n, lds[i]);
+}
+
+// dst[c][r] = src[r][c] for src of rows x cols
+constexpr int kTile = 32;
+__global__ __launch_bounds__(256) void k_transpose(const float2 *__restrict__ src, float2 *__restrict__ dst,
+                                                   int rows, int cols)
+{
+    __shared__ float2 t[kTile][kTile + 1];
+    const int c0 = blockIdx.x * kTile, r0 = blockIdx.y * kTile;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int k = ty; k < kTile; k += 8) {
+        const int r = r0 + k, c = c0 + tx;
+        if (r < rows && c < cols) t[k][tx] = src[(size_t)r * cols + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < kTile; k += 8) {
+        const int c = c0 + k, r = r0 + tx;
+        if (r < rows && c < cols) dst[(size_t)c * rows + r] = t[tx][k];
+    }
+}
+
+__global__ void k_zero_c(float2 *p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = make_float2(0.f, 0.f);
+}
+
+// occupied pixel range: min/max corner over the pixel catalog
+__global__ void k_bbox(const int2 *__restrict__ pos, int64_t n, int *__restrict__ box)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int2 p = pos[i];
+    atomicMin(&box[0], p.x);
+    atomicMin(&box[1], p.y);
+    atomicMax(&box[2], p.x);
+    atomicMax(&box[3], p.y);
+}
+
+// five field grids ([ny][nx] complex) and the slot map from the sorted pixels
+struct ScatterArgs {
+    const int2 *pos;
+    const double *sum;   // [pixel][3], by pixel index
+    const int *perm;     // sorted slot -> pixel
+    int64_t n;
+    int x0, y0;
+    int64_t side;
+    int nx, ny, nx_occ;
+    float2 *f[5];
+    int *slot;
+};
+__global__ void k_scatter_fields(ScatterArgs a)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n) return;
+    const int2 p = a.pos[s];
+    const int x = (int)(((int64_t)p.x - a.x0) / a.side), y = (int)(((int64_t)p.y - a.y0) / a.side);
+    const int P = a.perm[s];
+    const double c1 = a.sum[3 * (int64_t)P], c2 = a.sum[3 * (int64_t)P + 1], w = a.sum[3 * (int64_t)P + 2];
+    const size_t o = (size_t)y * a.nx + x;
+    a.f[0][o] = make_float2((float)c1, (float)c2);
+    a.f[1][o] = make_float2((float)w, 0.f);
+    a.f[2][o] = make_float2((float)(c1 * c1 - c2 * c2), (float)(2.0 * c1 * c2));
+    a.f[3][o] = make_float2((float)(c1 * c1 + c2 * c2), 0.f);
+    a.f[4][o] = make_float2((float)(w * w), 0.f);
+    a.slot[(size_t)y * a.nx_occ + x] = (int)s;
+}
+
+inline unsigned nblk(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+bool smooth(int n)
+{
+    for (int f : {2, 3, 5})
+        while (n % f == 0) n /= f;
+    return n == 1;
+}
+
+int nice_size(int n)
+{
+    for (int k = std::max(n, 1); k <= kFftMax; ++k)
+        if (smooth(k)) return k;
+    return -1;
+}
+
+void factor(int n, RowPlan &p)
+{
+    p.n = n;
+    p.ns = 0;
+    for (int r : {8, 4, 2, 5, 3})
+        while (n % r == 0 && p.ns < kMaxStages) {
+            p.radix[p.ns++] = r;
+            n /= r;
+        }
+}
+
+template <class Load, class Store>
+int rows_launch(const RowPlan &p, float s, Load ld, Store st, int n_rows, hipStream_t q, int row0 = 0,
+                int row_gap = 0, int gap_len = 0)
+{
+    if (n_rows <= 0) return T3_OK;
+    hipLaunchKernelGGL((k_fft_rows<Load, Store>), dim3((unsigned)n_rows), dim3(kFftThreads),
+                       sizeof(float2) * p.n, q, p, s, ld, st, row0, row_gap, gap_len);
+    T3_HIP_CHECK(hipGetLastError());
+    return T3_OK;
+}
+
+int transpose(const float2 *src, float2 *dst, int rows, int cols, hipStream_t q)
+{
+    hipLaunchKernelGGL(k_transpose, dim3((unsigned)((cols + kTile - 1) / kTile), (unsigned)((rows + kTile - 1) / kTile)),
+                       dim3(256), 0, q, src, dst, rows, cols);
+    T3_HIP_CHECK(hipGetLastError());
+    return T3_OK;
+}
+
+}  // namespace
+
+// Occupied pixel range of a level (corners), read back to the host.
+int level_bbox(GridLevel &lv, hipStream_t s)
+{
+    lv.nx_occ = lv.ny_occ = 0;
+    if (lv.n_pix == 0) return T3_OK;
+    T3_TRY(lv.fft_misc.reserve(sizeof(int) * 4));
+    const int init[4] = {0x7fffffff, 0x7fffffff, (int)0x80000000, (int)0x80000000};
+    T3_HIP_CHECK(hipMemcpyAsync(lv.fft_misc.ptr, init, sizeof(init), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_bbox, dim3(nblk(lv.n_pix, 256)), dim3(256), 0, s, (const int2 *)lv.pix.pos.as<int2>(),
+                       lv.n_pix, lv.fft_misc.as<int>());
+    T3_HIP_CHECK(hipGetLastError());
+    T3_HIP_CHECK(hipMemcpyAsync(lv.box, lv.fft_misc.ptr, sizeof(lv.box), hipMemcpyDeviceToHost, s));
+    T3_HIP_CHECK(hipStreamSynchronize(s));
+    lv.nx_occ = (int)(((int64_t)lv.box[2] - lv.box[0]) / lv.side) + 1;
+    lv.ny_occ = (int)(((int64_t)lv.box[3] - lv.box[1]) / lv.side) + 1;
+    return T3_OK;
+}
+
+// FFT grid of a level: sides >= occupied extent + kernel reach (the reach
+// clamped to the extent - 1: larger offsets never meet data), so the
+// circular correlation equals the linear one on the occupied pixels and
+// kernel offsets are represented without overlap.  False above 8192.
+bool fft_geometry(const t3_plan *plan, const GridLevel &lv, int *nx, int *ny, int *rx, int *ry)
+{
+    const double emax = std::sqrt(plan->e2[lv.b_lo + lv.nb]);
+    const int64_t R = (int64_t)(emax / (double)lv.side) + 1;
+    *rx = (int)std::min<int64_t>(R, lv.nx_occ - 1);
+    *ry = (int)std::min<int64_t>(R, lv.ny_occ - 1);
+    if ((int64_t)lv.nx_occ + *rx > kFftMax || (int64_t)lv.ny_occ + *ry > kFftMax) return false;
+    *nx = nice_size(lv.nx_occ + *rx);
+    *ny = nice_size(lv.ny_occ + *ry);
+    return *nx > 0 && *ny > 0;
+}
+
+// Modelled time (ms) of the FFT route for a level: two-dimensional
+// transforms of three passes, each reading and writing the grid; one kernel
+// transform per order and one inverse per (field, order), per bin.
+double fft_cost_ms(const t3_plan *plan, const GridLevel &lv)
+{
+    int nx, ny, rx, ry;
+    if (lv.n_pix == 0 || !fft_geometry(plan, lv, &nx, &ny, &rx, &ry)) return 1e30;
+    const int m_lo = -plan->n_max - 3, m_hi = std::max(plan->n_max - 1, plan->w_max);
+    int kern = 0, inv = 0;
+    for (int m = m_lo; m <= m_hi; ++m) {
+        const int g = m <= plan->n_max - 1, w = m >= 0 && m <= plan->w_max;
+        const int d = (m == -6) + 2 * (m == -2) + (m == 0);
+        if (g + w + d == 0) continue;
+        ++kern;
+        inv += g + w + d;
+    }
+    const double bytes = 6.0 * sizeof(float2) * (double)nx * ny * (double)(kern + inv) * lv.nb;
+    return 1e3 * bytes / 3.0e12;
+}
+
+int fft_level(t3_plan *plan, GridLevel &lv, hipStream_t s)
+{
+    const int64_t n_pix = lv.n_pix;
+    if (n_pix == 0) return T3_OK;
+    int nx, ny, Rx, Ry;
+    if (!fft_geometry(plan, lv, &nx, &ny, &Rx, &Ry))
+        return fail(T3_ERANGE, "t3_forward_grid: FFT grid above 8192 pixels per side");
+    const int nx_occ = lv.nx_occ, ny_occ = lv.ny_occ;
+    const int *box = lv.box;
+    const size_t N = (size_t)nx * ny;
+    // buffers: five field spectra, kernel spectrum, three work grids, slot map, twiddles
+    T3_TRY(lv.fft_buf.reserve(sizeof(float2) * N * 9 + sizeof(int) * (size_t)nx_occ * ny_occ +
+                              sizeof(float2) * (size_t)(nx + ny)));
+    float2 *F[5];
+    for (int f = 0; f < 5; ++f) F[f] = lv.fft_buf.as<float2>() + (size_t)f * N;
+    float2 *Ks = F[4] + N, *A = Ks + N, *Bw = A + N, *Kg = Bw + N;
+    int *slot = reinterpret_cast<int *>(Kg + N);
+    float2 *twx = reinterpret_cast<float2 *>(slot + (size_t)nx_occ * ny_occ);
+    float2 *twy = twx + nx;
+    {
+        std::vector<float2> h(nx + ny);
+        for (int k = 0; k < nx; ++k) {
+            const double a = -2.0 * M_PI * (double)k / nx;
+            h[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+        }
+        for (int k = 0; k < ny; ++k) {
+            const double a = -2.0 * M_PI * (double)k / ny;
+            h[nx + k] = make_float2((float)std::cos(a), (float)std::sin(a));
+        }
+        T3_HIP_CHECK(hipMemcpyAsync(twx, h.data(), sizeof(float2) * h.size(), hipMemcpyHostToDevice, s));
+        T3_HIP_CHECK(hipStreamSynchronize(s));  // h leaves scope
+    }
+    RowPlan px, py;
+    factor(nx, px);
+    factor(ny, py);
+    px.tw = twx;
+    py.tw = twy;
+
+    // fields on the grid, slot map
+    hipLaunchKernelGGL(k_zero_c, dim3(nblk(N * 5, 256)), dim3(256), 0, s, F[0], N * 5);
+    T3_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_zero_c, dim3(nblk(N, 256)), dim3(256), 0, s, Kg, N);
+    T3_HIP_CHECK(hipGetLastError());
+    T3_TRY(fill_int(slot, (int64_t)nx_occ * ny_occ, -1, s));
+    ScatterArgs sa;
+    sa.pos = lv.pix.pos.as<int2>();
+    sa.sum = lv.pix_sum.as<double>();
+    sa.perm = lv.pix.perm.as<int>();
+    sa.n = n_pix;
+    sa.x0 = box[0];
+    sa.y0 = box[1];
+    sa.side = lv.side;
+    sa.nx = nx;
+    sa.ny = ny;
+    sa.nx_occ = nx_occ;
+    for (int f = 0; f < 5; ++f) sa.f[f] = F[f];
+    sa.slot = slot;
+    hipLaunchKernelGGL(k_scatter_fields, dim3(nblk(n_pix, 256)), dim3(256), 0, s, sa);
+    T3_HIP_CHECK(hipGetLastError());
+    // forward transforms: rows over x, transpose, rows over y -> spectrum [nx][ny]
+    for (int f = 0; f < 5; ++f) {
+        T3_TRY(rows_launch(px, -1.0f, LoadGrid{F[f]}, StoreGrid{A}, ny, s));
+        T3_TRY(transpose(A, Bw, ny, nx, s));
+        T3_TRY(rows_launch(py, -1.0f, LoadGrid{Bw}, StoreGrid{F[f]}, nx, s));
+    }
+
+    const ChunkLayout &L = lv.L;
+    const float scale = 1.0f / (float)N;
+    const int m_lo = -plan->n_max - 3, m_hi = std::max(plan->n_max - 1, plan->w_max);
+    // inverse transform of F[f] * Ks into planes (p_re, p_im) of local bin bl
+    auto inverse = [&](int f, int p_re, int p_im, int bl) -> int {
+        T3_TRY(rows_launch(py, 1.0f, LoadProduct{F[f], Ks}, StoreGrid{A}, nx, s));
+        T3_TRY(transpose(A, Bw, nx, ny, s));
+        StorePlanes sp{slot, nx_occ, ny_occ, lv.planes.as<float>(), p_re, p_im, L.K, L.B, bl, scale};
+        T3_TRY(rows_launch(px, 1.0f, LoadGrid{Bw}, sp, ny, s));
+        return T3_OK;
+    };
+    for (int bl = 0; bl < lv.nb; ++bl) {
+        const int b = lv.b_lo + bl;
+        for (int m = m_lo; m <= m_hi; ++m) {
+            const bool need_g = m <= plan->n_max - 1;
+            const bool need_w = m >= 0 && m <= plan->w_max;
+            const bool need_d = m == -6 || m == -2 || m == 0;
+            if (!need_g && !need_w && !need_d) continue;
+            // kernel spectrum: only the rows |dy| <= R of the kernel grid are non-zero
+            LoadKernel lk{nx, ny, Rx, Ry, m, (double)lv.side, plan->e2[b], plan->e2[b + 1]};
+            const int head = Ry + 1, tail = Ry;  // ny >= 2 Ry + 1
+            T3_TRY(rows_launch(px, -1.0f, lk, StoreGrid{Kg}, head + tail, s, 0, head, ny - head - tail));
+            T3_TRY(transpose(Kg, A, ny, nx, s));
+            T3_TRY(rows_launch(py, -1.0f, LoadGrid{A}, StoreGrid{Ks}, nx, s));
+            if (need_g) T3_TRY(inverse(0, L.plane_G(m, 0), L.plane_G(m, 1), bl));
+            if (need_w) T3_TRY(inverse(1, L.plane_W(m, 0), L.plane_W(m, 1), bl));
+            if (m == -6) T3_TRY(inverse(2, L.plane_D(0), L.plane_D(1), bl));
+            if (m == -2) {
+                T3_TRY(inverse(2, L.plane_D(2), L.plane_D(3), bl));
+                T3_TRY(inverse(3, L.plane_D(4), L.plane_D(5), bl));
+            }
+            if (m == 0) T3_TRY(inverse(4, L.plane_D(6), -1, bl));
+        }
+    }
+    return T3_OK;
+}
+
+}  // namespace t3

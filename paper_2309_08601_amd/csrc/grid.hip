@@ -10,11 +10,11 @@
 //     result is deterministic) and its lower-left corner as position (only
 //     differences of positions enter, so corners and centres are the same);
 //  2. G_m^Delta, W_m^Delta and the j = k sums of the level's bins at every
-//     non-empty pixel: the stage-1 scan run on the pixel catalog.  This is
-//     the convolution of the gridded w gamma and w with the bin kernels
-//     e^{i m phi} 1(theta in Theta) evaluated directly, visiting non-empty
-//     pixels only; the multi-resolution choice keeps Theta / Delta bounded,
-//     so its cost per pixel is bounded too.
+//     non-empty pixel, i.e. the convolution of the gridded w gamma and w with
+//     the bin kernels e^{i m phi} 1(theta in Theta), by one of two routes:
+//     the stage-1 pair sums run on the pixel catalog (visits non-empty
+//     pixels only), or FFTs on the dense grid of the occupied pixels
+//     (fft.hip); a cost model picks one per level unless the caller does.
 // Then, per chunk of galaxy centres: stage 1 for the discrete bins, a gather
 // that copies every grid bin's planes from the pixel holding the galaxy,
 // and the ordinary stage 2 over galaxies.  A sum over galaxies of
@@ -29,6 +29,7 @@
 #include "t3_internal.h"
 
 #include <algorithm>
+#include <cmath>
 
 namespace t3 {
 
@@ -53,6 +54,8 @@ void GridLevel::release()
     slot_of_pix.release();
     cen_slot.release();
     planes.release();
+    fft_misc.release();
+    fft_buf.release();
 }
 
 namespace {
@@ -170,7 +173,7 @@ int prepare_counters(t3_plan *plan, hipStream_t s)
 }
 
 // Pixel catalog of one level and the stage-1 planes of its bins at every pixel.
-int build_level(t3_plan *plan, GridLevel &lv, const t3_catalog &cat, hipStream_t s)
+int build_level(t3_plan *plan, GridLevel &lv, const t3_catalog &cat, int method, hipStream_t s)
 {
     CellGrid pg;
     pg.cell = (int)lv.side;
@@ -233,19 +236,32 @@ int build_level(t3_plan *plan, GridLevel &lv, const t3_catalog &cat, hipStream_t
     if (lv.L.floats() * sizeof(float) > ((size_t)64 << 30))
         return fail(T3_ERANGE, "t3_forward_grid: pixel planes of a level above 64 GiB (coarser Delta_1)");
     T3_TRY(lv.planes.reserve(sizeof(float) * lv.L.floats()));
-    if (n_pix > 0) {
-        const SortedCatalog *cl[1] = {&lv.pix};
-        T3_TRY(scan_chunk(plan, cl, nullptr, 1, lv.pix_centres, 0, n_pix, lv.L, lv.planes.as<float>(),
-                          lv.L.floats(), plan->counter.as<unsigned long long>(), plan->scan_mode, s, lv.b_lo,
-                          lv.nb));
+    if (n_pix == 0) return T3_OK;
+    // route: pair sums over the pixel catalog, or FFT convolution on the
+    // dense grid of the occupied pixels (modelled cost decides for AUTO)
+    T3_TRY(level_bbox(lv, s));
+    int m = method;
+    if (m == T3_GRID_AUTO) {
+        const double area = (double)lv.nx_occ * lv.ny_occ;  // pixels^2
+        const double e_lo = std::sqrt(plan->e2[lv.b_lo]) / (double)lv.side;
+        const double e_hi = std::sqrt(plan->e2[lv.b_lo + lv.nb]) / (double)lv.side;
+        const double pairs = (double)n_pix * (double)n_pix / area * M_PI * (e_hi * e_hi - e_lo * e_lo);
+        // measured stage-1 rate: about 7e12 pair-orders per second
+        const double direct_ms = 1e3 * pairs * (3.0 * plan->n_max + 4.0) / 7.0e12;
+        m = fft_cost_ms(plan, lv) < direct_ms ? T3_GRID_FFT : T3_GRID_DIRECT;
     }
+    lv.method = m;
+    if (m == T3_GRID_FFT) return fft_level(plan, lv, s);
+    const SortedCatalog *cl[1] = {&lv.pix};
+    T3_TRY(scan_chunk(plan, cl, nullptr, 1, lv.pix_centres, 0, n_pix, lv.L, lv.planes.as<float>(), lv.L.floats(),
+                      plan->counter.as<unsigned long long>(), plan->scan_mode, s, lv.b_lo, lv.nb));
     return T3_OK;
 }
 
 }  // namespace
 
-int forward_grid(t3_plan *plan, const t3_catalog &cat, int64_t delta, const int32_t *levels, double *ups_out,
-                 int64_t *n_pairs, hipStream_t s)
+int forward_grid(t3_plan *plan, const t3_catalog &cat, int64_t delta, const int32_t *levels, int method,
+                 double *ups_out, int64_t *n_pairs, hipStream_t s)
 {
     T3_TRY(timing_begin_call(plan));
     T3_TRY(prepare_counters(plan, s));
@@ -275,7 +291,7 @@ int forward_grid(t3_plan *plan, const t3_catalog &cat, int64_t delta, const int3
     for (int l = 1; l <= kMaxGridLevels; ++l) {
         GridLevel &lv = plan->grid[l - 1];
         if (lv.nb == 0) continue;
-        T3_TRY(build_level(plan, lv, cat, s));
+        T3_TRY(build_level(plan, lv, cat, method, s));
         if (cat.n > 0) {
             hipLaunchKernelGGL(k_cen_slot, dim3(blocks(cat.n, 256)), dim3(256), 0, s,
                                (const int *)plan->cats[0].perm.as<int>(), cat.n,

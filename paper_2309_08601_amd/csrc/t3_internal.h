@@ -117,6 +117,10 @@ struct GridLevel {
     DevBuf cen_slot;        // int [n_gal]: galaxy (sorted slot) -> sorted pixel slot
     DevBuf planes;          // stage-1 planes of every pixel, layout L
     ChunkLayout L;
+    int box[4] = {0, 0, 0, 0};  // occupied corners: x min, y min, x max, y max
+    int nx_occ = 0, ny_occ = 0; // occupied extent, pixels
+    int method = 0;             // route taken: T3_GRID_DIRECT or T3_GRID_FFT
+    DevBuf fft_misc, fft_buf;   // FFT route: bounding box, grids and tables
     void release();
 };
 
@@ -207,8 +211,11 @@ int aperture_stats(t3_plan *plan, const double *gamma_cent, int n_sets, int n_ph
 int sphere_patch(t3_plan *plan, const t3_sphere_catalog &cat, const t3_patch &p, double theta_max_arcmin,
                  t3_catalog *view, const int32_t **core, int64_t *n_core, hipStream_t s);
 int add_doubles(double *dst, const double *src, size_t n, hipStream_t s);
-int forward_grid(t3_plan *plan, const t3_catalog &cat, int64_t delta, const int32_t *levels, double *ups_out,
-                 int64_t *n_pairs, hipStream_t s);
+int forward_grid(t3_plan *plan, const t3_catalog &cat, int64_t delta, const int32_t *levels, int method,
+                 double *ups_out, int64_t *n_pairs, hipStream_t s);
+int level_bbox(GridLevel &lv, hipStream_t s);
+double fft_cost_ms(const t3_plan *plan, const GridLevel &lv);
+int fft_level(t3_plan *plan, GridLevel &lv, hipStream_t s);
 int harmonics_export(t3_plan *plan, const CentreSet &cs, const ChunkLayout &L, const float *planes,
                      int64_t c0, int n_c, float *G, float *W, float *D, hipStream_t s);
 int normalise_backward(t3_plan *plan, const double *ups, const double *ggam, int n_sets, double *gups,

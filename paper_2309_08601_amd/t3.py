@@ -22,6 +22,7 @@ T3_ERANGE = -2
 T3_ENOMEM = -3
 T3_EHIP = -4
 T3_ELATTICE = -5
+GRID_METHODS = {"auto": 0, "direct": 1, "fft": 2}
 
 PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp16x3": 2, "bf16x6": 3}
 T3_FLAG_KEEP_JK = 1
@@ -84,7 +85,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.t3_forward_sphere.argtypes = [vp, P(t3_sphere_catalog), P(t3_patch), ctypes.c_int32, ctypes.c_double, vp,
                                       P(ctypes.c_int64), vp]
     lib.t3_forward_sphere.restype = ctypes.c_int
-    lib.t3_forward_grid.argtypes = [vp, P(t3_catalog), ctypes.c_int64, P(ctypes.c_int32), vp, P(ctypes.c_int64), vp]
+    lib.t3_forward_grid.argtypes = [vp, P(t3_catalog), ctypes.c_int64, P(ctypes.c_int32), ctypes.c_int32, vp,
+                                    P(ctypes.c_int64), vp]
     lib.t3_forward_grid.restype = ctypes.c_int
     lib.t3_harmonics.argtypes = [vp, P(t3_catalog), vp, ctypes.c_int64, vp, vp, vp, vp]
     lib.t3_harmonics.restype = ctypes.c_int
@@ -277,11 +279,12 @@ class Plan:
                                       ctypes.byref(npairs), _stream()))
         return torch.view_as_complex(out), int(npairs.value)
 
-    def forward_grid(self, cat: DeviceCatalog, delta: int, levels: Sequence[int],
+    def forward_grid(self, cat: DeviceCatalog, delta: int, levels: Sequence[int], method: str = "auto",
                      out: Optional[torch.Tensor] = None):
         """Combined discrete / grid-based multipoles: levels[b] = 0 for a
         discrete bin, l >= 1 for pixels of side delta * 2^(l-1) lattice steps
-        (non-decreasing in b).  Same output as forward."""
+        (non-decreasing in b); method "direct", "fft" or "auto" per level.
+        Same output as forward."""
         if len(levels) != self.B:
             raise ValueError("one level per radial bin")
         lv = (ctypes.c_int32 * self.B)(*[int(v) for v in levels])
@@ -289,8 +292,8 @@ class Plan:
             out = torch.empty(self._out_shape()[1:], dtype=torch.float64, device=cat.x.device)
         cs = cat.c_struct()
         npairs = ctypes.c_int64(0)
-        _check(_lib.t3_forward_grid(self._h, ctypes.byref(cs), int(delta), lv, _ptr(out), ctypes.byref(npairs),
-                                    _stream()))
+        _check(_lib.t3_forward_grid(self._h, ctypes.byref(cs), int(delta), lv, GRID_METHODS[method], _ptr(out),
+                                    ctypes.byref(npairs), _stream()))
         return torch.view_as_complex(out), int(npairs.value)
 
     def harmonics(self, cat: DeviceCatalog, centres: torch.Tensor):

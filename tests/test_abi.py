@@ -155,8 +155,8 @@ def test_forward_grid_argument_errors(lib):
         cat = t3.t3_catalog(0, None, None, None, None, None)
         out = ctypes.c_void_p(16)
         lv = lambda *v: (ctypes.c_int32 * 2)(*v)  # noqa: E731
-        call = lambda delta, levels: t3._lib.t3_forward_grid(h, ctypes.byref(cat), delta, levels, out,  # noqa: E731
-                                                              None, None)
+        call = lambda delta, levels, m=0: t3._lib.t3_forward_grid(h, ctypes.byref(cat), delta, levels, m,  # noqa: E731
+                                                                   out, None, None)
         assert call(1 << 14, None) == -1                 # no levels
         assert call(0, lv(0, 1)) == -1                   # delta < 1
         assert call(1 << 21, lv(0, 1)) == -1             # delta above the box
@@ -165,6 +165,7 @@ def test_forward_grid_argument_errors(lib):
         assert call(1 << 14, lv(-1, 0)) == -1            # negative level
         assert call(1 << 14, lv(0, 8)) == -2             # pixel side 2^21 > box
         assert call(64, lv(0, 1)) == -2                  # 16384 pixels along the box
-        assert t3._lib.t3_forward_grid(h, ctypes.byref(cat), 1 << 14, lv(0, 1), None, None, None) == -1
+        assert call(1 << 14, lv(0, 1), 3) == -1          # unknown method
+        assert t3._lib.t3_forward_grid(h, ctypes.byref(cat), 1 << 14, lv(0, 1), 0, None, None, None) == -1
     finally:
         t3._lib.t3_plan_destroy(h)

@@ -1,8 +1,10 @@
 """Grid-based and combined estimators on the GPU (Sect. 3.2-3.3, Appendix A)
 against the oracle's regrid-then-contract evaluation of every block.
 
-Cases: mixed discrete / multi-resolution levels, unused levels between used
-ones, every bin on one grid, edge correction (N to 2 n_max), n_max = 30,
+Both routes of a grid level (pair sums over the pixel catalog, FFT
+convolution on the dense grid) in every case.  Cases: mixed discrete /
+multi-resolution levels, unused levels between used ones, every bin on one
+grid, edge correction (N to 2 n_max), n_max = 30,
 ragged chunks (the gather across chunk offsets), all-discrete levels equal
 to the plain forward pass, and a field-shaped case with the bins and level
 rule of the 1M-galaxy field on a 50k-galaxy catalog.  The pixel anchor is
@@ -30,9 +32,9 @@ def _pack(ups, N, nm, wm):
     return np.concatenate([ups[:, nm:].reshape(4 * (nm + 1), B, B), N[wm:]], axis=0)
 
 
-def _compare(t3, plan, cat, edges, nm, delta, levels, ec, box_lo, label):
+def _compare(t3, plan, cat, edges, nm, delta, levels, ec, box_lo, label, method="direct"):
     from oracle import grid as og
-    ups, npairs = plan.forward_grid(t3.DeviceCatalog.from_catalog(cat), delta, levels)
+    ups, npairs = plan.forward_grid(t3.DeviceCatalog.from_catalog(cat), delta, levels, method=method)
     wm = 2 * nm if ec else nm
     o = og.multipoles_combined(cat, edges, nm, delta, levels, box_lo=box_lo, w_max=wm)
     ref = _pack(o["ups"], o["N"], nm, wm)
@@ -40,8 +42,13 @@ def _compare(t3, plan, cat, edges, nm, delta, levels, ec, box_lo, label):
     u_err = rel_fro(got[:4 * (nm + 1)], ref[:4 * (nm + 1)]).max()
     n0 = np.linalg.norm(ref[4 * (nm + 1)])
     n_err = np.max([np.linalg.norm(got[4 * (nm + 1) + k] - ref[4 * (nm + 1) + k]) / n0 for k in range(wm + 1)])
-    print(f"{label}: levels {levels}, {npairs} pairs, Upsilon {u_err:.2e}, N_n/N_0 {n_err:.2e}", flush=True)
-    assert npairs == o["npairs"]
+    print(f"{label} ({method}): levels {levels}, {npairs} pairs, Upsilon {u_err:.2e}, N_n/N_0 {n_err:.2e}",
+          flush=True)
+    # pairs: every pair sum (discrete bins; grid levels on the direct route)
+    if method == "direct":
+        assert npairs == o["npairs"]
+    elif method == "fft":
+        assert npairs == (int(o["units"][0][3]["npairs"].sum()) if 0 in o["units"] else 0)
     assert u_err <= FP32_TOL and n_err <= FP32_TOL
     return ups
 
@@ -55,13 +62,14 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("method", ["direct", "fft"])
 @pytest.mark.parametrize("label,levels,nm,ec", CASES, ids=[c[0] for c in CASES])
-def test_combined_matches_oracle(t3, label, levels, nm, ec):
+def test_combined_matches_oracle(t3, label, levels, nm, ec, method):
     cat = random_catalog(5000, 50.0, seed=1200 + nm)
     edges = np.geomspace(1.0, 14.0, 7)
     box_lo = (-12345, -6789)
     plan = t3.Plan(edges, nm, box_lo=box_lo, box_size=1 << 23, edge_correct=ec)
-    _compare(t3, plan, cat, edges, nm, int(0.25 / LATTICE_UNIT), levels, ec, box_lo, label)
+    _compare(t3, plan, cat, edges, nm, int(0.25 / LATTICE_UNIT), levels, ec, box_lo, label, method)
 
 
 def test_combined_ragged_chunks(t3):
@@ -71,7 +79,8 @@ def test_combined_ragged_chunks(t3):
     edges = np.geomspace(1.0, 12.0, 6)
     box_lo = (-333, 0)
     plan = t3.Plan(edges, 8, box_lo=box_lo, box_size=1 << 23, chunk_centres=256)
-    _compare(t3, plan, cat, edges, 8, int(0.5 / LATTICE_UNIT), [0, 1, 1, 2, 2], False, box_lo, "ragged")
+    for method in ("direct", "fft"):
+        _compare(t3, plan, cat, edges, 8, int(0.5 / LATTICE_UNIT), [0, 1, 1, 2, 2], False, box_lo, "ragged", method)
 
 
 def test_all_discrete_levels_equal_forward(t3):
@@ -99,4 +108,6 @@ def test_combined_field_shaped(t3):
     levels = t3.grid_levels(edges, 0.25)
     assert max(levels) == 4 and levels.count(0) == 9
     plan = t3.Plan(edges, wl.n_max, box_lo=(0, 0), box_size=1 << 24)
-    _compare(t3, plan, cat, edges, wl.n_max, int(0.25 / LATTICE_UNIT), levels, False, (0, 0), "field-shaped")
+    for method in ("direct", "fft", "auto"):
+        _compare(t3, plan, cat, edges, wl.n_max, int(0.25 / LATTICE_UNIT), levels, False, (0, 0), "field-shaped",
+                 method)
