@@ -342,21 +342,27 @@ def bench_combined(t3, torch, dev, dc, wl, box, disc_ms, disc_pairs):
     levels = t3.grid_levels(edges, 0.25)
     delta = int(round(0.25 / LATTICE_UNIT))
     plan = t3.Plan(edges, nm, box_lo=(0, 0), box_size=box, timing=True)
-    ups = None
-    for rep in range(3):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ups, npairs = plan.forward_grid(dc, delta, levels)
-        gn, gp = plan.normalise_resum(ups, n_phi=wl.n_phi)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        if rep == 1:
-            ms_acc, st_acc = dt, np.asarray(plan.stage_times()[0])
-        elif rep == 2:
-            ms_acc += dt
-            st_acc = st_acc + np.asarray(plan.stage_times()[0])
-    ms = 1e3 * ms_acc / 2
-    st = st_acc / 2
+    routes = {}
+    for method in ("direct", "fft", "auto"):
+        for rep in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ups, npairs = plan.forward_grid(dc, delta, levels, method=method)
+            gn, gp = plan.normalise_resum(ups, n_phi=wl.n_phi)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if rep == 1:
+                ms_acc, st_acc = dt, np.asarray(plan.stage_times()[0])
+            elif rep == 2:
+                ms_acc += dt
+                st_acc = st_acc + np.asarray(plan.stage_times()[0])
+        st = st_acc / 2
+        routes[method] = {"ms_per_step": 1e3 * ms_acc / 2, "pairs_per_step": int(npairs),
+                          "stage_ms": {"cells": float(st[0]), "levels_stage1_gather": float(st[1]),
+                                       "stage2": float(st[2])}}
+        log(f"[bench] combined ({method}): {1e3 * ms_acc / 2:.1f} ms/step ({disc_ms / (1e3 * ms_acc / 2):.1f}x the "
+            f"discrete step), {npairs} pairs, stages {st[:3].round(2).tolist()} ms")
+    ms = routes["auto"]["ms_per_step"]
     ref_plan = t3.Plan(edges, nm, box_lo=(0, 0), box_size=box)
     ref, _ = ref_plan.forward(dc)
     g_ref, _ = ref_plan.normalise_resum(ref, with_phi=False)
@@ -374,13 +380,12 @@ def bench_combined(t3, torch, dev, dc, wl, box, disc_ms, disc_pairs):
     n0c = ups.cpu().numpy()[4, 0].real
     m = ~np.outer(d, d)
     diff["N_0_with_grid"] = float(np.linalg.norm((n0c - n0r)[m]) / np.linalg.norm(n0r[m]))
-    res = {"ms_per_step": ms, "speedup_vs_discrete": disc_ms / ms, "pairs_per_step": int(npairs),
-           "discrete_pairs_per_step": int(disc_pairs),
-           "stage_ms": {"cells": float(st[0]), "pixels_stage1_gather": float(st[1]), "stage2": float(st[2])},
-           "levels": levels, "delta_arcmin": 0.25, "rel_diff_vs_discrete": diff,
-           "workload": "field_1m, combined estimator: Delta_1 = 0.25', levels " + str(levels)}
-    log(f"[bench] combined: {ms:.1f} ms/step ({disc_ms / ms:.1f}x the discrete step), {npairs} pairs, "
-        f"stages {st[:3].round(2).tolist()} ms, Gamma_n difference to discrete {diff}")
+    res = {"ms_per_step": ms, "speedup_vs_discrete": disc_ms / ms, "routes": routes,
+           "discrete_pairs_per_step": int(disc_pairs), "levels": levels, "delta_arcmin": 0.25,
+           "rel_diff_vs_discrete": diff,
+           "workload": "field_1m, combined estimator: Delta_1 = 0.25', levels " + str(levels) +
+                       "; routes: pair sums over pixels (direct), FFT convolution (fft), per-level cost model (auto)"}
+    log(f"[bench] combined: difference to discrete {diff}")
     return res
 
 

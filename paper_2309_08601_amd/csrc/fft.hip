@@ -18,7 +18,11 @@
 // 2-D transforms: rows by a Stockham FFT in LDS (one workgroup per row, radix
 // 2, 3, 4, 5 or 8 per stage, twiddles from an FP64-computed table), then a
 // tiled transpose, then rows again; the spectrum stays transposed, and the
-// inverse runs the same three steps back.  FP32 arithmetic.
+// inverse runs the same three steps back.  FP32 arithmetic.  Transforms run
+// in batches (one launch per step for many fields, orders or outputs, the
+// batch index on the grid's y axis) so that the coarse levels' small grids
+// still fill the chip.  The kernel spectra depend only on the plan and the
+// grid geometry; a level keeps them between calls while those are unchanged.
 #include "t3_internal.h"
 
 #include <algorithm>
@@ -35,6 +39,7 @@ struct RowPlan {
     int n = 0;                  // transform length
     int ns = 0;                 // stages
     int radix[kMaxStages];
+    unsigned magic[kMaxStages]; // ceil(2^32 / sub-transform size) of each stage (size >= 2)
     const float2 *tw = nullptr; // e^{-2 pi i k / n}, k < n
 };
 
@@ -125,8 +130,9 @@ template <> struct Dft<8> {
 // e^{s 2 pi i r (j mod ns) / (ns R)}, and writes buf[(j / ns) ns R + j mod ns + r ns].
 // Every thread first loads all of its butterflies, then the workgroup
 // synchronises and stores (one buffer serves as source and destination).
+// j / ns is a multiply-high by ceil(2^32 / ns): exact for j, ns <= 2^13.
 template <int R>
-__device__ __forceinline__ void stage(float2 *buf, const RowPlan &p, int ns, float s)
+__device__ __forceinline__ void stage(float2 *buf, const RowPlan &p, int ns, unsigned magic, float s)
 {
     constexpr int MB = (kFftMax / R + kFftThreads - 1) / kFftThreads;
     const int nb = p.n / R;
@@ -145,15 +151,18 @@ __device__ __forceinline__ void stage(float2 *buf, const RowPlan &p, int ns, flo
     for (int q = 0; q < MB; ++q) {
         const int j = threadIdx.x + q * kFftThreads;
         if (j < nb) {
-            const int k = j % ns;
+            const int jq = ns == 1 ? j : (int)__umulhi((unsigned)j, magic);
+            const int k = j - jq * ns;
+            if (k != 0) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                float2 w = p.tw[(r * k * tw_step) % p.n];
-                w.y *= -s;  // table holds e^{-2 pi i t / n}; s = +1 conjugates
-                v[q][r] = cmul(v[q][r], make_float2(w.x, w.y));
+                for (int r = 1; r < R; ++r) {
+                    float2 w = p.tw[r * k * tw_step];
+                    w.y *= -s;  // table holds e^{-2 pi i t / n}; s = +1 conjugates
+                    v[q][r] = cmul(v[q][r], w);
+                }
             }
             Dft<R>::run(v[q], s);
-            const int base = (j / ns) * ns * R + k;
+            const int base = jq * ns * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[base + r * ns] = v[q][r];
         }
@@ -166,37 +175,48 @@ __device__ void fft_lds(float2 *buf, const RowPlan &p, float s)
     int ns = 1;
     for (int st = 0; st < p.ns; ++st) {
         const int R = p.radix[st];
+        const unsigned mg = p.magic[st];
         switch (R) {
-            case 2: stage<2>(buf, p, ns, s); break;
-            case 3: stage<3>(buf, p, ns, s); break;
-            case 4: stage<4>(buf, p, ns, s); break;
-            case 5: stage<5>(buf, p, ns, s); break;
-            default: stage<8>(buf, p, ns, s); break;
+            case 2: stage<2>(buf, p, ns, mg, s); break;
+            case 3: stage<3>(buf, p, ns, mg, s); break;
+            case 4: stage<4>(buf, p, ns, mg, s); break;
+            case 5: stage<5>(buf, p, ns, mg, s); break;
+            default: stage<8>(buf, p, ns, mg, s); break;
         }
         ns *= R;
     }
 }
 
 // ---------------------------------------------------------------- loaders / storers
-struct LoadGrid {   // src[row * n + i]
+// (batch index t = blockIdx.y; grids of one batch entry are `stride` apart)
+struct LoadGrid {
     const float2 *src;
-    __device__ float2 operator()(int row, int i, int n) const { return src[(size_t)row * n + i]; }
-};
-struct LoadProduct {  // a[row * n + i] b[row * n + i]
-    const float2 *a, *b;
-    __device__ float2 operator()(int row, int i, int n) const
+    size_t stride;
+    __device__ float2 operator()(int t, int row, int i, int n) const
     {
-        const size_t o = (size_t)row * n + i;
-        return cmul(a[o], b[o]);
+        return src[t * stride + (size_t)row * n + i];
     }
 };
-// Kernel of order m and bin [e2lo, e2hi) on a grid of nx x ny pixels of side
-// `side` lattice steps; grid point (x, y) holds K(-signed(x), -signed(y)).
-struct LoadKernel {
-    int nx, ny, rx, ry, m;
-    double side, e2lo, e2hi;
-    __device__ float2 operator()(int row, int i, int) const
+// Spectrum of field f[job] times kernel spectrum k[job].
+struct LoadProduct {
+    const float2 *F, *K;
+    size_t stride;
+    const int *f, *k;
+    int job0;
+    __device__ float2 operator()(int t, int row, int i, int n) const
     {
+        const size_t o = (size_t)row * n + i;
+        return cmul(F[(size_t)f[job0 + t] * stride + o], K[(size_t)k[job0 + t] * stride + o]);
+    }
+};
+// Kernel of order m0 + t and bin [e2lo, e2hi) on a grid of nx x ny pixels of
+// side `side` lattice steps; grid point (x, y) holds K(-signed(x), -signed(y)).
+struct LoadKernel {
+    int nx, ny, rx, ry, m0;
+    double side, e2lo, e2hi;
+    __device__ float2 operator()(int t, int row, int i, int) const
+    {
+        const int m = m0 + t;
         const int sx = i <= nx / 2 ? i : i - nx;
         const int sy = row <= ny / 2 ? row : row - ny;
         const int dx = -sx, dy = -sy;
@@ -209,60 +229,70 @@ struct LoadKernel {
         double pr = 1.0, pi = 0.0;
         for (int e = m < 0 ? -m : m; e > 0; e >>= 1) {  // z^|m| by squaring, FP64
             if (e & 1) {
-                const double t = pr * zr - pi * zi;
+                const double u = pr * zr - pi * zi;
                 pi = pr * zi + pi * zr;
-                pr = t;
+                pr = u;
             }
-            const double t = zr * zr - zi * zi;
+            const double u = zr * zr - zi * zi;
             zi = 2.0 * zr * zi;
-            zr = t;
+            zr = u;
         }
         return make_float2((float)pr, (float)pi);
     }
 };
 struct StoreGrid {
     float2 *dst;
-    __device__ void operator()(int row, int i, int n, float2 v) const { dst[(size_t)row * n + i] = v; }
+    size_t stride;
+    __device__ void operator()(int t, int row, int i, int n, float2 v) const
+    {
+        dst[t * stride + (size_t)row * n + i] = v;
+    }
 };
-// Values at the non-empty pixels into stage-1 planes (layout K, nb).
+// Values at the non-empty pixels into stage-1 planes (layout K, nb) of
+// local bin b: planes re[job], im[job] (im < 0: real part only).
 struct StorePlanes {
     const int *slot;   // [ny_occ][nx_occ] sorted pixel slot or -1
     int nx_occ, ny_occ;
     float *planes;
-    int p_re, p_im;    // planes (p_im < 0: real part only)
-    int K, nb, b;
+    const int *p_re, *p_im;
+    int job0, K, nb, b;
     float scale;
-    __device__ void operator()(int row, int i, int, float2 v) const
+    __device__ void operator()(int t, int row, int i, int, float2 v) const
     {
         if (row >= ny_occ || i >= nx_occ) return;
         const int sl = slot[(size_t)row * nx_occ + i];
         if (sl < 0) return;
-        planes[chunk_offset(p_re, sl, b, K, nb)] = v.x * scale;
-        if (p_im >= 0) planes[chunk_offset(p_im, sl, b, K, nb)] = v.y * scale;
+        const int pr = p_re[job0 + t], pi = p_im[job0 + t];
+        planes[chunk_offset(pr, sl, b, K, nb)] = v.x * scale;
+        if (pi >= 0) planes[chunk_offset(pi, sl, b, K, nb)] = v.y * scale;
     }
 };
 
-// One workgroup per row: load, transform in LDS, store.  rows[] maps block ->
-// row when given (kernel generation touches only the rows that can be non-zero).
+// One workgroup per (row, batch entry): load, transform in LDS, store.
+// Blocks x >= row_gap skip gap_len rows (kernel generation touches only the
+// rows that can be non-zero).
 template <class Load, class Store>
-__global__ __launch_bounds__(kFftThreads) void k_fft_rows(RowPlan p, float s, Load ld, Store st, int row0,
-                                                          int row_gap, int gap_len)
+__global__ __launch_bounds__(kFftThreads) void k_fft_rows(RowPlan p, float s, Load ld, Store st, int row_gap,
+                                                          int gap_len)
 {
     extern __shared__ float2 lds[];
-    int row = row0 + (int)blockIdx.x;
+    int row = (int)blockIdx.x;
     if (gap_len > 0 && row >= row_gap) row += gap_len;
-    for (int i = threadIdx.x; i < p.n; i += kFftThreads) lds[i] = ld(row, i, p.n);
+    const int t = (int)blockIdx.y;
+    for (int i = threadIdx.x; i < p.n; i += kFftThreads) lds[i] = ld(t, row, i, p.n);
     __syncthreads();
     fft_lds(lds, p, s);
-    for (int i = threadIdx.x; i < p.n; i += kFftThreads) st(row, i, p.n, lds[i]);
+    for (int i = threadIdx.x; i < p.n; i += kFftThreads) st(t, row, i, p.n, lds[i]);
 }
 
-// dst[c][r] = src[r][c] for src of rows x cols
+// dst[z][c][r] = src[z][r][c] for grids of rows x cols, `stride` apart
 constexpr int kTile = 32;
 __global__ __launch_bounds__(256) void k_transpose(const float2 *__restrict__ src, float2 *__restrict__ dst,
-                                                   int rows, int cols)
+                                                   int rows, int cols, size_t stride)
 {
     __shared__ float2 t[kTile][kTile + 1];
+    src += blockIdx.z * stride;
+    dst += blockIdx.z * stride;
     const int c0 = blockIdx.x * kTile, r0 = blockIdx.y * kTile;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
     for (int k = ty; k < kTile; k += 8) {
@@ -294,7 +324,7 @@ __global__ void k_bbox(const int2 *__restrict__ pos, int64_t n, int *__restrict_
     atomicMax(&box[3], p.y);
 }
 
-// five field grids ([ny][nx] complex) and the slot map from the sorted pixels
+// five field grids ([ny][nx] complex, N apart) and the slot map from the sorted pixels
 struct ScatterArgs {
     const int2 *pos;
     const double *sum;   // [pixel][3], by pixel index
@@ -302,8 +332,9 @@ struct ScatterArgs {
     int64_t n;
     int x0, y0;
     int64_t side;
-    int nx, ny, nx_occ;
-    float2 *f[5];
+    int nx, nx_occ;
+    size_t N;
+    float2 *f;
     int *slot;
 };
 __global__ void k_scatter_fields(ScatterArgs a)
@@ -315,11 +346,11 @@ __global__ void k_scatter_fields(ScatterArgs a)
     const int P = a.perm[s];
     const double c1 = a.sum[3 * (int64_t)P], c2 = a.sum[3 * (int64_t)P + 1], w = a.sum[3 * (int64_t)P + 2];
     const size_t o = (size_t)y * a.nx + x;
-    a.f[0][o] = make_float2((float)c1, (float)c2);
-    a.f[1][o] = make_float2((float)w, 0.f);
-    a.f[2][o] = make_float2((float)(c1 * c1 - c2 * c2), (float)(2.0 * c1 * c2));
-    a.f[3][o] = make_float2((float)(c1 * c1 + c2 * c2), 0.f);
-    a.f[4][o] = make_float2((float)(w * w), 0.f);
+    a.f[o] = make_float2((float)c1, (float)c2);
+    a.f[a.N + o] = make_float2((float)w, 0.f);
+    a.f[2 * a.N + o] = make_float2((float)(c1 * c1 - c2 * c2), (float)(2.0 * c1 * c2));
+    a.f[3 * a.N + o] = make_float2((float)(c1 * c1 + c2 * c2), 0.f);
+    a.f[4 * a.N + o] = make_float2((float)(w * w), 0.f);
     a.slot[(size_t)y * a.nx_occ + x] = (int)s;
 }
 
@@ -343,31 +374,61 @@ void factor(int n, RowPlan &p)
 {
     p.n = n;
     p.ns = 0;
+    int ns = 1;
     for (int r : {8, 4, 2, 5, 3})
         while (n % r == 0 && p.ns < kMaxStages) {
+            p.magic[p.ns] = ns >= 2 ? (unsigned)(((1ull << 32) + ns - 1) / ns) : 0u;
             p.radix[p.ns++] = r;
+            ns *= r;
             n /= r;
         }
 }
 
 template <class Load, class Store>
-int rows_launch(const RowPlan &p, float s, Load ld, Store st, int n_rows, hipStream_t q, int row0 = 0,
-                int row_gap = 0, int gap_len = 0)
+int rows_launch(const RowPlan &p, float s, Load ld, Store st, int n_rows, int batch, hipStream_t q, int row_gap = 0,
+                int gap_len = 0)
 {
-    if (n_rows <= 0) return T3_OK;
-    hipLaunchKernelGGL((k_fft_rows<Load, Store>), dim3((unsigned)n_rows), dim3(kFftThreads),
-                       sizeof(float2) * p.n, q, p, s, ld, st, row0, row_gap, gap_len);
+    if (n_rows <= 0 || batch <= 0) return T3_OK;
+    hipLaunchKernelGGL((k_fft_rows<Load, Store>), dim3((unsigned)n_rows, (unsigned)batch), dim3(kFftThreads),
+                       sizeof(float2) * p.n, q, p, s, ld, st, row_gap, gap_len);
     T3_HIP_CHECK(hipGetLastError());
     return T3_OK;
 }
 
-int transpose(const float2 *src, float2 *dst, int rows, int cols, hipStream_t q)
+int transpose(const float2 *src, float2 *dst, int rows, int cols, int batch, size_t stride, hipStream_t q)
 {
-    hipLaunchKernelGGL(k_transpose, dim3((unsigned)((cols + kTile - 1) / kTile), (unsigned)((rows + kTile - 1) / kTile)),
-                       dim3(256), 0, q, src, dst, rows, cols);
+    hipLaunchKernelGGL(k_transpose,
+                       dim3((unsigned)((cols + kTile - 1) / kTile), (unsigned)((rows + kTile - 1) / kTile),
+                            (unsigned)batch),
+                       dim3(256), 0, q, src, dst, rows, cols, stride);
     T3_HIP_CHECK(hipGetLastError());
     return T3_OK;
 }
+
+// Orders and inverse transforms of one bin: kernel order m is needed by
+// G (m <= n_max - 1), W (0 <= m <= w_max) and the j = k sums (m = -6, -2, 0).
+struct Job {
+    int f, m, p_re, p_im;
+};
+void jobs_of(const t3_plan *plan, const ChunkLayout &L, int *m_lo, int *m_hi, std::vector<Job> &jobs)
+{
+    *m_lo = -plan->n_max - 3;
+    *m_hi = std::max(plan->n_max - 1, plan->w_max);
+    jobs.clear();
+    for (int m = *m_lo; m <= *m_hi; ++m) {
+        if (m <= plan->n_max - 1) jobs.push_back({0, m, L.plane_G(m, 0), L.plane_G(m, 1)});
+        if (m >= 0 && m <= plan->w_max) jobs.push_back({1, m, L.plane_W(m, 0), L.plane_W(m, 1)});
+        if (m == -6) jobs.push_back({2, m, L.plane_D(0), L.plane_D(1)});
+        if (m == -2) {
+            jobs.push_back({2, m, L.plane_D(2), L.plane_D(3)});
+            jobs.push_back({3, m, L.plane_D(4), L.plane_D(5)});
+        }
+        if (m == 0) jobs.push_back({4, m, L.plane_D(6), -1});
+    }
+}
+
+constexpr double kBatchBytes = 2.0 * (1 << 30);    // work grids of one batch of inverse transforms
+constexpr double kSpectraBytes = 24.0 * (1 << 30); // kernel spectra kept per level
 
 }  // namespace
 
@@ -405,24 +466,23 @@ bool fft_geometry(const t3_plan *plan, const GridLevel &lv, int *nx, int *ny, in
     return *nx > 0 && *ny > 0;
 }
 
-// Modelled time (ms) of the FFT route for a level: two-dimensional
-// transforms of three passes, each reading and writing the grid; one kernel
-// transform per order and one inverse per (field, order), per bin.
+// Modelled time (ms) of the FFT route for a level: the inverse transforms
+// (three passes over the grid each, the first reading two grids), plus the
+// kernel transforms unless they are kept from an earlier call.
 double fft_cost_ms(const t3_plan *plan, const GridLevel &lv)
 {
     int nx, ny, rx, ry;
     if (lv.n_pix == 0 || !fft_geometry(plan, lv, &nx, &ny, &rx, &ry)) return 1e30;
-    const int m_lo = -plan->n_max - 3, m_hi = std::max(plan->n_max - 1, plan->w_max);
-    int kern = 0, inv = 0;
-    for (int m = m_lo; m <= m_hi; ++m) {
-        const int g = m <= plan->n_max - 1, w = m >= 0 && m <= plan->w_max;
-        const int d = (m == -6) + 2 * (m == -2) + (m == 0);
-        if (g + w + d == 0) continue;
-        ++kern;
-        inv += g + w + d;
-    }
-    const double bytes = 6.0 * sizeof(float2) * (double)nx * ny * (double)(kern + inv) * lv.nb;
-    return 1e3 * bytes / 3.0e12;
+    int m_lo, m_hi;
+    std::vector<Job> jobs;
+    ChunkLayout L = lv.L;
+    jobs_of(plan, L, &m_lo, &m_hi, jobs);
+    const double grid = sizeof(float2) * (double)nx * ny;
+    double bytes = 7.0 * grid * (double)jobs.size() * lv.nb;
+    const bool kept = lv.spec_key[0] == nx && lv.spec_key[1] == ny && lv.spec_key[2] == rx && lv.spec_key[3] == ry &&
+                      lv.spec_key[4] == lv.side && lv.spec_key[5] == lv.b_lo && lv.spec_key[6] == lv.nb;
+    if (!kept) bytes += 5.0 * grid * (double)(m_hi - m_lo + 1) * lv.nb;
+    return 1e3 * bytes / 4.0e12 + 0.05 * lv.nb;
 }
 
 int fft_level(t3_plan *plan, GridLevel &lv, hipStream_t s)
@@ -433,17 +493,33 @@ int fft_level(t3_plan *plan, GridLevel &lv, hipStream_t s)
     if (!fft_geometry(plan, lv, &nx, &ny, &Rx, &Ry))
         return fail(T3_ERANGE, "t3_forward_grid: FFT grid above 8192 pixels per side");
     const int nx_occ = lv.nx_occ, ny_occ = lv.ny_occ;
-    const int *box = lv.box;
+    const ChunkLayout &L = lv.L;
     const size_t N = (size_t)nx * ny;
-    // buffers: five field spectra, kernel spectrum, three work grids, slot map, twiddles
-    T3_TRY(lv.fft_buf.reserve(sizeof(float2) * N * 9 + sizeof(int) * (size_t)nx_occ * ny_occ +
-                              sizeof(float2) * (size_t)(nx + ny)));
-    float2 *F[5];
-    for (int f = 0; f < 5; ++f) F[f] = lv.fft_buf.as<float2>() + (size_t)f * N;
-    float2 *Ks = F[4] + N, *A = Ks + N, *Bw = A + N, *Kg = Bw + N;
-    int *slot = reinterpret_cast<int *>(Kg + N);
+    int m_lo, m_hi;
+    std::vector<Job> jobs;
+    jobs_of(plan, L, &m_lo, &m_hi, jobs);
+    const int n_ord = m_hi - m_lo + 1;
+    const int n_jobs = (int)jobs.size();
+    // kernel spectra of every (bin, order): kept between calls when they fit
+    const double spec_bytes = sizeof(float2) * (double)N * n_ord * lv.nb;
+    const bool keep = spec_bytes <= kSpectraBytes;
+    const int64_t key[7] = {nx, ny, Rx, Ry, lv.side, lv.b_lo, lv.nb};
+    bool have = keep;
+    for (int i = 0; i < 7; ++i) have = have && lv.spec_key[i] == key[i];
+    // batch of inverse transforms: two work grids per job
+    const int jb = (int)std::max(1.0, std::min((double)n_jobs, kBatchBytes / (2.0 * sizeof(float2) * N)));
+    const int kb = std::min(n_ord, jb);  // kernel orders per batch (when not kept)
+    const size_t n_spec = keep ? (size_t)n_ord * lv.nb : (size_t)n_ord;
+    T3_TRY(lv.fft_spec.reserve(sizeof(float2) * N * n_spec));
+    T3_TRY(lv.fft_buf.reserve(sizeof(float2) * N * (5 + 2 * (size_t)jb) + sizeof(int) * (size_t)nx_occ * ny_occ +
+                              sizeof(float2) * (size_t)(nx + ny) + sizeof(int) * 4 * (size_t)n_jobs));
+    float2 *F = lv.fft_buf.as<float2>();  // five field spectra
+    float2 *A = F + 5 * N, *Bw = A + (size_t)jb * N;
+    int *slot = reinterpret_cast<int *>(Bw + (size_t)jb * N);
     float2 *twx = reinterpret_cast<float2 *>(slot + (size_t)nx_occ * ny_occ);
     float2 *twy = twx + nx;
+    int *jf = reinterpret_cast<int *>(twy + ny), *jk = jf + n_jobs, *jre = jk + n_jobs, *jim = jre + n_jobs;
+    float2 *Ks = lv.fft_spec.as<float2>();
     {
         std::vector<float2> h(nx + ny);
         for (int k = 0; k < nx; ++k) {
@@ -454,8 +530,16 @@ int fft_level(t3_plan *plan, GridLevel &lv, hipStream_t s)
             const double a = -2.0 * M_PI * (double)k / ny;
             h[nx + k] = make_float2((float)std::cos(a), (float)std::sin(a));
         }
+        std::vector<int> jt(4 * (size_t)n_jobs);
+        for (int j = 0; j < n_jobs; ++j) {
+            jt[j] = jobs[j].f;
+            jt[n_jobs + j] = jobs[j].m - m_lo;  // spectrum slot within the bin
+            jt[2 * n_jobs + j] = jobs[j].p_re;
+            jt[3 * n_jobs + j] = jobs[j].p_im;
+        }
         T3_HIP_CHECK(hipMemcpyAsync(twx, h.data(), sizeof(float2) * h.size(), hipMemcpyHostToDevice, s));
-        T3_HIP_CHECK(hipStreamSynchronize(s));  // h leaves scope
+        T3_HIP_CHECK(hipMemcpyAsync(jf, jt.data(), sizeof(int) * jt.size(), hipMemcpyHostToDevice, s));
+        T3_HIP_CHECK(hipStreamSynchronize(s));  // h, jt leave scope
     }
     RowPlan px, py;
     factor(nx, px);
@@ -463,68 +547,48 @@ int fft_level(t3_plan *plan, GridLevel &lv, hipStream_t s)
     px.tw = twx;
     py.tw = twy;
 
-    // fields on the grid, slot map
-    hipLaunchKernelGGL(k_zero_c, dim3(nblk(N * 5, 256)), dim3(256), 0, s, F[0], N * 5);
-    T3_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(k_zero_c, dim3(nblk(N, 256)), dim3(256), 0, s, Kg, N);
+    // fields on the grid, slot map, forward transforms -> spectra [nx][ny]
+    hipLaunchKernelGGL(k_zero_c, dim3(nblk(N * 5, 256)), dim3(256), 0, s, F, N * 5);
     T3_HIP_CHECK(hipGetLastError());
     T3_TRY(fill_int(slot, (int64_t)nx_occ * ny_occ, -1, s));
-    ScatterArgs sa;
-    sa.pos = lv.pix.pos.as<int2>();
-    sa.sum = lv.pix_sum.as<double>();
-    sa.perm = lv.pix.perm.as<int>();
-    sa.n = n_pix;
-    sa.x0 = box[0];
-    sa.y0 = box[1];
-    sa.side = lv.side;
-    sa.nx = nx;
-    sa.ny = ny;
-    sa.nx_occ = nx_occ;
-    for (int f = 0; f < 5; ++f) sa.f[f] = F[f];
-    sa.slot = slot;
+    ScatterArgs sa{lv.pix.pos.as<int2>(), lv.pix_sum.as<double>(), lv.pix.perm.as<int>(), n_pix, lv.box[0],
+                   lv.box[1], lv.side, nx, nx_occ, N, F, slot};
     hipLaunchKernelGGL(k_scatter_fields, dim3(nblk(n_pix, 256)), dim3(256), 0, s, sa);
     T3_HIP_CHECK(hipGetLastError());
-    // forward transforms: rows over x, transpose, rows over y -> spectrum [nx][ny]
-    for (int f = 0; f < 5; ++f) {
-        T3_TRY(rows_launch(px, -1.0f, LoadGrid{F[f]}, StoreGrid{A}, ny, s));
-        T3_TRY(transpose(A, Bw, ny, nx, s));
-        T3_TRY(rows_launch(py, -1.0f, LoadGrid{Bw}, StoreGrid{F[f]}, nx, s));
+    for (int f0 = 0; f0 < 5; f0 += jb) {
+        const int nf = std::min(jb, 5 - f0);
+        T3_TRY(rows_launch(px, -1.0f, LoadGrid{F + f0 * N, N}, StoreGrid{A, N}, ny, nf, s));
+        T3_TRY(transpose(A, Bw, ny, nx, nf, N, s));
+        T3_TRY(rows_launch(py, -1.0f, LoadGrid{Bw, N}, StoreGrid{F + f0 * N, N}, nx, nf, s));
     }
 
-    const ChunkLayout &L = lv.L;
     const float scale = 1.0f / (float)N;
-    const int m_lo = -plan->n_max - 3, m_hi = std::max(plan->n_max - 1, plan->w_max);
-    // inverse transform of F[f] * Ks into planes (p_re, p_im) of local bin bl
-    auto inverse = [&](int f, int p_re, int p_im, int bl) -> int {
-        T3_TRY(rows_launch(py, 1.0f, LoadProduct{F[f], Ks}, StoreGrid{A}, nx, s));
-        T3_TRY(transpose(A, Bw, nx, ny, s));
-        StorePlanes sp{slot, nx_occ, ny_occ, lv.planes.as<float>(), p_re, p_im, L.K, L.B, bl, scale};
-        T3_TRY(rows_launch(px, 1.0f, LoadGrid{Bw}, sp, ny, s));
-        return T3_OK;
-    };
     for (int bl = 0; bl < lv.nb; ++bl) {
         const int b = lv.b_lo + bl;
-        for (int m = m_lo; m <= m_hi; ++m) {
-            const bool need_g = m <= plan->n_max - 1;
-            const bool need_w = m >= 0 && m <= plan->w_max;
-            const bool need_d = m == -6 || m == -2 || m == 0;
-            if (!need_g && !need_w && !need_d) continue;
-            // kernel spectrum: only the rows |dy| <= R of the kernel grid are non-zero
-            LoadKernel lk{nx, ny, Rx, Ry, m, (double)lv.side, plan->e2[b], plan->e2[b + 1]};
-            const int head = Ry + 1, tail = Ry;  // ny >= 2 Ry + 1
-            T3_TRY(rows_launch(px, -1.0f, lk, StoreGrid{Kg}, head + tail, s, 0, head, ny - head - tail));
-            T3_TRY(transpose(Kg, A, ny, nx, s));
-            T3_TRY(rows_launch(py, -1.0f, LoadGrid{A}, StoreGrid{Ks}, nx, s));
-            if (need_g) T3_TRY(inverse(0, L.plane_G(m, 0), L.plane_G(m, 1), bl));
-            if (need_w) T3_TRY(inverse(1, L.plane_W(m, 0), L.plane_W(m, 1), bl));
-            if (m == -6) T3_TRY(inverse(2, L.plane_D(0), L.plane_D(1), bl));
-            if (m == -2) {
-                T3_TRY(inverse(2, L.plane_D(2), L.plane_D(3), bl));
-                T3_TRY(inverse(3, L.plane_D(4), L.plane_D(5), bl));
+        float2 *Kb = Ks + (keep ? (size_t)bl * n_ord * N : 0);  // spectra of this bin's orders
+        if (!have) {
+            // only the rows |dy| <= Ry of a kernel grid are non-zero (ny >= 2 Ry + 1)
+            const int head = Ry + 1, tail = Ry;
+            for (int m0 = 0; m0 < n_ord; m0 += kb) {
+                const int nm = std::min(kb, n_ord - m0);
+                hipLaunchKernelGGL(k_zero_c, dim3(nblk(N * nm, 256)), dim3(256), 0, s, A, N * nm);
+                T3_HIP_CHECK(hipGetLastError());
+                LoadKernel lk{nx, ny, Rx, Ry, m_lo + m0, (double)lv.side, plan->e2[b], plan->e2[b + 1]};
+                T3_TRY(rows_launch(px, -1.0f, lk, StoreGrid{A, N}, head + tail, nm, s, head, ny - head - tail));
+                T3_TRY(transpose(A, Bw, ny, nx, nm, N, s));
+                T3_TRY(rows_launch(py, -1.0f, LoadGrid{Bw, N}, StoreGrid{Kb + (size_t)m0 * N, N}, nx, nm, s));
             }
-            if (m == 0) T3_TRY(inverse(4, L.plane_D(6), -1, bl));
+        }
+        // inverse transforms of field spectrum x kernel spectrum, values at the pixels
+        for (int j0 = 0; j0 < n_jobs; j0 += jb) {
+            const int nj = std::min(jb, n_jobs - j0);
+            T3_TRY(rows_launch(py, 1.0f, LoadProduct{F, Kb, N, jf, jk, j0}, StoreGrid{A, N}, nx, nj, s));
+            T3_TRY(transpose(A, Bw, nx, ny, nj, N, s));
+            StorePlanes sp{slot, nx_occ, ny_occ, lv.planes.as<float>(), jre, jim, j0, L.K, L.B, bl, scale};
+            T3_TRY(rows_launch(px, 1.0f, LoadGrid{Bw, N}, sp, ny, nj, s));
         }
     }
+    for (int i = 0; i < 7; ++i) lv.spec_key[i] = keep ? key[i] : -1;
     return T3_OK;
 }
 

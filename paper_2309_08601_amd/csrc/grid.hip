@@ -56,6 +56,8 @@ void GridLevel::release()
     planes.release();
     fft_misc.release();
     fft_buf.release();
+    fft_spec.release();
+    for (auto &k : spec_key) k = -1;
 }
 
 namespace {

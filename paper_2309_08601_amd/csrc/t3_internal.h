@@ -121,6 +121,8 @@ struct GridLevel {
     int nx_occ = 0, ny_occ = 0; // occupied extent, pixels
     int method = 0;             // route taken: T3_GRID_DIRECT or T3_GRID_FFT
     DevBuf fft_misc, fft_buf;   // FFT route: bounding box, grids and tables
+    DevBuf fft_spec;            // FFT route: kernel spectra of every (bin, order)
+    int64_t spec_key[7] = {-1, -1, -1, -1, -1, -1, -1};  // geometry the spectra belong to
     void release();
 };
 

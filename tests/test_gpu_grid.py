@@ -111,3 +111,22 @@ def test_combined_field_shaped(t3):
     for method in ("direct", "fft", "auto"):
         _compare(t3, plan, cat, edges, wl.n_max, int(0.25 / LATTICE_UNIT), levels, False, (0, 0), "field-shaped",
                  method)
+
+
+def test_fft_kernel_spectra_kept_between_calls(t3):
+    """The bin-kernel spectra of a level depend only on the plan and the grid
+    geometry: a second call on the same footprint reuses them and must give
+    the same multipoles bit for bit; a catalog with another footprint (other
+    grid sides) recomputes them and must still match the oracle."""
+    cat = random_catalog(4000, 50.0, seed=31)
+    edges = np.geomspace(1.0, 14.0, 7)
+    levels = [0, 0, 1, 1, 2, 3]
+    box_lo = (-12345, -6789)
+    plan = t3.Plan(edges, 6, box_lo=box_lo, box_size=1 << 23)
+    dc = t3.DeviceCatalog.from_catalog(cat)
+    delta = int(0.25 / LATTICE_UNIT)
+    a, _ = plan.forward_grid(dc, delta, levels, method="fft")
+    b, _ = plan.forward_grid(dc, delta, levels, method="fft")
+    assert torch.equal(a, b)
+    other = random_catalog(3000, 35.0, seed=32)
+    _compare(t3, plan, other, edges, 6, delta, levels, False, box_lo, "new footprint", "fft")
