@@ -251,7 +251,7 @@ struct StoreGrid {
 // Values at the non-empty pixels into stage-1 planes (layout K, nb) of
 // local bin b: planes re[job], im[job] (im < 0: real part only).
 struct StorePlanes {
-    const int *slot;   // [ny_occ][nx_occ] sorted pixel slot or -1
+    const int *slot;   // [ny_occ][nx_occ] pixel index or -1
     int nx_occ, ny_occ;
     float *planes;
     const int *p_re, *p_im;
@@ -312,23 +312,35 @@ __global__ void k_zero_c(float2 *p, size_t n)
     if (i < n) p[i] = make_float2(0.f, 0.f);
 }
 
-// occupied pixel range: min/max corner over the pixel catalog
-__global__ void k_bbox(const int2 *__restrict__ pos, int64_t n, int *__restrict__ box)
+// occupied pixel range: min/max corner over the pixels (wave reduction, then
+// one atomic per wave)
+__global__ void k_bbox(const int32_t *__restrict__ px, const int32_t *__restrict__ py, int64_t n,
+                       int *__restrict__ box)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int2 p = pos[i];
-    atomicMin(&box[0], p.x);
-    atomicMin(&box[1], p.y);
-    atomicMax(&box[2], p.x);
-    atomicMax(&box[3], p.y);
+    int x0 = 0x7fffffff, y0 = 0x7fffffff, x1 = (int)0x80000000, y1 = (int)0x80000000;
+    if (i < n) {
+        x0 = x1 = px[i];
+        y0 = y1 = py[i];
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        x0 = min(x0, __shfl_xor(x0, d, 64));
+        y0 = min(y0, __shfl_xor(y0, d, 64));
+        x1 = max(x1, __shfl_xor(x1, d, 64));
+        y1 = max(y1, __shfl_xor(y1, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&box[0], x0);
+        atomicMin(&box[1], y0);
+        atomicMax(&box[2], x1);
+        atomicMax(&box[3], y1);
+    }
 }
 
-// five field grids ([ny][nx] complex, N apart) and the slot map from the sorted pixels
+// five field grids ([ny][nx] complex, N apart) and the slot map (pixel index)
 struct ScatterArgs {
-    const int2 *pos;
-    const double *sum;   // [pixel][3], by pixel index
-    const int *perm;     // sorted slot -> pixel
+    const int32_t *px, *py;  // corners, by pixel index
+    const double *sum;       // [pixel][3]
     int64_t n;
     int x0, y0;
     int64_t side;
@@ -339,11 +351,9 @@ struct ScatterArgs {
 };
 __global__ void k_scatter_fields(ScatterArgs a)
 {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= a.n) return;
-    const int2 p = a.pos[s];
-    const int x = (int)(((int64_t)p.x - a.x0) / a.side), y = (int)(((int64_t)p.y - a.y0) / a.side);
-    const int P = a.perm[s];
+    const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= a.n) return;
+    const int x = (int)(((int64_t)a.px[P] - a.x0) / a.side), y = (int)(((int64_t)a.py[P] - a.y0) / a.side);
     const double c1 = a.sum[3 * (int64_t)P], c2 = a.sum[3 * (int64_t)P + 1], w = a.sum[3 * (int64_t)P + 2];
     const size_t o = (size_t)y * a.nx + x;
     a.f[o] = make_float2((float)c1, (float)c2);
@@ -351,7 +361,7 @@ __global__ void k_scatter_fields(ScatterArgs a)
     a.f[2 * a.N + o] = make_float2((float)(c1 * c1 - c2 * c2), (float)(2.0 * c1 * c2));
     a.f[3 * a.N + o] = make_float2((float)(c1 * c1 + c2 * c2), 0.f);
     a.f[4 * a.N + o] = make_float2((float)(w * w), 0.f);
-    a.slot[(size_t)y * a.nx_occ + x] = (int)s;
+    a.slot[(size_t)y * a.nx_occ + x] = (int)P;
 }
 
 inline unsigned nblk(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -432,16 +442,15 @@ constexpr double kSpectraBytes = 24.0 * (1 << 30); // kernel spectra kept per le
 
 }  // namespace
 
-// Occupied pixel range of a level (corners), read back to the host.
-int level_bbox(GridLevel &lv, hipStream_t s)
+// Occupied pixel range of a level (corners px, py by pixel), read back to the host.
+int level_bbox(GridLevel &lv, const int32_t *px, const int32_t *py, hipStream_t s)
 {
     lv.nx_occ = lv.ny_occ = 0;
     if (lv.n_pix == 0) return T3_OK;
     T3_TRY(lv.fft_misc.reserve(sizeof(int) * 4));
     const int init[4] = {0x7fffffff, 0x7fffffff, (int)0x80000000, (int)0x80000000};
     T3_HIP_CHECK(hipMemcpyAsync(lv.fft_misc.ptr, init, sizeof(init), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_bbox, dim3(nblk(lv.n_pix, 256)), dim3(256), 0, s, (const int2 *)lv.pix.pos.as<int2>(),
-                       lv.n_pix, lv.fft_misc.as<int>());
+    hipLaunchKernelGGL(k_bbox, dim3(nblk(lv.n_pix, 256)), dim3(256), 0, s, px, py, lv.n_pix, lv.fft_misc.as<int>());
     T3_HIP_CHECK(hipGetLastError());
     T3_HIP_CHECK(hipMemcpyAsync(lv.box, lv.fft_misc.ptr, sizeof(lv.box), hipMemcpyDeviceToHost, s));
     T3_HIP_CHECK(hipStreamSynchronize(s));
@@ -551,8 +560,10 @@ int fft_level(t3_plan *plan, GridLevel &lv, hipStream_t s)
     hipLaunchKernelGGL(k_zero_c, dim3(nblk(N * 5, 256)), dim3(256), 0, s, F, N * 5);
     T3_HIP_CHECK(hipGetLastError());
     T3_TRY(fill_int(slot, (int64_t)nx_occ * ny_occ, -1, s));
-    ScatterArgs sa{lv.pix.pos.as<int2>(), lv.pix_sum.as<double>(), lv.pix.perm.as<int>(), n_pix, lv.box[0],
-                   lv.box[1], lv.side, nx, nx_occ, N, F, slot};
+    const int32_t *pxa = lv.pix_xy.as<int32_t>();
+    const size_t np1 = (size_t)(n_pix > 0 ? n_pix : 1);
+    ScatterArgs sa{pxa, pxa + np1, lv.pix_sum.as<double>(), n_pix, lv.box[0], lv.box[1], lv.side, nx, nx_occ, N, F,
+                   slot};
     hipLaunchKernelGGL(k_scatter_fields, dim3(nblk(n_pix, 256)), dim3(256), 0, s, sa);
     T3_HIP_CHECK(hipGetLastError());
     for (int f0 = 0; f0 < 5; f0 += jb) {

@@ -126,13 +126,15 @@ __global__ void k_pix_factors(const int *__restrict__ perm, int64_t n, const dou
     slot_of_pix[P] = (int)s;
 }
 
-// Galaxy centre (sorted slot of the main catalog) -> sorted slot of its pixel.
+// Galaxy centre (sorted slot of the main catalog) -> plane slot of its pixel
+// (slot_of_pix null: the pixel index itself).
 __global__ void k_cen_slot(const int *__restrict__ perm, int64_t n, const int *__restrict__ gal_pix,
                            const int *__restrict__ slot_of_pix, int *__restrict__ out)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
-    out[g] = slot_of_pix[gal_pix[perm[g]]];
+    const int P = gal_pix[perm[g]];
+    out[g] = slot_of_pix ? slot_of_pix[P] : P;
 }
 
 // Copy the planes of one level's bins from each centre's pixel into the
@@ -220,15 +222,6 @@ int build_level(t3_plan *plan, GridLevel &lv, const t3_catalog &cat, int method,
         hipLaunchKernelGGL(k_pix_build, dim3(blocks(nc, 256)), dim3(256), 0, s, a);
         T3_HIP_CHECK(hipGetLastError());
     }
-    const t3_catalog pc{n_pix, a.px, a.py, a.fg1, a.fg2, a.fw};
-    T3_TRY(build_cells(plan, lv.pix, pc, choose_grid(plan, n_pix), s));
-    if (n_pix > 0) {
-        hipLaunchKernelGGL(k_pix_factors, dim3(blocks(n_pix, 256)), dim3(256), 0, s,
-                           (const int *)lv.pix.perm.as<int>(), (int64_t)n_pix, (const double *)a.sum,
-                           lv.pix.cw.as<float4>(), lv.slot_of_pix.as<int>());
-        T3_HIP_CHECK(hipGetLastError());
-    }
-    T3_TRY(gather_sorted_centres(plan, lv.pix, lv.pix_centres, s));
     // harmonics of the level's bins at every pixel
     lv.L.n_max = plan->n_max;
     lv.L.w_max = plan->w_max;
@@ -238,10 +231,11 @@ int build_level(t3_plan *plan, GridLevel &lv, const t3_catalog &cat, int method,
     if (lv.L.floats() * sizeof(float) > ((size_t)64 << 30))
         return fail(T3_ERANGE, "t3_forward_grid: pixel planes of a level above 64 GiB (coarser Delta_1)");
     T3_TRY(lv.planes.reserve(sizeof(float) * lv.L.floats()));
+    lv.method = T3_GRID_DIRECT;
     if (n_pix == 0) return T3_OK;
     // route: pair sums over the pixel catalog, or FFT convolution on the
     // dense grid of the occupied pixels (modelled cost decides for AUTO)
-    T3_TRY(level_bbox(lv, s));
+    T3_TRY(level_bbox(lv, a.px, a.py, s));
     int m = method;
     if (m == T3_GRID_AUTO) {
         const double area = (double)lv.nx_occ * lv.ny_occ;  // pixels^2
@@ -253,7 +247,16 @@ int build_level(t3_plan *plan, GridLevel &lv, const t3_catalog &cat, int method,
         m = fft_cost_ms(plan, lv) < direct_ms ? T3_GRID_FFT : T3_GRID_DIRECT;
     }
     lv.method = m;
+    // the FFT route indexes planes by pixel (row-major over the box: rows of
+    // the grid are runs of consecutive pixels); the pair sums sweep the
+    // cell-sorted pixel catalog and index planes by its sorted slot
     if (m == T3_GRID_FFT) return fft_level(plan, lv, s);
+    const t3_catalog pc{n_pix, a.px, a.py, a.fg1, a.fg2, a.fw};
+    T3_TRY(build_cells(plan, lv.pix, pc, choose_grid(plan, n_pix), s));
+    hipLaunchKernelGGL(k_pix_factors, dim3(blocks(n_pix, 256)), dim3(256), 0, s, (const int *)lv.pix.perm.as<int>(),
+                       (int64_t)n_pix, (const double *)a.sum, lv.pix.cw.as<float4>(), lv.slot_of_pix.as<int>());
+    T3_HIP_CHECK(hipGetLastError());
+    T3_TRY(gather_sorted_centres(plan, lv.pix, lv.pix_centres, s));
     const SortedCatalog *cl[1] = {&lv.pix};
     T3_TRY(scan_chunk(plan, cl, nullptr, 1, lv.pix_centres, 0, n_pix, lv.L, lv.planes.as<float>(), lv.L.floats(),
                       plan->counter.as<unsigned long long>(), plan->scan_mode, s, lv.b_lo, lv.nb));
@@ -297,7 +300,8 @@ int forward_grid(t3_plan *plan, const t3_catalog &cat, int64_t delta, const int3
         if (cat.n > 0) {
             hipLaunchKernelGGL(k_cen_slot, dim3(blocks(cat.n, 256)), dim3(256), 0, s,
                                (const int *)plan->cats[0].perm.as<int>(), cat.n,
-                               (const int *)lv.gal_pix.as<int>(), (const int *)lv.slot_of_pix.as<int>(),
+                               (const int *)lv.gal_pix.as<int>(),
+                               lv.method == T3_GRID_FFT ? nullptr : (const int *)lv.slot_of_pix.as<int>(),
                                lv.cen_slot.as<int>());
             T3_HIP_CHECK(hipGetLastError());
         }

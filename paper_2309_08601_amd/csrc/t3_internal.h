@@ -113,9 +113,10 @@ struct GridLevel {
     DevBuf gal_pix;         // int [n_gal]: galaxy (input order) -> pixel
     SortedCatalog pix;      // the pixel catalog, cell-sorted for the sweep
     CentreSet pix_centres;  // every pixel, in pix's sorted order
-    DevBuf slot_of_pix;     // int [n_pix]: pixel -> sorted slot in pix
-    DevBuf cen_slot;        // int [n_gal]: galaxy (sorted slot) -> sorted pixel slot
-    DevBuf planes;          // stage-1 planes of every pixel, layout L
+    DevBuf slot_of_pix;     // int [n_pix]: pixel -> sorted slot in pix (pair-sum route)
+    DevBuf cen_slot;        // int [n_gal]: galaxy (sorted slot) -> plane slot of its pixel
+    DevBuf planes;          // stage-1 planes of every pixel, layout L: by sorted slot
+                            // (pair-sum route) or by pixel index (FFT route)
     ChunkLayout L;
     int box[4] = {0, 0, 0, 0};  // occupied corners: x min, y min, x max, y max
     int nx_occ = 0, ny_occ = 0; // occupied extent, pixels
@@ -215,7 +216,7 @@ int sphere_patch(t3_plan *plan, const t3_sphere_catalog &cat, const t3_patch &p,
 int add_doubles(double *dst, const double *src, size_t n, hipStream_t s);
 int forward_grid(t3_plan *plan, const t3_catalog &cat, int64_t delta, const int32_t *levels, int method,
                  double *ups_out, int64_t *n_pairs, hipStream_t s);
-int level_bbox(GridLevel &lv, hipStream_t s);
+int level_bbox(GridLevel &lv, const int32_t *px, const int32_t *py, hipStream_t s);
 double fft_cost_ms(const t3_plan *plan, const GridLevel &lv);
 int fft_level(t3_plan *plan, GridLevel &lv, hipStream_t s);
 int harmonics_export(t3_plan *plan, const CentreSet &cs, const ChunkLayout &L, const float *planes,
