@@ -157,6 +157,9 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
     }
     T3_TRY(timing_mark(plan, 0, false, s));
     T3_TRY(check_flag(plan, s, n_z > 1 ? "t3_forward_tomo" : "t3_forward"));
+    // leading bins with few neighbours per centre: one lane per centre
+    int n_lane = 0;
+    if (n_z == 1) T3_TRY(lane_bins(plan, plan->cats[0], 0, plan->B, kLaneNeighbours, s, &n_lane));
 
     ChunkLayout L = layout_of(plan);
     if (plan->chunk_req <= 0) {
@@ -197,7 +200,7 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
                 const int n = (int)((cs.n - c0) < L.K ? (cs.n - c0) : L.K);
                 T3_TRY(timing_mark(plan, 1, true, q));
                 T3_TRY(scan_chunk(plan, cl, order, n_z, cs, c0, n, L, plan->chunk.as<float>(), zstride,
-                                  plan->counter.as<unsigned long long>(), plan->scan_mode, q));
+                                  plan->counter.as<unsigned long long>(), plan->scan_mode, q, 0, plan->B, n_lane));
                 T3_TRY(timing_mark(plan, 1, false, q));
                 T3_TRY(timing_mark(plan, 2, true, q));
                 T3_TRY(contract_chunk(plan, cs, c0, n, L, plan->chunk.as<float>(), zstride, n_z, jk, out, q));

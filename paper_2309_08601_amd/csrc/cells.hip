@@ -244,6 +244,39 @@ int build_cells(t3_plan *plan, SortedCatalog &sc, const t3_catalog &cat, const C
     return T3_OK;
 }
 
+namespace {
+// number of non-empty cells (one atomic per wavefront)
+__global__ void k_count_nonempty(const int *__restrict__ start, int64_t ncells, unsigned *__restrict__ out)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned v = c < ncells && start[c + 1] > start[c] ? 1u : 0u;
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
+}
+}  // namespace
+
+int lane_bins(t3_plan *plan, const SortedCatalog &sc, int b0, int nb, double most, hipStream_t s, int *n_lane)
+{
+    *n_lane = 0;
+    if (sc.n == 0 || nb <= 0) return T3_OK;
+    const int64_t nc = sc.grid.ncells();
+    T3_TRY(plan->misc2.reserve(sizeof(unsigned) * 4));
+    T3_HIP_CHECK(hipMemsetAsync(plan->misc2.ptr, 0, sizeof(unsigned), s));
+    hipLaunchKernelGGL(k_count_nonempty, dim3(blocks_for(nc, 256)), dim3(256), 0, s, (const int *)sc.cell_start.as<int>(),
+                       nc, plan->misc2.as<unsigned>());
+    T3_HIP_CHECK(hipGetLastError());
+    unsigned occupied = 0;
+    T3_HIP_CHECK(hipMemcpyAsync(&occupied, plan->misc2.ptr, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    T3_HIP_CHECK(hipStreamSynchronize(s));
+    if (occupied == 0) return T3_OK;
+    // galaxies per lattice step^2 over the occupied cells
+    const double density = (double)sc.n / ((double)occupied * (double)sc.grid.cell * (double)sc.grid.cell);
+    int k = 0;
+    while (k < nb && density * 3.14159265358979323846 * (plan->e2[b0 + k + 1] - plan->e2[b0 + k]) <= most) ++k;
+    *n_lane = k;
+    return T3_OK;
+}
+
 int gather_centres(t3_plan *plan, const t3_catalog &cat, const int32_t *idx, int64_t n,
                    CentreSet &cs, hipStream_t s)
 {

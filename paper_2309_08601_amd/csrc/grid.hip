@@ -325,12 +325,14 @@ int forward_grid(t3_plan *plan, const t3_catalog &cat, int64_t delta, const int3
     T3_TRY(zero_doubles(ups_out, n_out, s));
     const SortedCatalog *cl[1] = {&plan->cats[0]};
     const bool jk = !(plan->flags & T3_FLAG_KEEP_JK);
+    int n_lane = 0;
+    T3_TRY(lane_bins(plan, plan->cats[0], 0, b_disc, kLaneNeighbours, s, &n_lane));
     for (int64_t c0 = 0; c0 < cs.n; c0 += L.K) {
         const int n = (int)((cs.n - c0) < L.K ? (cs.n - c0) : L.K);
         T3_TRY(timing_mark(plan, 1, true, s));
         if (b_disc > 0)
             T3_TRY(scan_chunk(plan, cl, nullptr, 1, cs, c0, n, L, plan->chunk.as<float>(), zstride,
-                              plan->counter.as<unsigned long long>(), plan->scan_mode, s, 0, b_disc));
+                              plan->counter.as<unsigned long long>(), plan->scan_mode, s, 0, b_disc, n_lane));
         for (int l = 1; l <= kMaxGridLevels; ++l) {
             const GridLevel &lv = plan->grid[l - 1];
             if (lv.nb == 0) continue;

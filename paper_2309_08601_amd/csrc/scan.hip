@@ -46,7 +46,8 @@ struct ScanArgs {
     const int2 *cpos;       // centre positions (chunk-relative)
     int n_c;                // centres in the chunk
     int n_bins;             // bins swept (squared edges e2[0 .. n_bins])
-    int B_out;              // bins of the plane layout (swept bin b is stored as bin b)
+    int B_out;              // bins of the plane layout
+    int b_out0;             // swept bin b is stored as bin b_out0 + b
     int n_max;
     int K;                  // chunk capacity (plane layout)
     const short *dest;      // slot -> plane (or -1) for this pass
@@ -258,7 +259,7 @@ __device__ __forceinline__ unsigned long long scan_task(const ScanArgs &a, int z
         for (int k = 0; k < S::P; ++k) {
             const int slot = S::P * lane + k;
             const int pl = a.dest[slot];
-            if (pl >= 0) out[chunk_offset(pl, ci, b, a.K, a.B_out)] = (float)accd[k];
+            if (pl >= 0) out[chunk_offset(pl, ci, a.b_out0 + b, a.K, a.B_out)] = (float)accd[k];
         }
     }
     return pairs;
@@ -320,6 +321,137 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
     if (lane == 0 && a.npairs) atomicAdd(a.npairs, pairs);
 }
 
+// Lane per centre, for bins with few neighbours per centre: the wavefront's
+// 64 centres are swept independently (each lane walks its own cell rows), so
+// the per-(centre, bin) cost follows the neighbour count instead of a full
+// 64-lane batch plus a 64-lane reduction.  Each lane first collects up to
+// kLaneList in-bin neighbours (indices in LDS), then the wavefront runs the
+// same per-pair arithmetic on the lists in lock-step (max count iterations)
+// and goes back to collecting until every lane has finished its annulus.
+// Sums stay in FP32 per lane (the host sends only bins whose expected
+// neighbour count keeps that within the FP32 error of the wavefront path).
+constexpr int kLaneList = 32;
+constexpr int kLaneBlock = 128;
+
+template <int GA, int GB, int WA, int WB, bool EXTRA>
+__global__ __launch_bounds__(kLaneBlock) void k_scan_lane(ScanArgs a)
+{
+    using S = PassShape<GA, GB, WA, WB, EXTRA>;
+    __shared__ int list[kLaneList][kLaneBlock];
+    const int t = threadIdx.x;
+    const int ci = blockIdx.x * kLaneBlock + t;
+    const bool active = ci < a.n_c;
+    const int2 cp = active ? a.cpos[ci] : make_int2(0, 0);
+    const SweepArgs &sw = a.sw[0];
+    const CellGrid &g = sw.g;
+    float *out = a.out[0];
+    unsigned long long pairs = 0;
+    for (int b = 0; b < a.n_bins; ++b) {
+        const double e2lo = a.e2[b], e2hi = a.e2[b + 1];
+        float acc[S::V];
+#pragma unroll
+        for (int k = 0; k < S::V; ++k) acc[k] = 0.0f;
+        // this lane's walk: rows [row, row_hi], current range [gi, gend), second range of the row pending
+        const long long R = (long long)sqrt(e2hi) + 1;
+        long long row = floor_div((long long)cp.y - R - g.oy, g.cell);
+        long long row_hi = floor_div((long long)cp.y + R - g.oy, g.cell);
+        row = row < 0 ? 0 : row;
+        row_hi = row_hi > g.ncy - 1 ? g.ncy - 1 : row_hi;
+        if (!active) row_hi = row - 1;
+        int gi = 0, gend = 0;
+        int2 second = make_int2(0, 0);
+        bool have_second = false;
+        for (;;) {
+            // collect: up to kLaneList in-bin neighbours or the end of the annulus
+            int cnt = 0;
+            bool done = false;
+            while (cnt < kLaneList) {
+                if (gi + 4 <= gend && cnt + 4 <= kLaneList) {
+                    // four independent loads in flight (one wavefront per SIMD hides little latency)
+                    int2 p[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) p[u] = sw.npos[gi + u];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int dx = p[u].x - cp.x, dy = p[u].y - cp.y;
+                        const double r2 = fma((double)dx, (double)dx, (double)dy * (double)dy);
+                        if (r2 >= e2lo && r2 < e2hi) list[cnt++][t] = gi + u;
+                    }
+                    gi += 4;
+                } else if (gi < gend) {
+                    const int2 p = sw.npos[gi];
+                    const int dx = p.x - cp.x, dy = p.y - cp.y;
+                    const double r2 = fma((double)dx, (double)dx, (double)dy * (double)dy);
+                    if (r2 >= e2lo && r2 < e2hi) list[cnt++][t] = gi;
+                    ++gi;
+                } else if (have_second) {
+                    gi = second.x;
+                    gend = second.y;
+                    have_second = false;
+                } else if (row <= row_hi) {
+                    int2 sa, sb;
+                    row_ranges(sw, cp, row, e2lo, e2hi, sa, sb);
+                    ++row;
+                    gi = sa.x;
+                    gend = sa.y;
+                    second = sb;
+                    have_second = sb.y > sb.x;
+                } else {
+                    done = true;
+                    break;
+                }
+            }
+            pairs += (unsigned long long)cnt;
+            // process the lists in lock-step
+            int most = cnt;
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) most = max(most, __shfl_xor(most, d, 64));
+            // the next neighbour's loads are issued before the current one's arithmetic
+            int2 pc = make_int2(cp.x, cp.y);
+            float4 cc = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (cnt > 0) {
+                const int j = list[0][t];
+                pc = sw.npos[j];
+                cc = sw.ncw[j];
+            }
+            for (int k = 0; k < most; ++k) {
+                int2 pn = pc;
+                float4 cn = cc;
+                if (k + 1 < cnt) {
+                    const int j = list[k + 1][t];
+                    pn = sw.npos[j];
+                    cn = sw.ncw[j];
+                }
+                if (k < cnt) accumulate<GA, GB, WA, WB, EXTRA>(acc, pc.x - cp.x, pc.y - cp.y, cc.x, cc.y, cc.z);
+                pc = pn;
+                cc = cn;
+            }
+            const bool all_done = __all(done);
+            if (all_done) break;
+        }
+        if (active) {
+            // S -> G conversion (as in the wavefront reduction), then every slot to its plane
+#pragma unroll
+            for (int k = 0; k < S::NG; ++k) {
+                const float s1 = acc[4 * k], s2 = acc[4 * k + 1], s3 = acc[4 * k + 2], s4 = acc[4 * k + 3];
+                acc[4 * k + 0] = s1 - s2;
+                acc[4 * k + 1] = s3 + s4;
+                acc[4 * k + 2] = s1 + s2;
+                acc[4 * k + 3] = s4 - s3;
+            }
+#pragma unroll
+            for (int k = 0; k < S::V; ++k) {
+                const int pl = a.dest[k];
+                if (pl >= 0) out[chunk_offset(pl, ci, a.b_out0 + b, a.K, a.B_out)] = acc[k];
+            }
+        }
+    }
+    // one atomic per wavefront
+    unsigned long long tot = pairs;
+    for (int d = 32; d > 0; d >>= 1) tot += __shfl_xor(tot, d, 64);
+    if ((t & 63) == 0 && a.npairs && tot) atomicAdd(a.npairs, tot);
+}
+
 __global__ void k_zero_u32(unsigned *p) { *p = 0u; }
 
 // --------------------------------------------------------------- host side
@@ -328,13 +460,14 @@ struct PassDesc {
     bool extra;
     void (*kernel)(ScanArgs);          // single catalog, one wavefront per centre
     void (*kernel_general)(ScanArgs);  // n_z catalogs, either launch mode
+    void (*kernel_lane)(ScanArgs);     // single catalog, one lane per centre (small bins)
 };
 
 template <int GA, int GB, int WA, int WB, bool EXTRA>
 PassDesc make_pass()
 {
     return PassDesc{GA, GB, WA, WB, EXTRA, k_scan<GA, GB, WA, WB, EXTRA, false>,
-                    k_scan<GA, GB, WA, WB, EXTRA, true>};
+                    k_scan<GA, GB, WA, WB, EXTRA, true>, k_scan_lane<GA, GB, WA, WB, EXTRA>};
 }
 
 // Variant table: a single pass for n_max up to the capacity C (orders
@@ -450,11 +583,12 @@ int scan_prepare(t3_plan *plan)
 
 int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order, int n_z,
                const CentreSet &cs, int64_t c0, int n_c, const ChunkLayout &L, float *planes,
-               size_t zstride, unsigned long long *npairs, int mode, hipStream_t s, int b0, int nb)
+               size_t zstride, unsigned long long *npairs, int mode, hipStream_t s, int b0, int nb, int n_lane)
 {
     if (n_c <= 0) return T3_OK;
     if (nb < 0) nb = L.B;
     if (b0 < 0 || nb < 1 || nb > L.B || b0 + nb > plan->B) return fail(T3_ERANGE, "scan: bad bin range");
+    if (n_lane < 0 || n_lane > nb || (n_lane > 0 && n_z != 1)) return fail(T3_ERANGE, "scan: bad lane-bin count");
     if (n_z < 1 || n_z > kMaxZ) return fail(T3_ERANGE, "scan: bad catalog count");
     if (plan->scan_var < 0) T3_TRY(scan_prepare(plan));
     const Variant &var = variants()[plan->scan_var];
@@ -471,11 +605,30 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
     a.n_z = n_z;
     a.cpos = cs.pos.as<int2>() + c0;
     a.n_c = n_c;
-    a.n_bins = nb;
     a.B_out = L.B;
     a.n_max = L.n_max;
     a.K = L.K;
-    for (int b = 0; b <= nb; ++b) a.e2[b] = plan->e2[b0 + b];
+    const int npass = var.npass + (plan->w_max > var.cap ? 1 : 0);
+    // bins [b0, b0 + n_lane): one lane per centre
+    if (n_lane > 0) {
+        ScanArgs al = a;
+        al.n_bins = n_lane;
+        al.b_out0 = 0;
+        for (int b = 0; b <= n_lane; ++b) al.e2[b] = plan->e2[b0 + b];
+        for (int p = 0; p < npass; ++p) {
+            const PassDesc &pd = p < var.npass ? var.pass[p] : var.wext;
+            al.dest = plan->dest.as<short>() + plan->scan_dest_off[p];
+            al.npairs = p == 0 ? npairs : nullptr;
+            hipLaunchKernelGGL(pd.kernel_lane, dim3((unsigned)((n_c + kLaneBlock - 1) / kLaneBlock)),
+                               dim3(kLaneBlock), 0, s, al);
+            T3_HIP_CHECK(hipGetLastError());
+        }
+    }
+    if (n_lane == nb) return T3_OK;
+    // bins [b0 + n_lane, b0 + nb): one wavefront per centre
+    a.n_bins = nb - n_lane;
+    a.b_out0 = n_lane;
+    for (int b = 0; b <= a.n_bins; ++b) a.e2[b] = plan->e2[b0 + n_lane + b];
     const int total = n_z * n_c;
     int nwg;
     if (mode == 1) {
@@ -493,7 +646,6 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
         a.queue = nullptr;
         a.grab = 0;
     }
-    const int npass = var.npass + (plan->w_max > var.cap ? 1 : 0);
     for (int p = 0; p < npass; ++p) {
         const PassDesc &pd = p < var.npass ? var.pass[p] : var.wext;
         a.dest = plan->dest.as<short>() + plan->scan_dest_off[p];

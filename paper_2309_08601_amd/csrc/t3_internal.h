@@ -190,11 +190,18 @@ int scan_prepare(t3_plan *plan);
 // centre, one launch per catalog; mode 1: one persistent launch over every
 // (centre, catalog) task with a work counter.  Only the plan's bins
 // [b0, b0 + nb) are swept (nb < 0: all L.B of them); swept bin k is stored
-// as bin k of the layout L (L.B >= nb).
+// as bin k of the layout L (L.B >= nb).  The first n_lane of them (n_z = 1
+// only) run one lane per centre: for bins with few neighbours per centre.
 int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order, int n_z,
                const CentreSet &cs, int64_t c0, int n_c, const ChunkLayout &L, float *planes,
                size_t zstride, unsigned long long *npairs, int mode, hipStream_t s, int b0 = 0,
-               int nb = -1);
+               int nb = -1, int n_lane = 0);
+// Leading bins of [b0, b0 + nb) whose expected neighbours per centre are at
+// most `most` (uniform density over the non-empty cells of sc); synchronises s.
+// Lane-per-centre sums stay in FP32: with up to ~90 terms (the Poisson tail
+// of 64 expected) the rounding of a sequential sum is below 3e-7 relative.
+constexpr double kLaneNeighbours = 64.0;
+int lane_bins(t3_plan *plan, const SortedCatalog &sc, int b0, int nb, double most, hipStream_t s, int *n_lane);
 int fill_int(int *p, int64_t n, int v, hipStream_t s);
 int exclusive_scan(int *data, int64_t n, DevBuf &tmp, hipStream_t s);  // in place, n <= 2^30
 int zero_doubles(double *p, size_t n, hipStream_t s);
