@@ -88,6 +88,8 @@ def main():
                     help="skip the tomography and gradient workloads")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "bf16x6", "fp16x3"],
                     help="stage-2 precision of the --profile-steps passes")
+    ap.add_argument("--profile-combined", default=None, choices=["direct", "fft", "auto"],
+                    help="with --profile-steps: run the combined estimator (Delta_1 = 0.25') by this route")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design "
@@ -125,7 +127,12 @@ def main():
         pplan = plan if args.precision == "fp32" else t3.Plan(
             edges, wl.n_max, box_lo=(0, 0), box_size=box, precision=args.precision, timing=True)
         for i in range(args.profile_steps):
-            _, npairs = step(pplan)
+            if args.profile_combined:
+                ups, npairs = pplan.forward_grid(dc, int(round(0.25 / LATTICE_UNIT)), t3.grid_levels(edges, 0.25),
+                                                 method=args.profile_combined)
+                pplan.normalise_resum(ups, n_phi=wl.n_phi)
+            else:
+                _, npairs = step(pplan)
             torch.cuda.synchronize()
             log(f"[bench] profile step {i}: {npairs} pairs")
         return
@@ -208,7 +215,7 @@ def main():
         "split_precision": split,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": profiled_traffic(int(launches[1] // K)),
-                     "kernel": "k_scan (stage 1)",
+                     "kernel": "k_scan_lane + k_scan (stage 1: small bins one lane per centre, the rest one wavefront per centre)",
                      "flops_per_pair": flops_pair, "launches_per_step": int(launches[1] // K)},
     }
 
