@@ -198,9 +198,10 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
                int nb = -1, int n_lane = 0);
 // Leading bins of [b0, b0 + nb) whose expected neighbours per centre are at
 // most `most` (uniform density over the non-empty cells of sc); synchronises s.
-// Lane-per-centre sums stay in FP32: with up to ~90 terms (the Poisson tail
-// of 64 expected) the rounding of a sequential sum is below 3e-7 relative.
-constexpr double kLaneNeighbours = 64.0;
+// Lane-per-centre sums stay in FP32: a sequential sum of k random-phase
+// terms has relative rounding error about 2^-25 sqrt(k / 2), below 3e-7 for
+// the ~170 terms of the Poisson tail at 128 expected neighbours.
+constexpr double kLaneNeighbours = 128.0;
 int lane_bins(t3_plan *plan, const SortedCatalog &sc, int b0, int nb, double most, hipStream_t s, int *n_lane);
 int fill_int(int *p, int64_t n, int v, hipStream_t s);
 int exclusive_scan(int *data, int64_t n, DevBuf &tmp, hipStream_t s);  // in place, n <= 2^30
