@@ -86,6 +86,9 @@ extern "C" {
 #define T3_FLAG_EDGE_CORRECT 8u /* forward: N_n up to 2 n_max (stage 1 sums W_m to  */
                                 /* 2 n_max); t3_normalise_resum: edge-corrected    */
                                 /* Gamma_n (eq. GammaMultipolesWithEC).  No adjoint. */
+#define T3_FLAG_NO_LANE 16u /* stage 1: one wavefront per centre for every bin  */
+                            /* (default: bins with at most 128 expected         */
+                            /* neighbours per centre run one lane per centre)   */
 
 typedef struct {
     int32_t n_bins;        /* B >= 1                                         */
@@ -214,7 +217,9 @@ int t3_forward_sphere(t3_plan *plan, const t3_sphere_catalog *cat, const t3_patc
  * method: how a level's harmonics are computed: T3_GRID_DIRECT (pair sums
  *   over the non-empty pixels), T3_GRID_FFT (FFT convolution on a dense
  *   grid of the occupied pixels, sides products of 2, 3, 5 up to 8192; FP32
- *   transforms) or T3_GRID_AUTO (a cost model picks per level).
+ *   transforms, whose rounding scales with the grid's largest values) or
+ *   T3_GRID_AUTO (a cost model picks per level; levels whose heaviest
+ *   pixel exceeds 100 times the mean pixel weight keep the pair sums).
  * ups_out: t3_forward layout.  n_pairs: HOST, optional: galaxy pairs of the
  *   discrete bins plus pixel pairs of the levels summed pairwise (FFT
  *   levels add none).  Synchronises the stream (pixel counts and extents

@@ -477,12 +477,14 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
     if (lds > 64 * 1024)
         T3_HIP_CHECK(hipFuncSetAttribute((const void *)k_adj_coef,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int n_lane = 0;
+    T3_TRY(lane_bins(plan, sc, 0, B, kLaneNeighbours, s, &n_lane));
     for (int64_t c0 = 0; c0 < n; c0 += L.K) {
         const int nc = (int)((n - c0) < L.K ? (n - c0) : L.K);
         T3_TRY(timing_mark(plan, 1, true, s));
         const SortedCatalog *cl[1] = {&sc};
         T3_TRY(scan_chunk(plan, cl, nullptr, 1, plan->centres, c0, nc, L, plan->chunk.as<float>(), 0, nullptr,
-                          plan->scan_mode, s));
+                          plan->scan_mode, s, 0, B, n_lane));
         T3_TRY(timing_mark(plan, 1, false, s));
         T3_TRY(timing_mark(plan, 2, true, s));
         CoefArgs ca{};

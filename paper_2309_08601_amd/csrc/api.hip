@@ -158,8 +158,14 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
     T3_TRY(timing_mark(plan, 0, false, s));
     T3_TRY(check_flag(plan, s, n_z > 1 ? "t3_forward_tomo" : "t3_forward"));
     // leading bins with few neighbours per centre: one lane per centre
-    int n_lane = 0;
-    if (n_z == 1) T3_TRY(lane_bins(plan, plan->cats[0], 0, plan->B, kLaneNeighbours, s, &n_lane));
+    // (the densest catalog decides for every catalog of a tomographic call)
+    int n_lane = plan->B;
+    for (int z = 0; z < n_z; ++z) {
+        int k = 0;
+        T3_TRY(lane_bins(plan, plan->cats[z], 0, plan->B, kLaneNeighbours, s, &k));
+        if (plan->cats[z].n > 0) n_lane = std::min(n_lane, k);
+    }
+    if (n_lane == plan->B && n_all == 0) n_lane = 0;
 
     ChunkLayout L = layout_of(plan);
     if (plan->chunk_req <= 0) {
@@ -274,7 +280,7 @@ int t3_plan_create(const t3_params *p, t3_plan **out)
         if (p->n_max < 0 || p->n_max > 64) return fail(T3_ERANGE, "t3_plan_create: n_max must be in [0, 64]");
         if (p->precision < T3_PREC_FP32 || p->precision > T3_PREC_BF16X6)
             return fail(T3_EINVAL, "t3_plan_create: unknown precision");
-        if (p->flags & ~(T3_FLAG_KEEP_JK | T3_FLAG_TIMING | T3_FLAG_NO_GRAPH | T3_FLAG_EDGE_CORRECT))
+        if (p->flags & ~(T3_FLAG_KEEP_JK | T3_FLAG_TIMING | T3_FLAG_NO_GRAPH | T3_FLAG_EDGE_CORRECT | T3_FLAG_NO_LANE))
             return fail(T3_EINVAL, "t3_plan_create: unknown flag");
         const double unit = p->lattice_unit == 0.0 ? std::ldexp(1.0, -16) : p->lattice_unit;
         if (!(unit > 0.0) || !std::isfinite(unit)) return fail(T3_EINVAL, "t3_plan_create: bad lattice unit");
@@ -425,11 +431,13 @@ int t3_harmonics(t3_plan *plan, const t3_catalog *cat, const int32_t *centres, i
         if (plan->chunk_req <= 0 && (int64_t)L.K > n_centres)  // small requests, small buffers
             L.K = (int)std::max<int64_t>(256, (n_centres + 255) & ~(int64_t)255);
         T3_TRY(plan->chunk.reserve(sizeof(float) * L.floats()));
+        int n_lane = 0;
+        T3_TRY(lane_bins(plan, sc, 0, plan->B, kLaneNeighbours, s, &n_lane));
         for (int64_t c0 = 0; c0 < n_centres; c0 += L.K) {
             const int n = (int)((n_centres - c0) < L.K ? (n_centres - c0) : L.K);
             const SortedCatalog *cl[1] = {&sc};
             T3_TRY(scan_chunk(plan, cl, nullptr, 1, plan->centres, c0, n, L, plan->chunk.as<float>(), 0,
-                              plan->counter.as<unsigned long long>(), plan->scan_mode, s));
+                              plan->counter.as<unsigned long long>(), plan->scan_mode, s, 0, plan->B, n_lane));
             T3_TRY(harmonics_export(plan, plan->centres, L, plan->chunk.as<float>(), c0, n, G_out,
                                     W_out, D_out, s));
         }

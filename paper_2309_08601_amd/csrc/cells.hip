@@ -258,7 +258,7 @@ __global__ void k_count_nonempty(const int *__restrict__ start, int64_t ncells, 
 int lane_bins(t3_plan *plan, const SortedCatalog &sc, int b0, int nb, double most, hipStream_t s, int *n_lane)
 {
     *n_lane = 0;
-    if (sc.n == 0 || nb <= 0) return T3_OK;
+    if (sc.n == 0 || nb <= 0 || (plan->flags & T3_FLAG_NO_LANE)) return T3_OK;
     const int64_t nc = sc.grid.ncells();
     T3_TRY(plan->misc2.reserve(sizeof(unsigned) * 4));
     T3_HIP_CHECK(hipMemsetAsync(plan->misc2.ptr, 0, sizeof(unsigned), s));

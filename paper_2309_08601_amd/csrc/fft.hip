@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 namespace t3 {
 namespace {
@@ -312,28 +313,36 @@ __global__ void k_zero_c(float2 *p, size_t n)
     if (i < n) p[i] = make_float2(0.f, 0.f);
 }
 
-// occupied pixel range: min/max corner over the pixels (wave reduction, then
-// one atomic per wave)
-__global__ void k_bbox(const int32_t *__restrict__ px, const int32_t *__restrict__ py, int64_t n,
-                       int *__restrict__ box)
+// occupied pixel range (min/max corner) and the largest and total pixel
+// weight (wave reduction, then one atomic per wavefront; weights >= 0, so
+// their bit patterns order like the values)
+__global__ void k_bbox(const int32_t *__restrict__ px, const int32_t *__restrict__ py,
+                       const double *__restrict__ sum, int64_t n, int *__restrict__ box, float *__restrict__ wsum)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int x0 = 0x7fffffff, y0 = 0x7fffffff, x1 = (int)0x80000000, y1 = (int)0x80000000;
+    float w = 0.0f;
     if (i < n) {
         x0 = x1 = px[i];
         y0 = y1 = py[i];
+        w = fmaxf((float)sum[3 * i + 2], 0.0f);
     }
+    float wmax = w;
     for (int d = 32; d > 0; d >>= 1) {
         x0 = min(x0, __shfl_xor(x0, d, 64));
         y0 = min(y0, __shfl_xor(y0, d, 64));
         x1 = max(x1, __shfl_xor(x1, d, 64));
         y1 = max(y1, __shfl_xor(y1, d, 64));
+        wmax = fmaxf(wmax, __shfl_xor(wmax, d, 64));
+        w += __shfl_xor(w, d, 64);
     }
     if ((threadIdx.x & 63) == 0) {
         atomicMin(&box[0], x0);
         atomicMin(&box[1], y0);
         atomicMax(&box[2], x1);
         atomicMax(&box[3], y1);
+        atomicMax(&box[4], __float_as_int(wmax));
+        atomicAdd(wsum, w);
     }
 }
 
@@ -442,20 +451,29 @@ constexpr double kSpectraBytes = 24.0 * (1 << 30); // kernel spectra kept per le
 
 }  // namespace
 
-// Occupied pixel range of a level (corners px, py by pixel), read back to the host.
-int level_bbox(GridLevel &lv, const int32_t *px, const int32_t *py, hipStream_t s)
+// Occupied pixel range of a level (corners px, py by pixel) and the ratio of
+// its largest pixel weight to the mean, read back to the host.
+int level_bbox(GridLevel &lv, const int32_t *px, const int32_t *py, const double *sum, hipStream_t s)
 {
     lv.nx_occ = lv.ny_occ = 0;
+    lv.w_peak = 0.0;
     if (lv.n_pix == 0) return T3_OK;
-    T3_TRY(lv.fft_misc.reserve(sizeof(int) * 4));
-    const int init[4] = {0x7fffffff, 0x7fffffff, (int)0x80000000, (int)0x80000000};
+    T3_TRY(lv.fft_misc.reserve(sizeof(int) * 8));
+    const int init[6] = {0x7fffffff, 0x7fffffff, (int)0x80000000, (int)0x80000000, 0, 0};
     T3_HIP_CHECK(hipMemcpyAsync(lv.fft_misc.ptr, init, sizeof(init), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_bbox, dim3(nblk(lv.n_pix, 256)), dim3(256), 0, s, px, py, lv.n_pix, lv.fft_misc.as<int>());
+    hipLaunchKernelGGL(k_bbox, dim3(nblk(lv.n_pix, 256)), dim3(256), 0, s, px, py, sum, lv.n_pix,
+                       lv.fft_misc.as<int>(), reinterpret_cast<float *>(lv.fft_misc.as<int>() + 5));
     T3_HIP_CHECK(hipGetLastError());
-    T3_HIP_CHECK(hipMemcpyAsync(lv.box, lv.fft_misc.ptr, sizeof(lv.box), hipMemcpyDeviceToHost, s));
+    int h[6];
+    T3_HIP_CHECK(hipMemcpyAsync(h, lv.fft_misc.ptr, sizeof(h), hipMemcpyDeviceToHost, s));
     T3_HIP_CHECK(hipStreamSynchronize(s));
+    for (int k = 0; k < 4; ++k) lv.box[k] = h[k];
     lv.nx_occ = (int)(((int64_t)lv.box[2] - lv.box[0]) / lv.side) + 1;
     lv.ny_occ = (int)(((int64_t)lv.box[3] - lv.box[1]) / lv.side) + 1;
+    float wmax, wsum;
+    std::memcpy(&wmax, &h[4], sizeof(float));
+    std::memcpy(&wsum, &h[5], sizeof(float));
+    lv.w_peak = wsum > 0.0f ? (double)wmax * (double)lv.n_pix / (double)wsum : 0.0;
     return T3_OK;
 }
 

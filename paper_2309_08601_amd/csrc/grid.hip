@@ -64,6 +64,9 @@ namespace {
 
 inline unsigned blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// AUTO route: pixel weight peak-to-mean above which a level keeps the pair sums
+constexpr double kFftPeakRatio = 100.0;
+
 // 1 for non-empty cells, 0 for empty ones and for the extra entry [ncells]
 __global__ void k_pix_flags(const int *__restrict__ start, int64_t ncells, int *__restrict__ flags)
 {
@@ -235,7 +238,7 @@ int build_level(t3_plan *plan, GridLevel &lv, const t3_catalog &cat, int method,
     if (n_pix == 0) return T3_OK;
     // route: pair sums over the pixel catalog, or FFT convolution on the
     // dense grid of the occupied pixels (modelled cost decides for AUTO)
-    T3_TRY(level_bbox(lv, a.px, a.py, s));
+    T3_TRY(level_bbox(lv, a.px, a.py, a.sum, s));
     int m = method;
     if (m == T3_GRID_AUTO) {
         const double area = (double)lv.nx_occ * lv.ny_occ;  // pixels^2
@@ -245,6 +248,9 @@ int build_level(t3_plan *plan, GridLevel &lv, const t3_catalog &cat, int method,
         // measured stage-1 rate: about 7e12 pair-orders per second
         const double direct_ms = 1e3 * pairs * (3.0 * plan->n_max + 4.0) / 7.0e12;
         m = fft_cost_ms(plan, lv) < direct_ms ? T3_GRID_FFT : T3_GRID_DIRECT;
+        // FFT rounding scales with the field's largest values: a pixel far
+        // heavier than the mean (strong clustering) keeps the pair sums
+        if (lv.w_peak > kFftPeakRatio) m = T3_GRID_DIRECT;
     }
     lv.method = m;
     // the FFT route indexes planes by pixel (row-major over the box: rows of

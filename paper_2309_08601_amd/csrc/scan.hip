@@ -18,9 +18,13 @@
 // Arithmetic per neighbour: dx, dy are exact lattice integers, r^2 is exact
 // in FP64 and is compared with the same FP64 squared edges as everywhere
 // else, so bin membership is exact.  z is formed in FP64 (rsqrt seed + one
-// Newton step), anchors z^{8k} are FP64 and rounded once to FP32; between
-// anchors powers p_m = z^m advance by FP32 complex multiplication, so the
-// error of any p_m is a few FP32 ulp whatever m.  G_m and G_{-m} share p_m:
+// Newton step), anchors z^{4k} are FP64 and rounded once to FP32 (those at
+// multiples of 8 form the only dependency chain, each z^{8k+4} hangs off the
+// anchor below); between anchors powers p_m = z^m advance by FP32 complex
+// multiplication from the nearer anchor (at most two steps), so the error of
+// any p_m is a few FP32 ulp whatever m (with chains of up to 4 steps, small
+// tomographic samples reached the 1e-6 FP32 bar on single blocks).
+// G_m and G_{-m} share p_m:
 //     S1 += Re c Re p,  S2 += Im c Im p,  S3 += Re c Im p,  S4 += Im c Re p
 //     G_m = (S1 - S2, S3 + S4),   G_{-m} = (S1 + S2, S4 - S3)
 // which costs 4 FMAs for two orders.
@@ -30,7 +34,7 @@ namespace t3 {
 namespace {
 
 constexpr int kWaves = 4;       // wavefronts (centres) per workgroup
-constexpr int kAnchor = 8;      // FP64 anchor stride of the power recurrence
+constexpr int kAnchor = 8;      // FP64 anchor chain stride of the power recurrence
 constexpr int kMaxBins = 64;
 constexpr int kMaxZ = 8;        // neighbour catalogs per launch (tomographic bins)
 constexpr int kFlush = 64;      // batches of 64 neighbours per FP32 run before FP64 promotion
@@ -95,20 +99,8 @@ __device__ __forceinline__ void accumulate(float (&acc)[V], int dx, int dy, floa
         ai = fma(ar, z8i, ai * z8r);
         ar = tr;
     }
-    float pr = (float)ar, pi = (float)ai;
-#pragma unroll
-    for (int m = S::M0 + 1; m <= S::MTOP; ++m) {
-        if (m % kAnchor == 0) {
-            const double tr = fma(ar, z8r, -ai * z8i);
-            ai = fma(ar, z8i, ai * z8r);
-            ar = tr;
-            pr = (float)ar;
-            pi = (float)ai;
-        } else {
-            const float tr = fmaf(pr, fzr, -pi * fzi);
-            pi = fmaf(pr, fzi, pi * fzr);
-            pr = tr;
-        }
+    // the sums of one order m with its power (pr, pi)
+    auto add = [&](int m, float pr, float pi) {
         if (m >= GA && m <= GB) {
             const int k = 4 * (m - GA);
             acc[k + 0] = fmaf(cr, pr, acc[k + 0]);
@@ -121,6 +113,42 @@ __device__ __forceinline__ void accumulate(float (&acc)[V], int dx, int dy, floa
             acc[k + 0] = fmaf(wt, pr, acc[k + 0]);
             acc[k + 1] = fmaf(wt, pi, acc[k + 1]);
         }
+    };
+    // FP32 steps from a power (fr, fi) of order m0: forward up to order m0 + 2,
+    // or backward (z^-1 = conj z on the unit circle) down to order m0 - 1
+    auto up2 = [&](int m0, float fr, float fi) {
+#pragma unroll
+        for (int j = 1; j <= 2; ++j) {
+            if (m0 + j > S::MTOP) break;
+            const float tr = fmaf(fr, fzr, -fi * fzi);
+            fi = fmaf(fr, fzi, fi * fzr);
+            fr = tr;
+            add(m0 + j, fr, fi);
+        }
+    };
+    auto down1 = [&](int m0, float fr, float fi) {
+        if (m0 - 1 <= S::MTOP) add(m0 - 1, fmaf(fr, fzr, fi * fzi), fmaf(fi, fzr, -fr * fzi));
+    };
+    // Segments of 8 orders: the FP64 anchors a = z^{8k} form the only chain
+    // (one z^8 step per segment); z^{8k+4} = a z^4 is a second FP64 anchor of
+    // depth one; every other power is at most two FP32 multiplications from
+    // one of them (8k+1, 8k+2 forward from 8k; 8k+3 backward from 8k+4;
+    // 8k+5, 8k+6 forward from 8k+4; 8k+7 backward from 8k+8).
+#pragma unroll
+    for (int b0 = S::M0; b0 < S::MTOP; b0 += kAnchor) {
+        up2(b0, (float)ar, (float)ai);
+        if (b0 + 2 >= S::MTOP) break;
+        const double hr = fma(ar, z4r, -ai * z4i), hi = fma(ar, z4i, ai * z4r);
+        const float fhr = (float)hr, fhi = (float)hi;
+        down1(b0 + 4, fhr, fhi);
+        if (b0 + 4 <= S::MTOP) add(b0 + 4, fhr, fhi);
+        up2(b0 + 4, fhr, fhi);
+        if (b0 + 6 >= S::MTOP) break;
+        const double nr = fma(ar, z8r, -ai * z8i), ni = fma(ar, z8i, ai * z8r);
+        ar = nr;
+        ai = ni;
+        down1(b0 + 8, (float)ar, (float)ai);
+        if (b0 + 8 <= S::MTOP) add(b0 + 8, (float)ar, (float)ai);
     }
     if constexpr (EXTRA) {
         constexpr int k = 4 * S::NG + 2 * S::NW;
@@ -328,8 +356,8 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
 // kLaneList in-bin neighbours (indices in LDS), then the wavefront runs the
 // same per-pair arithmetic on the lists in lock-step (max count iterations)
 // and goes back to collecting until every lane has finished its annulus.
-// Sums stay in FP32 per lane (the host sends only bins whose expected
-// neighbour count keeps that within the FP32 error of the wavefront path).
+// Sums stay in FP32 per lane (sequential rounding of the ~170 terms of the
+// Poisson tail at 128 expected neighbours is below 3e-7 relative).
 constexpr int kLaneList = 32;
 constexpr int kLaneBlock = 128;
 
@@ -402,11 +430,11 @@ __global__ __launch_bounds__(kLaneBlock) void k_scan_lane(ScanArgs a)
                 }
             }
             pairs += (unsigned long long)cnt;
-            // process the lists in lock-step
+            // process the lists in lock-step; the next neighbour's loads are
+            // issued before the current one's arithmetic
             int most = cnt;
 #pragma unroll
             for (int d = 32; d > 0; d >>= 1) most = max(most, __shfl_xor(most, d, 64));
-            // the next neighbour's loads are issued before the current one's arithmetic
             int2 pc = make_int2(cp.x, cp.y);
             float4 cc = make_float4(0.f, 0.f, 0.f, 0.f);
             if (cnt > 0) {
@@ -426,8 +454,7 @@ __global__ __launch_bounds__(kLaneBlock) void k_scan_lane(ScanArgs a)
                 pc = pn;
                 cc = cn;
             }
-            const bool all_done = __all(done);
-            if (all_done) break;
+            if (__all(done)) break;
         }
         if (active) {
             // S -> G conversion (as in the wavefront reduction), then every slot to its plane
@@ -588,7 +615,7 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
     if (n_c <= 0) return T3_OK;
     if (nb < 0) nb = L.B;
     if (b0 < 0 || nb < 1 || nb > L.B || b0 + nb > plan->B) return fail(T3_ERANGE, "scan: bad bin range");
-    if (n_lane < 0 || n_lane > nb || (n_lane > 0 && n_z != 1)) return fail(T3_ERANGE, "scan: bad lane-bin count");
+    if (n_lane < 0 || n_lane > nb) return fail(T3_ERANGE, "scan: bad lane-bin count");
     if (n_z < 1 || n_z > kMaxZ) return fail(T3_ERANGE, "scan: bad catalog count");
     if (plan->scan_var < 0) T3_TRY(scan_prepare(plan));
     const Variant &var = variants()[plan->scan_var];
@@ -609,19 +636,25 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
     a.n_max = L.n_max;
     a.K = L.K;
     const int npass = var.npass + (plan->w_max > var.cap ? 1 : 0);
-    // bins [b0, b0 + n_lane): one lane per centre
+    // bins [b0, b0 + n_lane): one lane per centre, one launch per catalog
     if (n_lane > 0) {
         ScanArgs al = a;
         al.n_bins = n_lane;
         al.b_out0 = 0;
+        al.n_z = 1;
         for (int b = 0; b <= n_lane; ++b) al.e2[b] = plan->e2[b0 + b];
         for (int p = 0; p < npass; ++p) {
             const PassDesc &pd = p < var.npass ? var.pass[p] : var.wext;
             al.dest = plan->dest.as<short>() + plan->scan_dest_off[p];
             al.npairs = p == 0 ? npairs : nullptr;
-            hipLaunchKernelGGL(pd.kernel_lane, dim3((unsigned)((n_c + kLaneBlock - 1) / kLaneBlock)),
-                               dim3(kLaneBlock), 0, s, al);
-            T3_HIP_CHECK(hipGetLastError());
+            for (int z = 0; z < n_z; ++z) {
+                ScanArgs a1 = al;
+                a1.sw[0] = a.sw[z];
+                a1.out[0] = a.out[z];
+                hipLaunchKernelGGL(pd.kernel_lane, dim3((unsigned)((n_c + kLaneBlock - 1) / kLaneBlock)),
+                                   dim3(kLaneBlock), 0, s, a1);
+                T3_HIP_CHECK(hipGetLastError());
+            }
         }
     }
     if (n_lane == nb) return T3_OK;

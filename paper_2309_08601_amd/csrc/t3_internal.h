@@ -120,6 +120,7 @@ struct GridLevel {
     ChunkLayout L;
     int box[4] = {0, 0, 0, 0};  // occupied corners: x min, y min, x max, y max
     int nx_occ = 0, ny_occ = 0; // occupied extent, pixels
+    double w_peak = 0;          // largest pixel weight / mean pixel weight
     int method = 0;             // route taken: T3_GRID_DIRECT or T3_GRID_FFT
     DevBuf fft_misc, fft_buf;   // FFT route: bounding box, grids and tables
     DevBuf fft_spec;            // FFT route: kernel spectra of every (bin, order)
@@ -224,7 +225,7 @@ int sphere_patch(t3_plan *plan, const t3_sphere_catalog &cat, const t3_patch &p,
 int add_doubles(double *dst, const double *src, size_t n, hipStream_t s);
 int forward_grid(t3_plan *plan, const t3_catalog &cat, int64_t delta, const int32_t *levels, int method,
                  double *ups_out, int64_t *n_pairs, hipStream_t s);
-int level_bbox(GridLevel &lv, const int32_t *px, const int32_t *py, hipStream_t s);
+int level_bbox(GridLevel &lv, const int32_t *px, const int32_t *py, const double *sum, hipStream_t s);
 double fft_cost_ms(const t3_plan *plan, const GridLevel &lv);
 int fft_level(t3_plan *plan, GridLevel &lv, hipStream_t s);
 int harmonics_export(t3_plan *plan, const CentreSet &cs, const ChunkLayout &L, const float *planes,

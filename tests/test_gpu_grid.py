@@ -130,3 +130,38 @@ def test_fft_kernel_spectra_kept_between_calls(t3):
     assert torch.equal(a, b)
     other = random_catalog(3000, 35.0, seed=32)
     _compare(t3, plan, other, edges, 6, delta, levels, False, box_lo, "new footprint", "fft")
+
+
+@pytest.mark.parametrize("method", ["direct", "fft", "auto"])
+def test_combined_edge_cases(t3, method):
+    """Empty catalog and a single galaxy: zero multipoles, zero pairs; every
+    galaxy inside one coarse pixel (that level sees no pixel pairs); a thin
+    strip of galaxies (occupied extent of one pixel along y: the FFT grid's
+    kernel reach clamps to the extent)."""
+    from paper_2309_08601_amd.synth import Catalog
+    edges = np.geomspace(1.0, 14.0, 7)
+    levels = [0, 0, 1, 1, 2, 3]
+    box_lo = (0, 0)
+    delta = int(0.25 / LATTICE_UNIT)
+    plan = t3.Plan(edges, 4, box_lo=box_lo, box_size=1 << 23)
+    empty = Catalog(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32),
+                    np.zeros(0, np.float32), np.zeros(0, np.float32))
+    for cat in (empty, random_catalog(1, 10.0, seed=4)):
+        ups, npairs = plan.forward_grid(t3.DeviceCatalog.from_catalog(cat), delta, levels, method=method)
+        assert npairs == 0 and float(torch.linalg.vector_norm(ups)) == 0.0
+    rng = np.random.default_rng(9)
+    # 300 galaxies inside one 1' pixel (level 3 = 0.25' * 4), plus 500 spread out
+    clump = random_catalog(300, 0.9, seed=10)
+    spread = random_catalog(500, 40.0, seed=11)
+    off = int(20.05 / LATTICE_UNIT)
+    cat = Catalog(np.concatenate([clump.x + off, spread.x]).astype(np.int32),
+                  np.concatenate([clump.y + off, spread.y]).astype(np.int32),
+                  np.concatenate([clump.g1, spread.g1]), np.concatenate([clump.g2, spread.g2]),
+                  np.concatenate([clump.w, spread.w]))
+    _compare(t3, plan, cat, edges, 4, delta, levels, False, box_lo, "clump", method)
+    # a strip 0.2' high: every grid level has a one-pixel-high occupied extent
+    x = rng.integers(0, int(40.0 / LATTICE_UNIT), 800).astype(np.int32)
+    y = (int(10.0 / LATTICE_UNIT) + rng.integers(0, int(0.2 / LATTICE_UNIT), 800)).astype(np.int32)
+    strip = Catalog(x, y, rng.normal(0, 0.3, 800).astype(np.float32), rng.normal(0, 0.3, 800).astype(np.float32),
+                    rng.uniform(0.5, 1.5, 800).astype(np.float32))
+    _compare(t3, plan, strip, edges, 4, delta, levels, False, box_lo, "strip", method)

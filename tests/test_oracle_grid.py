@@ -141,3 +141,15 @@ def test_grid_approximates_discrete_with_theta_above_20_delta():
     print("grid vs discrete Gamma_n (Theta/Delta = 24, 12, 6):", errs, "N_n:", nerr)
     assert errs[0] < 1.5e-2 and nerr[0] < 1.5e-2
     assert errs[0] < errs[1] < errs[2]
+
+
+def test_binding_level_rule_matches_oracle():
+    """The binding's default level rule (host logic) and the oracle's, written
+    separately from the same statement (coarsest grid with lower edge >=
+    20 Delta_l, discrete below theta_disc), agree on the workloads' bins."""
+    from paper_2309_08601_amd import t3
+    from paper_2309_08601_amd.synth import WORKLOADS
+    for wl in WORKLOADS.values():
+        e = wl.edges()
+        for d, td in ((0.25, 0.0), (0.5, 0.0), (0.25, 8.0), (0.1, 3.0)):
+            assert t3.grid_levels(e, d, theta_disc=td) == og.default_levels(e, d, theta_disc=td)
