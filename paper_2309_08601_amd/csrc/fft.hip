@@ -314,11 +314,16 @@ __global__ void k_zero_c(float2 *p, size_t n)
 }
 
 // occupied pixel range (min/max corner) and the largest and total pixel
-// weight (wave reduction, then one atomic per wavefront; weights >= 0, so
-// their bit patterns order like the values)
-__global__ void k_bbox(const int32_t *__restrict__ px, const int32_t *__restrict__ py,
-                       const double *__restrict__ sum, int64_t n, int *__restrict__ box, float *__restrict__ wsum)
+// weight: wave reduction, then a workgroup reduction in LDS, then one set of
+// atomics per workgroup (weights >= 0, so their bit patterns order like the
+// values)
+constexpr int kBoxBlock = 1024;
+__global__ __launch_bounds__(kBoxBlock) void k_bbox(const int32_t *__restrict__ px, const int32_t *__restrict__ py,
+                                                    const double *__restrict__ sum, int64_t n, int *__restrict__ box,
+                                                    float *__restrict__ wsum)
 {
+    __shared__ int s_i[kBoxBlock / 64][5];
+    __shared__ float s_w[kBoxBlock / 64];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int x0 = 0x7fffffff, y0 = 0x7fffffff, x1 = (int)0x80000000, y1 = (int)0x80000000;
     float w = 0.0f;
@@ -336,13 +341,31 @@ __global__ void k_bbox(const int32_t *__restrict__ px, const int32_t *__restrict
         wmax = fmaxf(wmax, __shfl_xor(wmax, d, 64));
         w += __shfl_xor(w, d, 64);
     }
+    const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        atomicMin(&box[0], x0);
-        atomicMin(&box[1], y0);
-        atomicMax(&box[2], x1);
-        atomicMax(&box[3], y1);
-        atomicMax(&box[4], __float_as_int(wmax));
-        atomicAdd(wsum, w);
+        s_i[wv][0] = x0;
+        s_i[wv][1] = y0;
+        s_i[wv][2] = x1;
+        s_i[wv][3] = y1;
+        s_i[wv][4] = __float_as_int(wmax);
+        s_w[wv] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kBoxBlock / 64; ++k) {
+            s_i[0][0] = min(s_i[0][0], s_i[k][0]);
+            s_i[0][1] = min(s_i[0][1], s_i[k][1]);
+            s_i[0][2] = max(s_i[0][2], s_i[k][2]);
+            s_i[0][3] = max(s_i[0][3], s_i[k][3]);
+            s_i[0][4] = max(s_i[0][4], s_i[k][4]);
+            s_w[0] += s_w[k];
+        }
+        atomicMin(&box[0], s_i[0][0]);
+        atomicMin(&box[1], s_i[0][1]);
+        atomicMax(&box[2], s_i[0][2]);
+        atomicMax(&box[3], s_i[0][3]);
+        atomicMax(&box[4], s_i[0][4]);
+        atomicAdd(wsum, s_w[0]);
     }
 }
 
@@ -461,7 +484,7 @@ int level_bbox(GridLevel &lv, const int32_t *px, const int32_t *py, const double
     T3_TRY(lv.fft_misc.reserve(sizeof(int) * 8));
     const int init[6] = {0x7fffffff, 0x7fffffff, (int)0x80000000, (int)0x80000000, 0, 0};
     T3_HIP_CHECK(hipMemcpyAsync(lv.fft_misc.ptr, init, sizeof(init), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_bbox, dim3(nblk(lv.n_pix, 256)), dim3(256), 0, s, px, py, sum, lv.n_pix,
+    hipLaunchKernelGGL(k_bbox, dim3(nblk(lv.n_pix, kBoxBlock)), dim3(kBoxBlock), 0, s, px, py, sum, lv.n_pix,
                        lv.fft_misc.as<int>(), reinterpret_cast<float *>(lv.fft_misc.as<int>() + 5));
     T3_HIP_CHECK(hipGetLastError());
     int h[6];
