@@ -132,10 +132,10 @@ template <> struct Dft<8> {
 // Every thread first loads all of its butterflies, then the workgroup
 // synchronises and stores (one buffer serves as source and destination).
 // j / ns is a multiply-high by ceil(2^32 / ns): exact for j, ns <= 2^13.
-template <int R>
+template <int R, int NMAX>
 __device__ __forceinline__ void stage(float2 *buf, const RowPlan &p, int ns, unsigned magic, float s)
 {
-    constexpr int MB = (kFftMax / R + kFftThreads - 1) / kFftThreads;
+    constexpr int MB = (NMAX / R + kFftThreads - 1) / kFftThreads;  // butterflies per thread
     const int nb = p.n / R;
     float2 v[MB][R];
 #pragma unroll
@@ -171,6 +171,10 @@ __device__ __forceinline__ void stage(float2 *buf, const RowPlan &p, int ns, uns
     __syncthreads();
 }
 
+// NMAX: largest row length of the instantiation (sizes the per-thread
+// butterfly registers: rows up to 1024 or 4096 points keep fewer registers
+// live than 8192-point rows, so more wavefronts fit per SIMD)
+template <int NMAX>
 __device__ void fft_lds(float2 *buf, const RowPlan &p, float s)
 {
     int ns = 1;
@@ -178,11 +182,11 @@ __device__ void fft_lds(float2 *buf, const RowPlan &p, float s)
         const int R = p.radix[st];
         const unsigned mg = p.magic[st];
         switch (R) {
-            case 2: stage<2>(buf, p, ns, mg, s); break;
-            case 3: stage<3>(buf, p, ns, mg, s); break;
-            case 4: stage<4>(buf, p, ns, mg, s); break;
-            case 5: stage<5>(buf, p, ns, mg, s); break;
-            default: stage<8>(buf, p, ns, mg, s); break;
+            case 2: stage<2, NMAX>(buf, p, ns, mg, s); break;
+            case 3: stage<3, NMAX>(buf, p, ns, mg, s); break;
+            case 4: stage<4, NMAX>(buf, p, ns, mg, s); break;
+            case 5: stage<5, NMAX>(buf, p, ns, mg, s); break;
+            default: stage<8, NMAX>(buf, p, ns, mg, s); break;
         }
         ns *= R;
     }
@@ -272,7 +276,7 @@ struct StorePlanes {
 // One workgroup per (row, batch entry): load, transform in LDS, store.
 // Blocks x >= row_gap skip gap_len rows (kernel generation touches only the
 // rows that can be non-zero).
-template <class Load, class Store>
+template <int NMAX, class Load, class Store>
 __global__ __launch_bounds__(kFftThreads) void k_fft_rows(RowPlan p, float s, Load ld, Store st, int row_gap,
                                                           int gap_len)
 {
@@ -282,7 +286,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows(RowPlan p, float s, Lo
     const int t = (int)blockIdx.y;
     for (int i = threadIdx.x; i < p.n; i += kFftThreads) lds[i] = ld(t, row, i, p.n);
     __syncthreads();
-    fft_lds(lds, p, s);
+    fft_lds<NMAX>(lds, p, s);
     for (int i = threadIdx.x; i < p.n; i += kFftThreads) st(t, row, i, p.n, lds[i]);
 }
 
@@ -431,8 +435,14 @@ int rows_launch(const RowPlan &p, float s, Load ld, Store st, int n_rows, int ba
                 int gap_len = 0)
 {
     if (n_rows <= 0 || batch <= 0) return T3_OK;
-    hipLaunchKernelGGL((k_fft_rows<Load, Store>), dim3((unsigned)n_rows, (unsigned)batch), dim3(kFftThreads),
-                       sizeof(float2) * p.n, q, p, s, ld, st, row_gap, gap_len);
+    const dim3 grid((unsigned)n_rows, (unsigned)batch), block(kFftThreads);
+    const size_t lds = sizeof(float2) * p.n;
+    if (p.n <= 1024)
+        hipLaunchKernelGGL((k_fft_rows<1024, Load, Store>), grid, block, lds, q, p, s, ld, st, row_gap, gap_len);
+    else if (p.n <= 4096)
+        hipLaunchKernelGGL((k_fft_rows<4096, Load, Store>), grid, block, lds, q, p, s, ld, st, row_gap, gap_len);
+    else
+        hipLaunchKernelGGL((k_fft_rows<kFftMax, Load, Store>), grid, block, lds, q, p, s, ld, st, row_gap, gap_len);
     T3_HIP_CHECK(hipGetLastError());
     return T3_OK;
 }
