@@ -374,7 +374,8 @@ __global__ __launch_bounds__(kLaneBlock) void k_scan_lane(ScanArgs a)
     const CellGrid &g = sw.g;
     float *out = a.out[0];
     unsigned long long pairs = 0;
-    for (int b = 0; b < a.n_bins; ++b) {
+    {
+        const int b = blockIdx.y;  // one bin per grid row: short, evenly spread wavefronts
         const double e2lo = a.e2[b], e2hi = a.e2[b + 1];
         float acc[S::V];
 #pragma unroll
@@ -651,7 +652,8 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
                 ScanArgs a1 = al;
                 a1.sw[0] = a.sw[z];
                 a1.out[0] = a.out[z];
-                hipLaunchKernelGGL(pd.kernel_lane, dim3((unsigned)((n_c + kLaneBlock - 1) / kLaneBlock)),
+                hipLaunchKernelGGL(pd.kernel_lane,
+                                   dim3((unsigned)((n_c + kLaneBlock - 1) / kLaneBlock), (unsigned)n_lane),
                                    dim3(kLaneBlock), 0, s, a1);
                 T3_HIP_CHECK(hipGetLastError());
             }
