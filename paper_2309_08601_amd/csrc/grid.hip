@@ -245,8 +245,10 @@ int build_level(t3_plan *plan, GridLevel &lv, const t3_catalog &cat, int method,
         const double e_lo = std::sqrt(plan->e2[lv.b_lo]) / (double)lv.side;
         const double e_hi = std::sqrt(plan->e2[lv.b_lo + lv.nb]) / (double)lv.side;
         const double pairs = (double)n_pix * (double)n_pix / area * M_PI * (e_hi * e_hi - e_lo * e_lo);
-        // measured stage-1 rate: about 7e12 pair-orders per second
-        const double direct_ms = 1e3 * pairs * (3.0 * plan->n_max + 4.0) / 7.0e12;
+        // measured stage 1: about 7e12 pair-orders per second plus about
+        // 7 ns per (centre, bin) of fixed cost (batch, reduction, row set-up)
+        const double direct_ms =
+            1e3 * pairs * (3.0 * plan->n_max + 4.0) / 7.0e12 + 7e-6 * (double)n_pix * lv.nb;
         m = fft_cost_ms(plan, lv) < direct_ms ? T3_GRID_FFT : T3_GRID_DIRECT;
         // FFT rounding scales with the field's largest values: a pixel far
         // heavier than the mean (strong clustering) keeps the pair sums
