@@ -160,13 +160,14 @@ def check_levels(levels: Sequence[int], n_bins: int):
 
 
 def multipoles_combined(cat, edges: Sequence[float], n_max: int, delta: int, levels: Sequence[int],
-                        box_lo=(0, 0), w_max=None):
+                        box_lo=(0, 0), w_max=None, diag: bool = True):
     """Combined discrete / multi-resolution grid multipoles of every block.
 
     delta: Delta_1 in lattice steps; levels[b]: 0 discrete, l >= 1 grid of
     side delta 2^(l-1).  Returns ups[4, 2 n_max + 1, B, B], N[2 w_max + 1,
     B, B] (index n + n_max, n + w_max), npairs (galaxy pairs of the
     discrete bins plus pixel pairs of the grid bins) and the pixel catalogs.
+    diag=False keeps the degenerate pairs (the literal sums).
     """
     edges = np.asarray(edges, np.float64)
     B = edges.size - 1
@@ -191,7 +192,7 @@ def multipoles_combined(cat, edges: Sequence[float], n_max: int, delta: int, lev
         npairs += int(h["npairs"].sum())
         units[L] = (u, c, w, h, bins)
         # blocks inside the level: the discrete (L = 0) or grid estimator
-        uu, nn = mp.upsilon_from_harmonics(c, w, h, h, n_max, diag=True)
+        uu, nn = mp.upsilon_from_harmonics(c, w, h, h, n_max, diag=diag)
         sl = slice(bins[0], bins[-1] + 1)
         ups[:, :, sl, sl] = uu
         N[:, sl, sl] = nn

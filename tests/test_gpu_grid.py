@@ -165,3 +165,44 @@ def test_combined_edge_cases(t3, method):
     strip = Catalog(x, y, rng.normal(0, 0.3, 800).astype(np.float32), rng.normal(0, 0.3, 800).astype(np.float32),
                     rng.uniform(0.5, 1.5, 800).astype(np.float32))
     _compare(t3, plan, strip, edges, 4, delta, levels, False, box_lo, "strip", method)
+
+
+@pytest.mark.parametrize("method", ["direct", "fft"])
+@pytest.mark.parametrize("precision,tol", [("bf16x6", 1e-6), ("fp16x3", 1e-5), ("bf16x3", 1e-5)])
+def test_combined_split_precision(t3, method, precision, tol):
+    """The combined estimator through the split-precision contractions: the
+    grid bins' planes enter stage 2 like any other (N_n stays FP32)."""
+    from oracle import grid as og
+    cat = random_catalog(4000, 50.0, seed=1301)
+    edges = np.geomspace(1.0, 14.0, 7)
+    levels = [0, 0, 1, 1, 2, 3]
+    delta = int(0.25 / LATTICE_UNIT)
+    plan = t3.Plan(edges, 6, box_lo=(0, 0), box_size=1 << 23, precision=precision)
+    ups, _ = plan.forward_grid(t3.DeviceCatalog.from_catalog(cat), delta, levels, method=method)
+    o = og.multipoles_combined(cat, edges, 6, delta, levels)
+    ref = _pack(o["ups"], o["N"], 6, 6)
+    got = ups.cpu().numpy().reshape(ref.shape)
+    e = rel_fro(got[:28], ref[:28]).max()
+    print(f"combined {precision} ({method}): Upsilon {e:.2e}", flush=True)
+    assert e <= tol
+
+
+def test_combined_keep_jk(t3):
+    """T3_FLAG_KEEP_JK: the literal sums, degenerate pairs of one neighbour
+    galaxy (discrete bins) or one neighbour pixel (grid bins) included."""
+    from oracle import grid as og
+    cat = random_catalog(3000, 40.0, seed=1302)
+    edges = np.geomspace(1.0, 12.0, 6)
+    levels = [0, 1, 1, 2, 2]
+    delta = int(0.5 / LATTICE_UNIT)
+    plan = t3.Plan(edges, 5, box_lo=(0, 0), box_size=1 << 23, keep_jk=True)
+    for method in ("direct", "fft"):
+        ups, _ = plan.forward_grid(t3.DeviceCatalog.from_catalog(cat), delta, levels, method=method)
+        o = og.multipoles_combined(cat, edges, 5, delta, levels, diag=False)
+        ref = _pack(o["ups"], o["N"], 5, 5)
+        got = ups.cpu().numpy().reshape(ref.shape)
+        e = rel_fro(got[:24], ref[:24]).max()
+        n0 = np.linalg.norm(ref[24])
+        en = max(np.linalg.norm(got[24 + k] - ref[24 + k]) / n0 for k in range(6))
+        print(f"keep_jk ({method}): Upsilon {e:.2e}, N_n/N_0 {en:.2e}", flush=True)
+        assert e <= FP32_TOL and en <= FP32_TOL
