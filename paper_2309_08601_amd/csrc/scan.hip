@@ -27,7 +27,9 @@
 // G_m and G_{-m} share p_m:
 //     S1 += Re c Re p,  S2 += Im c Im p,  S3 += Re c Im p,  S4 += Im c Re p
 //     G_m = (S1 - S2, S3 + S4),   G_{-m} = (S1 + S2, S4 - S3)
-// which costs 4 FMAs for two orders.
+// which costs 4 FMAs for two orders.  The conversion is linear, so it is
+// applied to the FP64 wave totals when each (S1, S2) and (S3, S4) pair ends
+// on one lane of the reduce-scatter, else to the FP32 lane partials first.
 #include "sweep.h"
 
 namespace t3 {
@@ -217,10 +219,26 @@ __device__ __forceinline__ void dpp_step(float (&v)[N], bool hi)
     }
 }
 
-// Wave reduction of the per-lane accumulators: S -> G conversion, then the
-// 6-step reduce-scatter above, after which lane l holds the wave totals of
-// slots [P l, P l + P).  These are added to the lane's FP64 partials and the
-// FP32 accumulators restart from zero.
+// Output order of the four slots of an order pair m: Re G_m, Re G_-m, Im G_m,
+// Im G_-m (from S1 - S2, S1 + S2, S3 + S4, S4 - S3).
+__device__ __forceinline__ void s_to_g(float &s1, float &s2, float &s3, float &s4)
+{
+    const float a = s1, b = s2, c = s3, d = s4;
+    s1 = a - b;
+    s2 = a + b;
+    s3 = c + d;
+    s4 = d - c;
+}
+
+// With an even slot count per lane, each (S1, S2) and (S3, S4) pair of the
+// reduce-scatter ends on one lane and the conversion waits for the totals.
+template <int GA, int GB, int WA, int WB, bool EXTRA>
+constexpr bool kConvertAfter = PassShape<GA, GB, WA, WB, EXTRA>::P % 2 == 0;
+
+// Wave reduction of the per-lane accumulators: S -> G conversion unless it
+// waits for the totals, then the 6-step reduce-scatter above, after which
+// lane l holds the wave totals of slots [P l, P l + P).  These are added to
+// the lane's FP64 partials and the FP32 accumulators restart from zero.
 template <int GA, int GB, int WA, int WB, bool EXTRA, int V, int P>
 __device__ __forceinline__ void flush(float (&acc)[V], double (&accd)[P], int lane)
 {
@@ -228,15 +246,11 @@ __device__ __forceinline__ void flush(float (&acc)[V], double (&accd)[P], int la
     constexpr int VP = S::VP;
     float v[VP];
 #pragma unroll
-    for (int k = 0; k < S::NG; ++k) {
-        const float s1 = acc[4 * k], s2 = acc[4 * k + 1], s3 = acc[4 * k + 2], s4 = acc[4 * k + 3];
-        v[4 * k + 0] = s1 - s2;  // Re G_m
-        v[4 * k + 1] = s3 + s4;  // Im G_m
-        v[4 * k + 2] = s1 + s2;  // Re G_-m
-        v[4 * k + 3] = s4 - s3;  // Im G_-m
-    }
+    for (int k = 0; k < S::V; ++k) v[k] = acc[k];
+    if constexpr (!kConvertAfter<GA, GB, WA, WB, EXTRA>) {
 #pragma unroll
-    for (int k = 4 * S::NG; k < S::V; ++k) v[k] = acc[k];
+        for (int k = 0; k < S::NG; ++k) s_to_g(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    }
 #pragma unroll
     for (int k = S::V; k < VP; ++k) v[k] = 0.0f;
 #pragma unroll
@@ -281,7 +295,20 @@ __device__ __forceinline__ unsigned long long scan_task(const ScanArgs &a, int z
                     batches = 0;
                 }
             });
-        flush<GA, GB, WA, WB, EXTRA>(acc, accd, lane);
+        if (batches > 0) flush<GA, GB, WA, WB, EXTRA>(acc, accd, lane);
+        if constexpr (kConvertAfter<GA, GB, WA, WB, EXTRA>) {
+            // slot pairs (2j, 2j + 1) of an order pair are (S1, S2) or (S3, S4)
+#pragma unroll
+            for (int j = 0; j < S::P / 2; ++j) {
+                const int slot = S::P * lane + 2 * j;
+                if (slot < 4 * S::NG) {
+                    const double x = accd[2 * j], y = accd[2 * j + 1];
+                    const bool re = (slot & 2) == 0;
+                    accd[2 * j] = re ? x - y : x + y;
+                    accd[2 * j + 1] = re ? x + y : y - x;
+                }
+            }
+        }
         // lane holds slots [P*lane, P*lane + P)
 #pragma unroll
         for (int k = 0; k < S::P; ++k) {
@@ -458,15 +485,9 @@ __global__ __launch_bounds__(kLaneBlock) void k_scan_lane(ScanArgs a)
             if (__all(done)) break;
         }
         if (active) {
-            // S -> G conversion (as in the wavefront reduction), then every slot to its plane
+            // S -> G conversion (slot order as in the wavefront reduction), then every slot to its plane
 #pragma unroll
-            for (int k = 0; k < S::NG; ++k) {
-                const float s1 = acc[4 * k], s2 = acc[4 * k + 1], s3 = acc[4 * k + 2], s4 = acc[4 * k + 3];
-                acc[4 * k + 0] = s1 - s2;
-                acc[4 * k + 1] = s3 + s4;
-                acc[4 * k + 2] = s1 + s2;
-                acc[4 * k + 3] = s4 - s3;
-            }
+            for (int k = 0; k < S::NG; ++k) s_to_g(acc[4 * k], acc[4 * k + 1], acc[4 * k + 2], acc[4 * k + 3]);
 #pragma unroll
             for (int k = 0; k < S::V; ++k) {
                 const int pl = a.dest[k];
@@ -546,12 +567,13 @@ std::vector<short> dest_table(const PassDesc &p, const ChunkLayout &L)
     const int nm = L.n_max;
     for (int k = 0; k < NG; ++k) {
         const int m = p.ga + k;
+        // slot order Re G_m, Re G_-m, Im G_m, Im G_-m
         if (m <= nm - 1) {
             d[4 * k + 0] = (short)L.plane_G(m, 0);
-            d[4 * k + 1] = (short)L.plane_G(m, 1);
+            d[4 * k + 2] = (short)L.plane_G(m, 1);
         }
         if (m <= nm + 3) {
-            d[4 * k + 2] = (short)L.plane_G(-m, 0);
+            d[4 * k + 1] = (short)L.plane_G(-m, 0);
             d[4 * k + 3] = (short)L.plane_G(-m, 1);
         }
     }
