@@ -235,16 +235,43 @@ def main():
         tc = time.perf_counter() - tc
         n_s = int(np.clip(64 * args.cpu_seconds / max(tc, 1e-3), 64, 20000))
         idx = centre_sample(cat.n, n_s, seed=8)
-        tc = time.perf_counter()
-        o = mp.multipoles(cat, edges, nm, centres=idx)
-        tc = time.perf_counter() - tc
+        tm = {}
+        o = mp.multipoles(cat, edges, nm, centres=idx, timings=tm)
+        tc = tm["harmonics"] + tm["contraction"]
         cores = mp.threads()
-        out["cpu_baseline"] = {"value": o["npairs"] / tc, "unit": "galaxy-pairs/s", "cores": cores,
-                               "kind": "oracle",
-                               "sample": f"{n_s} random centres of the {cat.n}-galaxy catalog against all "
-                                         f"neighbours ({o['npairs']} pairs, {tc:.1f} s, FP64 C/OpenMP + "
-                                         f"numpy contraction)"}
-        log(f"[bench] oracle: {n_s} centres, {o['npairs']} pairs in {tc:.1f} s on {cores} threads")
+        # one thread, harmonics only (the pair loop), on a sample of about 3 s
+        n_1 = int(np.clip(3.0 * n_s / max(tm["harmonics"] * cores, 1e-3), 8, n_s))
+        idx_1 = centre_sample(cat.n, n_1, seed=9)
+        mp.set_threads(1)
+        try:
+            tm_1 = {}
+            o_1 = mp.multipoles(cat, edges, nm, centres=idx_1, timings=tm_1)
+        finally:
+            mp.set_threads(cores)
+        # complex multiply-adds of the oracle's contraction: every |n| <= n_max
+        # (4 components) and every |n| <= n_max of N, B x B per centre
+        macs = (5 * (2 * nm + 1)) * len(edges[:-1]) ** 2 * n_s
+        pairs_s = o["npairs"] / tc
+        out["cpu_baseline"] = {
+            "value": pairs_s, "unit": "galaxy-pairs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_s} random centres of the {cat.n}-galaxy catalog against all "
+                      f"neighbours ({o['npairs']} pairs, {tc:.1f} s, FP64 C/OpenMP + numpy contraction)",
+            "cpu_model": cpu_model(),
+            "per_core": pairs_s / cores,
+            "stage_seconds": {"harmonics": tm["harmonics"], "contraction": tm["contraction"]},
+            "harmonics_pairs_per_s": o["npairs"] / tm["harmonics"],
+            "contraction_complex_mac_per_s": macs / tm["contraction"],
+            "one_thread": {"value": o_1["npairs"] / tm_1["harmonics"], "unit": "galaxy-pairs/s",
+                           "sample": f"{n_1} random centres, harmonics only ({o_1['npairs']} pairs, "
+                                     f"{tm_1['harmonics']:.1f} s)"},
+            "extrapolated_full_step_s": pairs_step / (o["npairs"] / tm["harmonics"])
+                                        + tm["contraction"] * cat.n / n_s,
+            "gpu_speedup_equal_work": value / pairs_s,
+        }
+        log(f"[bench] oracle: {n_s} centres, {o['npairs']} pairs in {tc:.1f} s on {cores} threads "
+            f"(harmonics {tm['harmonics']:.1f} s, contraction {tm['contraction']:.1f} s); one thread "
+            f"{o_1['npairs'] / tm_1['harmonics']:.3g} pairs/s; full step extrapolated "
+            f"{out['cpu_baseline']['extrapolated_full_step_s']:.0f} s")
         ref = mp.pack_nonneg(o["ups"], o["N"], nm)
         ref_g, _ = mp.normalise(o["ups"], o["N"])
         ref_g = ref_g[:, nm:]
@@ -263,6 +290,17 @@ def main():
         out["errors_vs_oracle"] = errs
         out["errors_vs_oracle"]["sample"] = f"{n_s} centres"
     print(json.dumps(out), flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_tomo(t3, torch, dev):

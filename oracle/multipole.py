@@ -19,6 +19,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import time
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -57,6 +58,8 @@ def _load():
                                      dp, dp, dp, lp]
         lib.o1_threads.restype = ctypes.c_int
         lib.o1_threads.argtypes = []
+        lib.o1_set_threads.restype = None
+        lib.o1_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -64,6 +67,11 @@ def _load():
 def threads() -> int:
     """OpenMP threads the C core runs with."""
     return int(_load().o1_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads for later calls from this thread (timing only)."""
+    _load().o1_set_threads(int(n))
 
 
 def _dp(a: np.ndarray):
@@ -167,14 +175,23 @@ def _c_of(cat: Catalog) -> np.ndarray:
 
 
 def multipoles(cat: Catalog, edges: Sequence[float], n_max: int, centres: Optional[np.ndarray] = None,
-               w_max: Optional[int] = None, diag: bool = True, positions: Optional[tuple] = None):
-    """Non-tomographic multipoles; centres index into ``cat`` (default: all)."""
+               w_max: Optional[int] = None, diag: bool = True, positions: Optional[tuple] = None,
+               timings: Optional[dict] = None):
+    """Non-tomographic multipoles; centres index into ``cat`` (default: all).
+
+    ``timings``, if given, receives the wall seconds of the two stages
+    (keys "harmonics" and "contraction")."""
     cen = cat if centres is None else cat.subset(centres)
     if positions is not None and centres is not None:
         raise ValueError("positions override needs all centres")
     pos = None if positions is None else (positions[0], positions[1], positions[0], positions[1])
+    t0 = time.perf_counter()
     h = harmonics(cen, cat, edges, n_max, w_max=w_max, positions=pos)
+    t1 = time.perf_counter()
     ups, N = upsilon_from_harmonics(_c_of(cen), cen.w, h, h, n_max, diag=diag)
+    if timings is not None:
+        timings["harmonics"] = t1 - t0
+        timings["contraction"] = time.perf_counter() - t1
     return dict(ups=ups, N=N, npairs=int(h["npairs"].sum()), harm=h)
 
 

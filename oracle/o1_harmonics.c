@@ -40,6 +40,12 @@ int o1_threads(void)
     return omp_get_max_threads();
 }
 
+/* Threads for later calls from the calling thread (n >= 1). */
+void o1_set_threads(int n)
+{
+    if (n >= 1) omp_set_num_threads(n);
+}
+
 static int find_bin(double r2, int n_bins, const double *e2)
 {
     if (!(r2 >= e2[0]) || !(r2 < e2[n_bins]))
