@@ -91,7 +91,7 @@ extern "C" {
                             /* neighbours per centre run one lane per centre)   */
 
 typedef struct {
-    int32_t n_bins;        /* B >= 1                                         */
+    int32_t n_bins;        /* 1 <= B <= 64                                   */
     const double *edges;   /* HOST, n_bins + 1 arcmin, strictly increasing,  */
                            /* edges[0] > 0, edges[n_bins] < 512 arcmin       */
     int32_t n_max;         /* largest multipole, 0 <= n_max <= 64            */
@@ -312,7 +312,9 @@ int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets,
  * dL/dg2, dL/dw of every galaxy.  Neighbour contributions are summed with
  * FP32 atomics, so results can differ between calls at rounding level.
  * Synchronises the stream before returning. */
-/* (Not available for plans with T3_FLAG_EDGE_CORRECT: T3_EINVAL.) */
+/* (Not available for plans with T3_FLAG_EDGE_CORRECT: T3_EINVAL.  The
+ * per-centre coefficient step holds B (3 n_max + 8) complex doubles in LDS:
+ * above 160 KiB, i.e. n_max > 50 at B = 64, T3_ERANGE.) */
 int t3_backward(t3_plan *plan, const t3_catalog *cat, const double *grad_ups,
                 float *grad_g1, float *grad_g2, float *grad_w, void *stream);
 

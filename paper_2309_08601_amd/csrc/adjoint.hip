@@ -70,8 +70,8 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
     double2 *Gb = sm;                     // [B][n_g]   index m + nm + 3
     double2 *Wb = Gb + B * n_g;           // [B][nm+1]
     double2 *Db = Wb + B * (nm + 1);      // [B][4]
-    double2 *Xs = Db + B * 4;             // [32]
-    double2 *Ys = Xs + 32;                // [32]
+    double2 *Xs = Db + B * 4;             // [kMaxRadialBins]
+    double2 *Ys = Xs + kMaxRadialBins;    // [kMaxRadialBins]
     const int lane = threadIdx.x;
     const int i = blockIdx.x;
     if (i >= a.n_c) return;
@@ -86,8 +86,7 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
     double ga_r[5] = {0, 0, 0, 0, 0}, ga_i[5] = {0, 0, 0, 0, 0};  // grad alpha (lanes 0..B-1 partials)
     __syncthreads();
 
-    const int b = lane & 31;
-    const bool side_y = lane >= 32;   // lanes 32.. compute grad Y
+    const bool side_y = lane >= 32;   // lanes 32.. compute grad Y, bins (lane & 31) + 32 g
     const size_t pstr = (size_t)(nm + 1) * B * B;
     for (int mu = 0; mu < 5; ++mu) {
         for (int n = 0; n <= nm; ++n) {
@@ -101,18 +100,23 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
             }
             const int pxr = mu < 4 ? 2 * (xm + nm + 3) : 2 * n_g + 2 * n;
             const int pyr = mu < 4 ? 2 * (ym + nm + 3) : 2 * n_g + 2 * n;
-            if (b < B) {
-                const int pl = side_y ? pyr : pxr;
-                const int cj = side_y ? ys : xs;
-                const double re = a.planes[chunk_offset(pl, i, b, K, B)];
-                double im = a.planes[chunk_offset(pl + 1, i, b, K, B)];
+            // operands of every bin: t < B is X(b = t), t >= B is Y(b = t - B)
+            for (int t = lane; t < 2 * B; t += 64) {
+                const bool ty_side = t >= B;
+                const int bt = ty_side ? t - B : t;
+                const int pl = ty_side ? pyr : pxr;
+                const int cj = ty_side ? ys : xs;
+                const double re = a.planes[chunk_offset(pl, i, bt, K, B)];
+                double im = a.planes[chunk_offset(pl + 1, i, bt, K, B)];
                 if (cj) im = -im;
-                (side_y ? Ys : Xs)[b] = make_double2(re, im);
+                (ty_side ? Ys : Xs)[bt] = make_double2(re, im);
             }
             __syncthreads();
             const double *U = a.gups + 2 * ((size_t)mu * pstr + (size_t)n * B * B);
-            double2 gop = make_double2(0.0, 0.0);
-            if (b < B) {
+            double2 gops[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+            for (int g = 0; g < 2; ++g) {
+                const int b = (lane & 31) + 32 * g;
+                if (b >= B) break;
                 // side X: u(b1) = sum_b2 Ub(b1, b2) conj(Y(b2)); side Y: v(b2) = sum_b1 Ub(b1, b2) conj(X(b1))
                 double ur = 0.0, ui = 0.0;
                 for (int k = 0; k < B; ++k) {
@@ -133,15 +137,21 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
                 }
                 const int cj = side_y ? ys : xs;
                 if (cj) gi = -gi;  // operand was conj(G): grad G = conj(grad operand)
-                gop = make_double2(gr, gi);
+                gops[g] = make_double2(gr, gi);
             }
             // the two sides may update the same (b, order): one side at a time
-            double2 *tx = mu < 4 ? &Gb[b * n_g + (xm + nm + 3)] : &Wb[b * (nm + 1) + n];
-            double2 *ty = mu < 4 ? &Gb[b * n_g + (ym + nm + 3)] : &Wb[b * (nm + 1) + n];
-            if (b < B && !side_y) *tx = make_double2(tx->x + gop.x, tx->y + gop.y);
-            __syncthreads();
-            if (b < B && side_y) *ty = make_double2(ty->x + gop.x, ty->y + gop.y);
-            __syncthreads();
+            for (int side = 0; side < 2; ++side) {
+                if (side_y == (side == 1)) {
+                    for (int g = 0; g < 2; ++g) {
+                        const int b = (lane & 31) + 32 * g;
+                        if (b >= B) break;
+                        const int m = side ? ym : xm;
+                        double2 *t = mu < 4 ? &Gb[b * n_g + (m + nm + 3)] : &Wb[b * (nm + 1) + n];
+                        *t = make_double2(t->x + gops[g].x, t->y + gops[g].y);
+                    }
+                }
+                __syncthreads();
+            }
         }
     }
     // j = k terms
@@ -195,13 +205,13 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
         sub(4, dw, 0.0);
     }
     __syncthreads();
-    // centre gradient: reduce grad alpha over lanes 0..B-1 (other lanes hold 0)
+    // centre gradient: reduce grad alpha over the wavefront (the X-side
+    // lanes hold the operand terms, lanes 0..B-1 the j = k terms, others 0)
     double gcr = 0.0, gci = 0.0, gw = 0.0;
     {
         double vr = -ga_r[0] - ga_r[1] - ga_r[2] - ga_r[3];
         double vi = -ga_i[0] + ga_i[1] - ga_i[2] - ga_i[3];
         double vw = ga_r[4];
-        if (lane >= 32) vr = vi = vw = 0.0;
         for (int d = 32; d > 0; d >>= 1) {
             vr += __shfl_xor(vr, d, 64);
             vi += __shfl_xor(vi, d, 64);
@@ -473,7 +483,9 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
     T3_HIP_CHECK(hipGetLastError());
     const bool jk = !(plan->flags & T3_FLAG_KEEP_JK);
     const int B = plan->B, nm = plan->n_max;
-    const size_t lds = sizeof(double2) * ((size_t)B * ((2 * nm + 3) + (nm + 1) + 4) + 64);
+    const size_t lds = sizeof(double2) * ((size_t)B * ((2 * nm + 3) + (nm + 1) + 4) + 2 * kMaxRadialBins);
+    if (lds > 160 * 1024)  // a workgroup's LDS limit on gfx950 (B = 64 allows n_max <= 50)
+        return fail(T3_ERANGE, "t3_backward: n_bins (3 n_max + 8) above the coefficient kernel's LDS");
     if (lds > 64 * 1024)
         T3_HIP_CHECK(hipFuncSetAttribute((const void *)k_adj_coef,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

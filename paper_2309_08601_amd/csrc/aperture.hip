@@ -37,7 +37,7 @@ struct ApArgs {
     double *corr;        // [n_sets][n_ap][4][2]
     double *stats;       // [n_sets][n_ap][8] or null
     int B, K, n_ap, ap0;  // ap0: index of this launch's first triple
-    double centre[32], width[32];  // radial bins, arcmin
+    double centre[kMaxRadialBins], width[kMaxRadialBins];  // radial bins, arcmin
     double ap[kApPerLaunch][3];    // aperture radii, arcmin
 };
 

@@ -276,7 +276,7 @@ int t3_plan_create(const t3_params *p, t3_plan **out)
     try {
         if (!p || !out) return fail(T3_EINVAL, "t3_plan_create: null argument");
         if (p->n_bins < 1 || !p->edges) return fail(T3_EINVAL, "t3_plan_create: need n_bins >= 1 and edges");
-        if (p->n_bins > 32) return fail(T3_ERANGE, "t3_plan_create: at most 32 radial bins");
+        if (p->n_bins > kMaxRadialBins) return fail(T3_ERANGE, "t3_plan_create: at most 64 radial bins");
         if (p->n_max < 0 || p->n_max > 64) return fail(T3_ERANGE, "t3_plan_create: n_max must be in [0, 64]");
         if (p->precision < T3_PREC_FP32 || p->precision > T3_PREC_BF16X6)
             return fail(T3_EINVAL, "t3_plan_create: unknown precision");

@@ -11,9 +11,11 @@
 // A complex product is four real MFMAs: Re += Xr Yr - Xi Yi, Im += Xr Yi + Xi Yr.
 //
 // Work decomposition: a workgroup of four wavefronts owns one n (the four
-// shear components, one wavefront each) or four orders of N, and one slice
-// of centres.  The operands the four products share (mu = 0 and 3 have the
-// same X, mu = 0 and 2 the same Y) are formed once per block of 16 centres:
+// shear components, one wavefront each) or four orders of N, one slice of
+// centres and one 32 x 32 tile of the B x B block (grid.y; one tile for
+// B <= 32, four for B <= 64).  The operands the four products share (mu = 0
+// and 3 have the same X, mu = 0 and 2 the same Y) are formed once per block
+// of 16 centres:
 // the whole workgroup loads the harmonic planes with coalesced float4 reads,
 // multiplies in the centre factor, splits into hi / lo parts where the
 // precision asks for it, and stores MFMA-ready rows in LDS; the next block's
@@ -45,7 +47,8 @@ typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 constexpr int kBlk = 16;   // centres staged through LDS per step
 constexpr int kRun = 64;   // centres per FP32 accumulation run before FP64 promotion
-constexpr int kRows = 32;  // tile rows (bins), B <= 32
+constexpr int kRows = 32;  // tile rows and columns (bins)
+constexpr int kScaleRows = kMaxRadialBins;  // fp16 row scales per operand array
 constexpr int kNYArr = 6;  // complex operand arrays of the Upsilon kernel
 
 // One launch covers every ordered pair (Z2, Z3) of neighbour catalogs
@@ -55,7 +58,7 @@ struct ContractArgs {
     const float *planes; // planes of catalog 0; catalog z at planes + z * zstride
     size_t zstride;
     const float4 *ccw;   // centre factors (w g1, w g2, w, 0), chunk-relative
-    const float *scale;  // fp16 row scales [pair][n][kNYArr][kRows] or null
+    const float *scale;  // fp16 row scales [pair][n][kNYArr][kScaleRows] or null
     int n_c, K, B, n_max, n_z;
     int w_max;           // largest order of N (n_max, or 2 n_max for mode coupling)
     int slice;           // centres per slice (multiple of kRun)
@@ -172,13 +175,14 @@ __device__ __forceinline__ void put4(typename Fmt<PK>::T *row, float v0, float v
     }
 }
 
-__device__ __forceinline__ void store_tile(double *dst, int B, int lane, const double (&dr)[16],
+// Accumulator tile (rows r0.., columns c0..) into the B x B block dst.
+__device__ __forceinline__ void store_tile(double *dst, int B, int r0, int c0, int lane, const double (&dr)[16],
                                            const double (&di)[16], const float *sx, const float *sy)
 {
-    const int col = lane & 31;
+    const int col = c0 + (lane & 31);
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const int row = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+        const int row = r0 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
         if (row < B && col < B) {
             const double f = sx ? 1.0 / ((double)sx[row] * (double)sy[col]) : 1.0;
             double2 v;
@@ -251,6 +255,8 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
     const int grp = jx % ngrp;
     const int sl = 8 * (jx / ngrp) + xcd;
     if (sl >= a.S) return;
+    const int nt = (a.B + kRows - 1) / kRows;  // bin tiles per side
+    const int tb1 = (int)blockIdx.y / nt, tb2 = (int)blockIdx.y % nt;
     const float *px, *py;
     pair_planes(a, pair, px, py);
     const int i_begin = sl * a.slice;
@@ -276,9 +282,11 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
     }
     const bool active = n <= (NK ? a.w_max : nm);
 
-    // staging role: bin sb, centre quad sq, side sh (0: X from px, 1: Y from py)
+    // staging role: tile row sb (bin bg), centre quad sq, side sh (0: X from
+    // px, bins of tile tb1; 1: Y from py, bins of tile tb2)
     const int sb = tid & 31, sq = (tid >> 5) & 3;
     const int sh = __builtin_amdgcn_readfirstlane(tid >> 7);
+    const int bg = (sh ? tb2 : tb1) * kRows + sb;
     int pl[NL];
     if constexpr (NK) {
         pl[0] = plane_w(min(2 * grp, a.w_max), nm);
@@ -289,7 +297,7 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
         pl[2] = plane_g(sh ? grp - 1 : -grp - 1, nm);
     }
     const float *src = sh ? py : px;
-    const int bc = min(sb, a.B - 1);
+    const int bc = min(bg, a.B - 1);
     unsigned off[NL][2];  // float offset of (plane, centre 0, bin bc)
 #pragma unroll
     for (int k = 0; k < NL; ++k)
@@ -304,10 +312,10 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
     float sc[3] = {1.f, 1.f, 1.f};        // fp16 row scales of this thread's arrays
     const float *scl = nullptr;
     if constexpr (PK == T3_PREC_FP16X3) {
-        scl = a.scale + ((size_t)pair * (nm + 1) + n) * kNYArr * kRows;
-        const float *srow = a.scale + ((size_t)pair * (nm + 1) + grp) * kNYArr * kRows;
+        scl = a.scale + ((size_t)pair * (nm + 1) + n) * kNYArr * kScaleRows;
+        const float *srow = a.scale + ((size_t)pair * (nm + 1) + grp) * kNYArr * kScaleRows;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) sc[k] = srow[(3 * sh + k) * kRows + sb];
+        for (int k = 0; k < 3; ++k) sc[k] = srow[(3 * sh + k) * kScaleRows + bg];
     }
 
     struct Stage {
@@ -322,7 +330,7 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
     auto load_block = [&](Stage &st, int i0) {
         const int q = (i0 >> 2) + sq;
         const unsigned qo = (unsigned)min(q, q_last) * qstride;
-        st.nv = sb < a.B ? max(0, min(4, i_end - 4 * q)) : 0;
+        st.nv = bg < a.B ? max(0, min(4, i_end - 4 * q)) : 0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const float4 f = a.ccw[min(4 * q + e, i_last)];
@@ -495,16 +503,16 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
     double *dst = a.partial + (((size_t)pair * a.S + sl) * nq + q) * a.B * a.B * 2;
     if constexpr (NK) {
         // one part per wavefront: real parts in dr of wave r = 0, imaginary in r = 1
-        const int col = lane & 31;
+        const int col = kRows * tb2 + (lane & 31);
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-            const int row = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+            const int row = kRows * tb1 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
             if (row < a.B && col < a.B) dst[2 * ((size_t)row * a.B + col) + ri] = dr[j];
         }
     } else if constexpr (PK == T3_PREC_FP16X3) {
-        store_tile(dst, a.B, lane, dr, di, scl + ia * kRows, scl + ib * kRows);
+        store_tile(dst, a.B, kRows * tb1, kRows * tb2, lane, dr, di, scl + ia * kScaleRows, scl + ib * kScaleRows);
     } else {
-        store_tile(dst, a.B, lane, dr, di, nullptr, nullptr);
+        store_tile(dst, a.B, kRows * tb1, kRows * tb2, lane, dr, di, nullptr, nullptr);
     }
 }
 
@@ -519,11 +527,14 @@ constexpr int kScaleSplit = 16;
 
 __global__ __launch_bounds__(256) void k_fp16_max(ContractArgs a, unsigned *mx_all)
 {
-    const int n = blockIdx.x, side = blockIdx.y & 1, pair = blockIdx.y >> 1;
+    // grid.y = (pair, side, bin tile)
+    const int nt = (a.B + 31) >> 5;
+    const int n = blockIdx.x, tile = (int)blockIdx.y % nt;
+    const int side = ((int)blockIdx.y / nt) & 1, pair = ((int)blockIdx.y / nt) >> 1;
     const float *px, *py;
     pair_planes(a, pair, px, py);
     const int nm = a.n_max;
-    const int b = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int bl = threadIdx.x & 31, b = 32 * tile + bl, g = threadIdx.x >> 5;
     int pl[3];
     if (side == 0) {
         pl[0] = plane_g(n - 3, nm);
@@ -569,13 +580,13 @@ __global__ __launch_bounds__(256) void k_fp16_max(ContractArgs a, unsigned *mx_a
     }
     __shared__ float sm[3][8][32];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) sm[k][g][b] = m[k];
+    for (int k = 0; k < 3; ++k) sm[k][g][bl] = m[k];
     __syncthreads();
     if (threadIdx.x < 96) {
         const int k = threadIdx.x >> 5;
         float mx = 0.f;
-        for (int j = 0; j < 8; ++j) mx = fmaxf(mx, sm[k][j][b]);
-        atomicMax(mx_all + (((size_t)pair * (nm + 1) + n) * kNYArr + 3 * side + k) * kRows + b,
+        for (int j = 0; j < 8; ++j) mx = fmaxf(mx, sm[k][j][bl]);
+        atomicMax(mx_all + (((size_t)pair * (nm + 1) + n) * kNYArr + 3 * side + k) * kScaleRows + b,
                   __float_as_uint(mx));
     }
 }
@@ -703,14 +714,16 @@ int zero_doubles(double *p, size_t n, hipStream_t s)
 
 // Centres per stage-2 slice: a function of the chunk capacity only, so that
 // every chunk of a call fits the buffers reserved up front.  The Upsilon
-// kernel runs (n_max + 1) n_z^2 workgroups per slice, two per compute unit at
+// kernel runs (n_max + 1) n_z^2 t^2 workgroups per slice (t bin tiles per
+// side), two per compute unit at
 // a time (256 CUs); the slice length (a multiple of the FP32 run) minimises
 // rounds x (length + 64), the time of the launch with the cost of writing
 // and reducing one partial tile counted as 64 centres of work, preferring
 // longer slices on ties.
 int contract_slice(const ChunkLayout &L, int n_z)
 {
-    const int64_t per_slice = (int64_t)(L.n_max + 1) * n_z * n_z;
+    const int64_t nt = (L.B + kRows - 1) / kRows;
+    const int64_t per_slice = (int64_t)(L.n_max + 1) * n_z * n_z * nt * nt;
     const int64_t slots = 2 * 256;
     int best = kRun;
     int64_t best_cost = INT64_MAX;
@@ -735,7 +748,7 @@ int reserve_contract(t3_plan *plan, const ChunkLayout &L, int n_z)
     T3_TRY(plan->partial.reserve(sizeof(double) * 2 * per * (size_t)S * pairs));
     T3_TRY(plan->diag.reserve(sizeof(double) * 2 * 5 * (size_t)L.B * n_z * kDiagSplit));
     if (plan->precision == T3_PREC_FP16X3)  // maxima (u32) then scales (f32)
-        T3_TRY(plan->scales.reserve(2 * sizeof(float) * (size_t)kNYArr * kRows * (L.n_max + 1) * pairs));
+        T3_TRY(plan->scales.reserve(2 * sizeof(float) * (size_t)kNYArr * kScaleRows * (L.n_max + 1) * pairs));
     return T3_OK;
 }
 
@@ -743,7 +756,7 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
                    const float *planes, size_t zstride, int n_z, bool jk, double *ups_out, hipStream_t s)
 {
     if (n_c <= 0) return T3_OK;
-    if (L.B > kRows) return T3_ERANGE;
+    if (L.B > kMaxRadialBins) return T3_ERANGE;
     if (L.floats() >= ((size_t)1 << 31)) return T3_ERANGE;  // 32-bit plane offsets in k_contract
     const int pairs = n_z * n_z;
     const int slice = contract_slice(L, n_z);
@@ -766,7 +779,10 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
     a.S = S;
     a.partial = plan->partial.as<double>();
     const int S8 = 8 * ((S + 7) / 8);  // slices padded to whole XCD rounds
-    const dim3 gy((unsigned)((L.n_max + 1) * S8 * pairs)), gn((unsigned)((L.w_max + 2) / 2 * S8 * pairs)), blk(256);
+    const unsigned nt = (unsigned)((L.B + kRows - 1) / kRows);  // bin tiles per side (grid.y: tile pairs)
+    const dim3 gy((unsigned)((L.n_max + 1) * S8 * pairs), nt * nt);
+    const dim3 gn((unsigned)((L.w_max + 2) / 2 * S8 * pairs), nt * nt);
+    const dim3 blk(256);
     switch (plan->precision) {
         case T3_PREC_FP32:
             hipLaunchKernelGGL((k_contract<T3_PREC_FP32, false>), gy, blk, 0, s, a);
@@ -778,11 +794,11 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
             hipLaunchKernelGGL((k_contract<T3_PREC_BF16X6, false>), gy, blk, 0, s, a);
             break;
         default: {
-            const int ns = kNYArr * kRows * (L.n_max + 1) * pairs;
+            const int ns = kNYArr * kScaleRows * (L.n_max + 1) * pairs;
             unsigned *mx = plan->scales.as<unsigned>();
             float *sc = plan->scales.as<float>() + ns;
             hipLaunchKernelGGL(k_zero_u32, dim3((ns + 255) / 256), blk, 0, s, mx, ns);
-            hipLaunchKernelGGL(k_fp16_max, dim3(L.n_max + 1, 2 * pairs, kScaleSplit), blk, 0, s, a, mx);
+            hipLaunchKernelGGL(k_fp16_max, dim3(L.n_max + 1, 2 * pairs * nt, kScaleSplit), blk, 0, s, a, mx);
             hipLaunchKernelGGL(k_fp16_scale, dim3((ns + 255) / 256), blk, 0, s, (const unsigned *)mx, sc, ns);
             T3_HIP_CHECK(hipGetLastError());
             a.scale = sc;

@@ -248,7 +248,7 @@ __global__ __launch_bounds__(64 * kMCWaves) void k_mode_couple(const double *ups
 }
 
 struct CentroidArgs {
-    double theta[32];  // representative radius per bin (any unit: only ratios matter)
+    double theta[kMaxRadialBins];  // representative radius per bin (any unit: only ratios matter)
     int B, n_phi;
     int64_t total;     // n_sets * 4 * B * B * n_phi
 };

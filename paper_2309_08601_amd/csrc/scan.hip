@@ -37,7 +37,7 @@ namespace {
 
 constexpr int kWaves = 4;       // wavefronts (centres) per workgroup
 constexpr int kAnchor = 8;      // FP64 anchor chain stride of the power recurrence
-constexpr int kMaxBins = 64;
+constexpr int kMaxBins = kMaxRadialBins;
 constexpr int kMaxZ = 8;        // neighbour catalogs per launch (tomographic bins)
 constexpr int kFlush = 64;      // batches of 64 neighbours per FP32 run before FP64 promotion
 

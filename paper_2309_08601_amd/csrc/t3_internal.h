@@ -98,6 +98,9 @@ struct CentreSet {
     DevBuf cw;   // float4[n]
 };
 
+// Radial bins of a plan (stage 2 tiles the B x B blocks by 32 x 32).
+constexpr int kMaxRadialBins = 64;
+
 // One resolution of the grid-based estimator: its non-empty pixels as a
 // catalog and the stage-1 planes of its bins at every pixel.
 constexpr int kMaxGridLevels = 8;

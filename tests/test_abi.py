@@ -60,6 +60,7 @@ def _params(**kw):
     (dict(edges=[1.0, 1.0]), -1),
     (dict(edges=[2.0, 1.0]), -1),
     (dict(edges=[1.0, 600.0]), -2),
+    (dict(edges=list(np.geomspace(1.0, 100.0, 66))), -2),  # 65 bins: above the 64 a plan holds
     (dict(n_max=65), -2),
     (dict(n_max=-1), -2),
     (dict(precision=7), -1),
