@@ -264,8 +264,9 @@ struct ScatterArgs {
     const int2 *cpos;     // centre positions (chunk-relative)
     const float *coef;    // [n_c][B][coef_size(cap)]
     int n_c, B, jk;
-    float *nb_gc;         // [2 n] grad c of neighbours (sorted index)
+    float *nb_gc;         // [2][n] grad c of neighbours (sorted index): real parts, then imaginary
     float *nb_gw;         // [n]
+    int64_t n_nb;         // neighbours n
     double e2[65];
 };
 
@@ -353,8 +354,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_scatter(ScatterArgs a)
                 gw = fmaf(2.0f * wt, c[o + 6], gw);
             }
             if (act) {
-                unsafeAtomicAdd(a.nb_gc + 2 * (size_t)gi, gr);
-                unsafeAtomicAdd(a.nb_gc + 2 * (size_t)gi + 1, gim);
+                // three planar arrays: a wavefront's in-bin neighbours are
+                // mostly consecutive sorted indices, so each atomic
+                // instruction covers few, fully used cache lines
+                unsafeAtomicAdd(a.nb_gc + gi, gr);
+                unsafeAtomicAdd(a.nb_gc + a.n_nb + gi, gim);
                 unsafeAtomicAdd(a.nb_gw + gi, gw);
             }
         });
@@ -368,8 +372,8 @@ __global__ void k_adj_combine(const int *perm, int64_t n, const float *nb_gc, co
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int i = perm[s];
-    const float gcr = nb_gc[2 * s] + cen_gc[s].x;
-    const float gci = nb_gc[2 * s + 1] + cen_gc[s].y;
+    const float gcr = nb_gc[s] + cen_gc[s].x;
+    const float gci = nb_gc[n + s] + cen_gc[s].y;
     const float gwd = nb_gw[s] + cen_gw[s];
     const float wi = w[i];
     out_g1[i] = wi * gcr;
@@ -470,7 +474,7 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
     if (plan->chunk_req <= 0 && (int64_t)L.K > n)  // small catalogs, small buffers
         L.K = (int)std::max<int64_t>(256, ((int64_t)n + 255) & ~(int64_t)255);
     const int CS = coef_size(sv->cap);
-    // scratch: nb_gc [2n], nb_gw [n], cen_gc [2n], cen_gw [n]
+    // scratch: nb_gc [2][n], nb_gw [n], cen_gc [2n], cen_gw [n]
     T3_TRY(plan->misc.reserve(sizeof(float) * 6 * (size_t)n));
     T3_TRY(plan->misc2.reserve(sizeof(float) * (size_t)L.K * L.B * CS));
     T3_TRY(plan->chunk.reserve(sizeof(float) * L.floats()));
@@ -528,6 +532,7 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
         sa.jk = jk ? 1 : 0;
         sa.nb_gc = nb_gc;
         sa.nb_gw = nb_gw;
+        sa.n_nb = n;
         for (int b = 0; b <= B; ++b) sa.e2[b] = plan->e2[b];
         int nwg = (nc + kWaves - 1) / kWaves;
         nwg = (nwg + 7) & ~7;
