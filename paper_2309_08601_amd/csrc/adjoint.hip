@@ -270,98 +270,163 @@ struct ScatterArgs {
     double e2[65];
 };
 
+// Gradient terms of one (centre, neighbour) pair: the transposed
+// recurrence against the centre's coefficient block c (LDS, uniform across
+// the wavefront), added to (gr, gim, gw).
+template <int C>
+__device__ __forceinline__ void pair_grad(const float *c, int dx, int dy, float cr, float cim, float wt, int jk,
+                                          float &gr_out, float &gim_out, float &gw_out)
+{
+    constexpr int M = C + 3;
+    const double xd = (double)dx, yd = (double)dy;
+    const double r2 = fma(xd, xd, yd * yd);
+    double s = (double)__builtin_amdgcn_rsqf((float)r2);
+    s = s * fma(-0.5 * r2 * s, s, 1.5);
+    const double zr = xd * s, zi = yd * s;
+    const float fzr = (float)zr, fzi = (float)zi;
+    const double z2r = fma(zr, zr, -zi * zi), z2i = 2.0 * zr * zi;
+    const double z4r = fma(z2r, z2r, -z2i * z2i), z4i = 2.0 * z2r * z2i;
+    const double z8r = fma(z4r, z4r, -z4i * z4i), z8i = 2.0 * z4r * z4i;
+    double ar = 1.0, ai = 0.0;
+    float pr = 1.0f, pi = 0.0f;
+    float gr = c[4 * M], gim = c[4 * M + 1];  // Gb_0
+    float gw = c[4 * M + 2];                   // Re Wb_0
+#pragma unroll
+    for (int m = 1; m <= M; ++m) {
+        if (m % kAnchor == 0) {
+            const double tr = fma(ar, z8r, -ai * z8i);
+            ai = fma(ar, z8i, ai * z8r);
+            ar = tr;
+            pr = (float)ar;
+            pi = (float)ai;
+        } else {
+            const float tr = fmaf(pr, fzr, -pi * fzi);
+            pi = fmaf(pr, fzi, pi * fzr);
+            pr = tr;
+        }
+        const float4 sd = *reinterpret_cast<const float4 *>(c + 4 * (m - 1));
+        gr = fmaf(pr, sd.x, fmaf(pi, sd.z, gr));
+        gim = fmaf(pr, sd.y, fmaf(pi, sd.w, gim));
+        if (m <= C) {
+            const float2 wb = *reinterpret_cast<const float2 *>(c + 4 * M + 2 + 2 * m);
+            gw = fmaf(pr, wb.x, fmaf(pi, wb.y, gw));
+        }
+    }
+    if (jk) {
+        const int o = 4 * M + 2 + 2 * (C + 1);
+        const float p2r = (float)z2r, p2i = (float)z2i;
+        const double z6r = fma(z4r, z2r, -z4i * z2i), z6i = fma(z4r, z2i, z4i * z2r);
+        const float p6r = (float)z6r, p6i = (float)z6i;
+        // 2 conj(c) p6 D6b + 2 conj(c) p2 D2b
+        const float q6r = fmaf(p6r, c[o + 0], -p6i * c[o + 1]);
+        const float q6i = fmaf(p6r, c[o + 1], p6i * c[o + 0]);
+        const float q2r = fmaf(p2r, c[o + 2], -p2i * c[o + 3]);
+        const float q2i = fmaf(p2r, c[o + 3], p2i * c[o + 2]);
+        const float qr = q6r + q2r, qi = q6i + q2i;
+        gr = fmaf(2.0f * cr, qr, fmaf(2.0f * cim, qi, gr));
+        gim = fmaf(2.0f * cr, qi, fmaf(-2.0f * cim, qr, gim));
+        // 2 c Re(DAb p2)
+        const float ra = fmaf(c[o + 4], p2r, -c[o + 5] * p2i);
+        gr = fmaf(2.0f * cr, ra, gr);
+        gim = fmaf(2.0f * cim, ra, gim);
+        // 2 w Re(DWb)
+        gw = fmaf(2.0f * wt, c[o + 6], gw);
+    }
+    gr_out += gr;
+    gim_out += gim;
+    gw_out += gw;
+}
+
+// Transpose scan.  A workgroup owns four consecutive centres of the
+// cell-sorted order (nearby on the sky).  Per bin its four wavefronts split
+// the cell rows (every fourth row) of one annulus around centre 0, widened
+// by the largest centre offset D so that it holds the four centres' annuli;
+// each lane takes one candidate through the transposed recurrences of the
+// centres in whose bin it lies and adds the summed terms with three
+// atomics: a quarter of the atomics of one centre per wavefront.  Where the
+// widening D exceeds the bin width (narrow bins, or a group that straddles
+// the end of a cell row) the group sweeps each centre's own annulus in turn
+// instead.  (Measured on 500k galaxies, 15 bins 1'-60': joint sweeps where
+// D <= width/8: 26 ms per 65k-centre chunk, D <= width/4: 21 ms,
+// D <= width/2: 19.7 ms, D <= width: 19.5 ms; one centre per wavefront:
+// 35 ms.)
 template <int C>
 __global__ __launch_bounds__(64 * kWaves) void k_adj_scatter(ScatterArgs a)
 {
-    constexpr int M = C + 3;
     constexpr int CS = coef_size(C);
     __shared__ int4 q_xyc[kWaves][kRing];
     __shared__ int2 q_wi[kWaves][kRing];
     __shared__ int2 spans[kWaves][2 * kRowsPerBlock + 1];
     constexpr int CSP = (CS + 3) & ~3;  // 16-byte aligned rows
-    __shared__ __align__(16) float cf[kWaves][CSP];
+    __shared__ __align__(16) float cf[kWaves][CSP];  // coefficient block of centre k of the group
+    __shared__ int2 cpk[kWaves];                       // positions of the group's centres
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int nwg = gridDim.x;
     const int per = nwg >> 3;
     const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    const int ci = wg * kWaves + wv;
-    if (ci >= a.n_c) return;
-    const int2 cp = a.cpos[ci];
+    const int c0 = wg * kWaves;  // first centre of the group
+    if (c0 >= a.n_c) return;     // the whole workgroup leaves together
+    const int nk = min(kWaves, a.n_c - c0);
+    double dmax = 0.0;
+    const int2 p0 = a.cpos[c0];
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+        const int2 pk = a.cpos[c0 + min(k, nk - 1)];
+        const double ox = (double)((long long)pk.x - p0.x), oy = (double)((long long)pk.y - p0.y);
+        dmax = fmax(dmax, sqrt(fma(ox, ox, oy * oy)));
+    }
+    if (threadIdx.x < kWaves) cpk[threadIdx.x] = a.cpos[c0 + min((int)threadIdx.x, nk - 1)];
+    const double D = ceil(dmax) + 2.0;  // covers the roundings of the square roots below
     const SweepLDS lds{q_xyc[wv], q_wi[wv], spans[wv]};
-    float *c = cf[wv];
 
     for (int b = 0; b < a.B; ++b) {
-        wave_sync_lds();
-        for (int k = lane; k < CS; k += 64) c[k] = a.coef[((size_t)ci * a.B + b) * CS + k];
-        wave_sync_lds();
-        sweep_annulus(a.sw, cp, a.e2[b], a.e2[b + 1], lane, lds,
-                      [&](const int4 &e, float wt, int gi, bool act) {
-            const float cr = __int_as_float(e.z), cim = __int_as_float(e.w);
-            const double xd = (double)e.x, yd = (double)e.y;
-            const double r2 = fma(xd, xd, yd * yd);
-            double s = (double)__builtin_amdgcn_rsqf((float)r2);
-            s = s * fma(-0.5 * r2 * s, s, 1.5);
-            const double zr = xd * s, zi = yd * s;
-            const float fzr = (float)zr, fzi = (float)zi;
-            const double z2r = fma(zr, zr, -zi * zi), z2i = 2.0 * zr * zi;
-            const double z4r = fma(z2r, z2r, -z2i * z2i), z4i = 2.0 * z2r * z2i;
-            const double z8r = fma(z4r, z4r, -z4i * z4i), z8i = 2.0 * z4r * z4i;
-            double ar = 1.0, ai = 0.0;
-            float pr = 1.0f, pi = 0.0f;
-            float gr = c[4 * M], gim = c[4 * M + 1];  // Gb_0
-            float gw = c[4 * M + 2];                   // Re Wb_0
-#pragma unroll
-            for (int m = 1; m <= M; ++m) {
-                if (m % kAnchor == 0) {
-                    const double tr = fma(ar, z8r, -ai * z8i);
-                    ai = fma(ar, z8i, ai * z8r);
-                    ar = tr;
-                    pr = (float)ar;
-                    pi = (float)ai;
-                } else {
-                    const float tr = fmaf(pr, fzr, -pi * fzi);
-                    pi = fmaf(pr, fzi, pi * fzr);
-                    pr = tr;
-                }
-                const float4 sd = *reinterpret_cast<const float4 *>(c + 4 * (m - 1));
-                gr = fmaf(pr, sd.x, fmaf(pi, sd.z, gr));
-                gim = fmaf(pr, sd.y, fmaf(pi, sd.w, gim));
-                if (m <= C) {
-                    const float2 wb = *reinterpret_cast<const float2 *>(c + 4 * M + 2 + 2 * m);
-                    gw = fmaf(pr, wb.x, fmaf(pi, wb.y, gw));
-                }
-            }
-            if (a.jk) {
-                const int o = 4 * M + 2 + 2 * (C + 1);
-                const float p2r = (float)z2r, p2i = (float)z2i;
-                const double z6r = fma(z4r, z2r, -z4i * z2i), z6i = fma(z4r, z2i, z4i * z2r);
-                const float p6r = (float)z6r, p6i = (float)z6i;
-                // 2 conj(c) p6 D6b + 2 conj(c) p2 D2b
-                const float q6r = fmaf(p6r, c[o + 0], -p6i * c[o + 1]);
-                const float q6i = fmaf(p6r, c[o + 1], p6i * c[o + 0]);
-                const float q2r = fmaf(p2r, c[o + 2], -p2i * c[o + 3]);
-                const float q2i = fmaf(p2r, c[o + 3], p2i * c[o + 2]);
-                const float qr = q6r + q2r, qi = q6i + q2i;
-                gr = fmaf(2.0f * cr, qr, fmaf(2.0f * cim, qi, gr));
-                gim = fmaf(2.0f * cr, qi, fmaf(-2.0f * cim, qr, gim));
-                // 2 c Re(DAb p2)
-                const float ra = fmaf(c[o + 4], p2r, -c[o + 5] * p2i);
-                gr = fmaf(2.0f * cr, ra, gr);
-                gim = fmaf(2.0f * cim, ra, gim);
-                // 2 w Re(DWb)
-                gw = fmaf(2.0f * wt, c[o + 6], gw);
-            }
-            if (act) {
-                // three planar arrays: a wavefront's in-bin neighbours are
-                // mostly consecutive sorted indices, so each atomic
-                // instruction covers few, fully used cache lines
-                unsafeAtomicAdd(a.nb_gc + gi, gr);
-                unsafeAtomicAdd(a.nb_gc + a.n_nb + gi, gim);
-                unsafeAtomicAdd(a.nb_gw + gi, gw);
-            }
-        });
+        __syncthreads();
+        for (int t = threadIdx.x; t < kWaves * CS; t += 64 * kWaves) {
+            const int k = t / CS, e = t - k * CS;
+            cf[k][e] = k < nk ? a.coef[((size_t)(c0 + k) * a.B + b) * CS + e] : 0.0f;
+        }
+        __syncthreads();
+        const double e2lo = a.e2[b], e2hi = a.e2[b + 1];
+        const double elo = sqrt(e2lo), ehi = sqrt(e2hi);
+        const bool joint = nk > 1 && D <= ehi - elo;
+        // joint: one sweep for every centre; else one sweep per centre
+        const int n_sweeps = joint ? 1 : nk;
+        for (int q = 0; q < n_sweeps; ++q) {
+            const int2 sc = cpk[q];
+            const int k_lo = joint ? 0 : q, k_hi = joint ? nk : q + 1;
+            const double wlo = joint ? fmax(elo - D, 0.0) : 0.0;
+            const double s2lo = joint ? wlo * wlo : e2lo;
+            const double s2hi = joint ? (ehi + D) * (ehi + D) : e2hi;
+            sweep_annulus(
+                a.sw, sc, s2lo, s2hi, lane, lds,
+                [&](const int4 &e, float wt, int gi, bool act) {
+                    const float cr = __int_as_float(e.z), cim = __int_as_float(e.w);
+                    float gr = 0.0f, gim = 0.0f, gw = 0.0f;
+                    bool any_in = false;
+#pragma unroll 1
+                    for (int k = k_lo; k < k_hi; ++k) {
+                        const int dx = e.x + (sc.x - cpk[k].x), dy = e.y + (sc.y - cpk[k].y);
+                        const double r2 = fma((double)dx, (double)dx, (double)dy * (double)dy);
+                        const bool in = act && r2 >= e2lo && r2 < e2hi;
+                        if (in) {
+                            pair_grad<C>(cf[k], dx, dy, cr, cim, wt, a.jk, gr, gim, gw);
+                            any_in = true;
+                        }
+                    }
+                    if (any_in) {
+                        // three planar arrays: a wavefront's compacted
+                        // neighbours are mostly consecutive sorted indices,
+                        // so each atomic instruction covers few, fully used
+                        // cache lines
+                        unsafeAtomicAdd(a.nb_gc + gi, gr);
+                        unsafeAtomicAdd(a.nb_gc + a.n_nb + gi, gim);
+                        unsafeAtomicAdd(a.nb_gw + gi, gw);
+                    }
+                },
+                wv, kWaves);
+        }
     }
 }
 

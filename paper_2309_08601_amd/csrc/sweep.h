@@ -113,10 +113,13 @@ __device__ __forceinline__ int locate(const int2 *span, int &t, int v)
 
 // Sweep one annulus.  batch(e, ew, gidx, active) is called with the lane's
 // queue entry; it must not touch the LDS slices.  Returns the number of
-// in-bin neighbours (wave-uniform).
+// in-bin neighbours (wave-uniform).  row_off, row_step: this wavefront
+// sweeps only the cell rows row_lo + row_off + k row_step (wavefronts that
+// split one annulus between them).
 template <class Batch>
 __device__ __forceinline__ int sweep_annulus(const SweepArgs &a, int2 cp, double e2lo, double e2hi,
-                                             int lane, const SweepLDS &L, Batch &&batch)
+                                             int lane, const SweepLDS &L, Batch &&batch, int row_off = 0,
+                                             int row_step = 1)
 {
     const CellGrid &g = a.g;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
@@ -127,10 +130,11 @@ __device__ __forceinline__ int sweep_annulus(const SweepArgs &a, int2 cp, double
     row_hi = row_hi > g.ncy - 1 ? g.ncy - 1 : row_hi;
 
     int head = 0, tail = 0;  // wave-uniform ring counters
-    for (long long r0 = row_lo; r0 <= row_hi; r0 += kRowsPerBlock) {
+    for (long long r0 = row_lo + row_off; r0 <= row_hi; r0 += (long long)kRowsPerBlock * row_step) {
         // ---- ranges of this lane's row, then a wave prefix sum of lengths
         int2 sa = make_int2(0, 0), sb = make_int2(0, 0);
-        if (r0 + lane <= row_hi) row_ranges(a, cp, r0 + lane, e2lo, e2hi, sa, sb);
+        const long long row = r0 + (long long)lane * row_step;
+        if (row <= row_hi) row_ranges(a, cp, row, e2lo, e2hi, sa, sb);
         const int la = sa.y - sa.x, lb = sb.y - sb.x;
         int incl = la + lb;
 #pragma unroll
