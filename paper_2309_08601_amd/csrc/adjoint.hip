@@ -88,70 +88,108 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
 
     const bool side_y = lane >= 32;   // lanes 32.. compute grad Y, bins (lane & 31) + 32 g
     const size_t pstr = (size_t)(nm + 1) * B * B;
-    for (int mu = 0; mu < 5; ++mu) {
-        for (int n = 0; n <= nm; ++n) {
-            int xm, ym, xs = 0, ys = 0;  // orders; xs/ys = 1 when the operand is conjugated
-            switch (mu) {
-                case 0: xm = n - 3; ym = -n - 3; break;
-                case 1: xm = n - 1; ym = -n - 1; break;
-                case 2: xm = -n - 1; ym = -n - 3; xs = 1; break;
-                case 3: xm = n - 3; ym = n - 1; ys = 1; break;
-                default: xm = n; ym = n; ys = 1; break;
-            }
-            const int pxr = mu < 4 ? 2 * (xm + nm + 3) : 2 * n_g + 2 * n;
-            const int pyr = mu < 4 ? 2 * (ym + nm + 3) : 2 * n_g + 2 * n;
-            // operands of every bin: t < B is X(b = t), t >= B is Y(b = t - B)
-            for (int t = lane; t < 2 * B; t += 64) {
+    // (mu, n) -> operand orders and planes; xs/ys = 1 when the operand is conjugated
+    auto orders = [&](int it, int &mu, int &n, int &xm, int &ym, int &xs, int &ys, int &pxr, int &pyr) {
+        mu = it / (nm + 1);
+        n = it - mu * (nm + 1);
+        xs = 0;
+        ys = 0;
+        switch (mu) {
+            case 0: xm = n - 3; ym = -n - 3; break;
+            case 1: xm = n - 1; ym = -n - 1; break;
+            case 2: xm = -n - 1; ym = -n - 3; xs = 1; break;
+            case 3: xm = n - 3; ym = n - 1; ys = 1; break;
+            default: xm = n; ym = n; ys = 1; break;
+        }
+        pxr = mu < 4 ? 2 * (xm + nm + 3) : 2 * n_g + 2 * n;
+        pyr = mu < 4 ? 2 * (ym + nm + 3) : 2 * n_g + 2 * n;
+    };
+    // operands of one iteration: slot t < B is X(b = t), t >= B is Y(b = t - B);
+    // lane holds slots lane and lane + 64.  Loaded one iteration ahead.
+    float pre[2][2];
+    auto fetch = [&](int it) {
+        int mu_, n_, xm_, ym_, xs_, ys_, pxr_, pyr_;
+        orders(it, mu_, n_, xm_, ym_, xs_, ys_, pxr_, pyr_);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int t = lane + 64 * r;
+            pre[r][0] = pre[r][1] = 0.0f;
+            if (t < 2 * B) {
                 const bool ty_side = t >= B;
                 const int bt = ty_side ? t - B : t;
-                const int pl = ty_side ? pyr : pxr;
-                const int cj = ty_side ? ys : xs;
-                const double re = a.planes[chunk_offset(pl, i, bt, K, B)];
-                double im = a.planes[chunk_offset(pl + 1, i, bt, K, B)];
-                if (cj) im = -im;
-                (ty_side ? Ys : Xs)[bt] = make_double2(re, im);
+                const int pl = ty_side ? pyr_ : pxr_;
+                pre[r][0] = a.planes[chunk_offset(pl, i, bt, K, B)];
+                const float im = a.planes[chunk_offset(pl + 1, i, bt, K, B)];
+                pre[r][1] = (ty_side ? ys_ : xs_) ? -im : im;
             }
-            __syncthreads();
-            const double *U = a.gups + 2 * ((size_t)mu * pstr + (size_t)n * B * B);
-            double2 gops[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
-            for (int g = 0; g < 2; ++g) {
-                const int b = (lane & 31) + 32 * g;
-                if (b >= B) break;
-                // side X: u(b1) = sum_b2 Ub(b1, b2) conj(Y(b2)); side Y: v(b2) = sum_b1 Ub(b1, b2) conj(X(b1))
-                double ur = 0.0, ui = 0.0;
-                for (int k = 0; k < B; ++k) {
-                    const double2 o = side_y ? Xs[k] : Ys[k];
+        }
+    };
+    const int n_it = 5 * (nm + 1);
+    fetch(0);
+    for (int it = 0; it < n_it; ++it) {
+        int mu, n, xm, ym, xs, ys, pxr, pyr;
+        orders(it, mu, n, xm, ym, xs, ys, pxr, pyr);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int t = lane + 64 * r;
+            if (t < 2 * B) {
+                const bool ty_side = t >= B;
+                (ty_side ? Ys : Xs)[ty_side ? t - B : t] = make_double2(pre[r][0], pre[r][1]);
+            }
+        }
+        if (it + 1 < n_it) fetch(it + 1);  // in flight during this iteration
+        __syncthreads();
+        const double *U = a.gups + 2 * ((size_t)mu * pstr + (size_t)n * B * B);
+        double2 gops[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+        for (int g = 0; g < 2; ++g) {
+            const int b = (lane & 31) + 32 * g;
+            if (b >= B) break;
+            // side X: u(b1) = sum_b2 Ub(b1, b2) conj(Y(b2)); side Y: v(b2) = sum_b1 Ub(b1, b2) conj(X(b1))
+            double ur = 0.0, ui = 0.0;
+            for (int k0 = 0; k0 < B; k0 += 8) {
+                // eight independent loads of Ub in flight, then the products
+                double ugr[8], ugi[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int k = min(k0 + q, B - 1);
                     const size_t idx = side_y ? ((size_t)k * B + b) : ((size_t)b * B + k);
-                    const double gr = U[2 * idx], gi = U[2 * idx + 1];
-                    ur += gr * o.x + gi * o.y;   // Ub * conj(o)
-                    ui += gi * o.x - gr * o.y;
+                    ugr[q] = U[2 * idx];
+                    ugi[q] = U[2 * idx + 1];
                 }
-                // grad operand = conj(alpha) * u
-                const double ar = al_r[mu], ai = al_i[mu];
-                double gr = ar * ur + ai * ui, gi = ar * ui - ai * ur;
-                if (!side_y) {
-                    // grad alpha += conj(X(b1)) u(b1)
-                    const double2 x = Xs[b];
-                    ga_r[mu] += x.x * ur + x.y * ui;
-                    ga_i[mu] += x.x * ui - x.y * ur;
-                }
-                const int cj = side_y ? ys : xs;
-                if (cj) gi = -gi;  // operand was conj(G): grad G = conj(grad operand)
-                gops[g] = make_double2(gr, gi);
-            }
-            // the two sides may update the same (b, order): one side at a time
-            for (int side = 0; side < 2; ++side) {
-                if (side_y == (side == 1)) {
-                    for (int g = 0; g < 2; ++g) {
-                        const int b = (lane & 31) + 32 * g;
-                        if (b >= B) break;
-                        const int m = side ? ym : xm;
-                        double2 *t = mu < 4 ? &Gb[b * n_g + (m + nm + 3)] : &Wb[b * (nm + 1) + n];
-                        *t = make_double2(t->x + gops[g].x, t->y + gops[g].y);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (k0 + q < B) {
+                        const double2 o = side_y ? Xs[k0 + q] : Ys[k0 + q];
+                        ur += ugr[q] * o.x + ugi[q] * o.y;  // Ub * conj(o)
+                        ui += ugi[q] * o.x - ugr[q] * o.y;
                     }
                 }
-                __syncthreads();
             }
+            // grad operand = conj(alpha) * u
+            const double ar = al_r[mu], ai = al_i[mu];
+            double gr = ar * ur + ai * ui, gi = ar * ui - ai * ur;
+            if (!side_y) {
+                // grad alpha += conj(X(b1)) u(b1)
+                const double2 x = Xs[b];
+                ga_r[mu] += x.x * ur + x.y * ui;
+                ga_i[mu] += x.x * ui - x.y * ur;
+            }
+            const int cj = side_y ? ys : xs;
+            if (cj) gi = -gi;  // operand was conj(G): grad G = conj(grad operand)
+            gops[g] = make_double2(gr, gi);
+        }
+        // the two sides may update the same (b, order): one side at a time
+        for (int side = 0; side < 2; ++side) {
+            if (side_y == (side == 1)) {
+                for (int g = 0; g < 2; ++g) {
+                    const int b = (lane & 31) + 32 * g;
+                    if (b >= B) break;
+                    const int m = side ? ym : xm;
+                    double2 *t = mu < 4 ? &Gb[b * n_g + (m + nm + 3)] : &Wb[b * (nm + 1) + n];
+                    *t = make_double2(t->x + gops[g].x, t->y + gops[g].y);
+                }
+            }
+            __syncthreads();
         }
     }
     // j = k terms
