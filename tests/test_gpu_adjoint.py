@@ -97,6 +97,35 @@ def test_backward_matches_fp64_autograd_oracle(t3):
         assert e < 2e-5 and m < 1e-4, (name, e, m)
 
 
+def test_backward_largest_order_matches_fp64_autograd_oracle(t3):
+    """n_max = 64: the largest compiled transpose-scan variant."""
+    from oracle import autodiff as ad
+    cat = random_catalog(700, 30.0, seed=511)
+    tgt = random_catalog(700, 30.0, seed=512)
+    edges = np.geomspace(1.0, 8.0, 5)
+    nm = 64
+    pl = ad.pairs(cat.x, cat.y, edges)
+    t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))  # noqa: E731
+    uT, NT = ad.multipoles(tgt.x, tgt.y, t(tgt.g1), t(tgt.g2), t(tgt.w), edges, nm)
+    T = ad.gamma(uT, NT).detach()
+    om = ad.loss_weights(T)
+    g1 = t(cat.g1).requires_grad_(True)
+    g2 = t(cat.g2).requires_grad_(True)
+    w = t(cat.w).requires_grad_(True)
+    u, N = ad.multipoles(cat.x, cat.y, g1, g2, w, edges, nm, pair_list=pl)
+    Lr = ad.loss(ad.gamma(u, N), T, om)
+    Lr.backward()
+    lo, size = box_for(30.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size)
+    L, _, d1, d2, dw = _gpu_loss_and_grad(t3, plan, cat, T, om)
+    assert abs(float(L) - float(Lr)) < 1e-5 * float(Lr)
+    for got, ref, name in ((d1, g1.grad, "g1"), (d2, g2.grad, "g2"), (dw, w.grad, "w")):
+        ref = ref.numpy()
+        e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"n_max 64 grad {name}: rel-norm {e:.2e}", flush=True)
+        assert e < 2e-5, (name, e)
+
+
 def test_backward_matches_finite_differences_of_gpu_forward(t3):
     cat = random_catalog(2000, 45.0, seed=601)
     tgt = random_catalog(2000, 45.0, seed=602)

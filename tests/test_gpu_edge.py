@@ -50,7 +50,7 @@ def _pack_ec(ups, N, nm):
     return np.concatenate([u, n], axis=0)
 
 
-@pytest.mark.parametrize("nm", [3, 8, 30, 40])
+@pytest.mark.parametrize("nm", [3, 8, 30, 40, 48, 64])
 def test_extended_normaliser_matches_oracle(t3, nm):
     from oracle import multipole as mp
     cat = _masked_catalog(4000, 50.0, seed=900 + nm)
