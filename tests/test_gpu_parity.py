@@ -75,7 +75,7 @@ def test_harmonics_match_oracle(t3):
     assert np.array_equal(W1[:, :, 0].real.cpu().numpy().astype(np.float64), cnt)
 
 
-@pytest.mark.parametrize("nm", [0, 3, 10, 20, 30, 48, 64])
+@pytest.mark.parametrize("nm", [0, 3, 10, 14, 20, 24, 30, 32, 48, 64])  # with 8, 12, 40 elsewhere: every compiled capacity
 def test_forward_small_orders(t3, nm):
     _, mp = _oracle()
     cat = random_catalog(1500, 40.0, seed=100 + nm)
