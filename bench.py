@@ -90,6 +90,8 @@ def main():
                     help="stage-2 precision of the --profile-steps passes")
     ap.add_argument("--profile-combined", default=None, choices=["direct", "fft", "auto"],
                     help="with --profile-steps: run the combined estimator (Delta_1 = 0.25') by this route")
+    ap.add_argument("--profile-extra", default=None, choices=["tomo", "grad"],
+                    help="with --profile-steps: run only the tomography or gradient leg (once)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design "
@@ -116,6 +118,10 @@ def main():
         gn, gp = p.normalise_resum(ups, n_phi=wl.n_phi)
         return ups, npairs
 
+    if args.profile_steps and args.profile_extra:
+        res = (bench_tomo if args.profile_extra == "tomo" else bench_grad)(t3, torch, dev)
+        log(f"[bench] profile {args.profile_extra}: {res}")
+        return
     if args.profile_steps:
         # plain copy of a known size: calibrates the HBM byte counters
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB
