@@ -348,10 +348,22 @@ def test_resum_point_values():
 
 
 def test_storage_size_formula():
-    """5 (n_max + 1) n_Theta^2 n_z^3 complex128 entries: about 150 MB for
-    n_max = 10, n_Theta = 38, n_z = 5 (Appendix A)."""
-    entries = 5 * (10 + 1) * 38 ** 2 * 5 ** 3
-    assert 140e6 < entries * 16 < 160e6
+    """The packed tomographic output (only n >= 0 kept, Appendix A
+    symmetries) of the paper's T17 setup has the size the paper prints
+    (tests/golden/appendix_a_storage.txt: about 150 MB)."""
+    import os
+    vals = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "appendix_a_storage.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = float(v)
+    nm, B, nz = int(vals["n_max"]), int(vals["n_theta"]), int(vals["n_z"])
+    ups = np.zeros((nz, nz, nz, 4, 2 * nm + 1, B, B), dtype=np.complex128)
+    N = np.zeros((nz, nz, nz, 2 * nm + 1, B, B), dtype=np.complex128)
+    packed = mp.pack_nonneg(ups, N, nm)
+    mb = packed.size * 16 / 2.0 ** 20
+    assert abs(mb - vals["megabytes"]) < 0.02 * vals["megabytes"], mb
 
 
 @pytest.mark.slow
