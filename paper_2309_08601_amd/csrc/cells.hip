@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_block(int *__restrict__ dat
     s[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < kScanBlock; off <<= 1) {
-        int t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        int t = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0;
         __syncthreads();
         s[threadIdx.x] += t;
         __syncthreads();
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_sums(int *__restrict__ sums
         s[threadIdx.x] = v;
         __syncthreads();
         for (int off = 1; off < kScanBlock; off <<= 1) {
-            int t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+            int t = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0;
             __syncthreads();
             s[threadIdx.x] += t;
             __syncthreads();
