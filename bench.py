@@ -90,8 +90,8 @@ def main():
                     help="stage-2 precision of the --profile-steps passes")
     ap.add_argument("--profile-combined", default=None, choices=["direct", "fft", "auto"],
                     help="with --profile-steps: run the combined estimator (Delta_1 = 0.25') by this route")
-    ap.add_argument("--profile-extra", default=None, choices=["tomo", "grad"],
-                    help="with --profile-steps: run only the tomography or gradient leg (once)")
+    ap.add_argument("--profile-extra", default=None, choices=["tomo", "grad", "combined_3m"],
+                    help="with --profile-steps: run only the tomography, gradient or 3.1M-galaxy combined leg (once)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design "
@@ -119,7 +119,8 @@ def main():
         return ups, npairs
 
     if args.profile_steps and args.profile_extra:
-        res = (bench_tomo if args.profile_extra == "tomo" else bench_grad)(t3, torch, dev)
+        res = {"tomo": bench_tomo, "grad": bench_grad, "combined_3m": bench_combined_3m}[args.profile_extra](
+            t3, torch, dev)
         log(f"[bench] profile {args.profile_extra}: {res}")
         return
     if args.profile_steps:
@@ -230,6 +231,7 @@ def main():
         out["tomography"] = bench_tomo(t3, torch, dev)
         out["gradient"] = bench_grad(t3, torch, dev)
         out["edge_correction"] = bench_edge(t3, torch, dev, dc, wl, box)
+        out["combined_3m"] = bench_combined_3m(t3, torch, dev)
 
     if not args.no_cpu:
         import oracle
@@ -307,6 +309,52 @@ def cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def bench_combined_3m(t3, torch, dev):
+    """The configuration of the paper's combined-estimator timing (Sect. 4.1:
+    3.1e6 galaxies on 100 deg^2, 33 log bins 0.25'-80', n_max 20): one
+    discrete step against one combined step with grids of Delta = 0.25', 0.5'
+    and 1' for the bins whose lower edge is at least 20 Delta (the coarsest
+    such, up to 1'), each after a warm-up pass.  The paper quotes about 20x
+    for this setup on CPU cores (context, not a target)."""
+    from paper_2309_08601_amd.synth import LATTICE_UNIT, WORKLOADS, make_catalogs
+    wl = WORKLOADS["field_3m_33bins"]
+    cat = make_catalogs(wl)[0]
+    dc = t3.DeviceCatalog.from_catalog(cat, device=dev)
+    box = int(round(wl.side / LATTICE_UNIT))
+    edges = wl.edges()
+    levels = t3.grid_levels(edges, 0.25, max_level=3)
+    plan = t3.Plan(edges, wl.n_max, box_size=box)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        npairs = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, npairs
+
+    def disc():
+        ups, npairs = plan.forward(dc)
+        plan.normalise_resum(ups, n_phi=wl.n_phi)
+        return npairs
+
+    def comb():
+        ups, npairs = plan.forward_grid(dc, int(round(0.25 / LATTICE_UNIT)), levels, method="auto")
+        plan.normalise_resum(ups, n_phi=wl.n_phi)
+        return npairs
+
+    t_d, p_d = timed(disc)
+    t_c, p_c = timed(comb)
+    res = {"discrete_s": t_d, "combined_s": t_c, "speedup": t_d / t_c, "discrete_pairs": p_d,
+           "discrete_pairs_per_s": p_d / t_d, "combined_pair_sums": p_c, "levels": levels,
+           "workload": "field_3m_33bins: 3100000 galaxies in 600' x 600', 33 log bins 0.25'-80', n_max=20; "
+                       "combined: Delta_1 = 0.25', grids for lower edge >= 20 Delta up to Delta = 1', route per level "
+                       "by the cost model"}
+    log(f"[bench] combined, 3.1M galaxies / 33 bins: discrete {t_d:.2f} s ({p_d / t_d:.3e} pairs/s), "
+        f"combined {t_c:.3f} s, {t_d / t_c:.1f}x; levels {levels}")
+    return res
 
 
 def bench_tomo(t3, torch, dev):
