@@ -13,7 +13,11 @@
 // Work decomposition: a workgroup of four wavefronts owns one n (the four
 // shear components, one wavefront each) or four orders of N, one slice of
 // centres and one 32 x 32 tile of the B x B block (grid.y; one tile for
-// B <= 32, four for B <= 64).  The operands the four products share (mu = 0
+// B <= 40, four for B = 41..64).  For B = 33..40 only the first tile runs on
+// MFMA: the outputs with a bin index of 32 or more (at most 8 rows and
+// columns) are summed by k_contract_edge on the vector ALUs in FP64, rather
+// than by three more MFMA tiles holding at most 8 real rows or columns each.
+// The operands the four products share (mu = 0
 // and 3 have the same X, mu = 0 and 2 the same Y) are formed once per block
 // of 16 centres:
 // the whole workgroup loads the harmonic planes with coalesced float4 reads,
@@ -66,6 +70,7 @@ struct ContractArgs {
     int w_max;           // largest order of N (n_max, or 2 n_max for mode coupling)
     int slice;           // centres per slice (multiple of kSliceStep)
     int S;               // slices
+    int nt;              // MFMA tiles per side of the B x B block (grid.y = nt^2)
     double *partial;     // [pair][S][4 (n_max+1) + w_max + 1][B][B][2]
 };
 
@@ -258,7 +263,7 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
     const int grp = jx % ngrp;
     const int sl = 8 * (jx / ngrp) + xcd;
     if (sl >= a.S) return;
-    const int nt = (a.B + kRows - 1) / kRows;  // bin tiles per side
+    const int nt = a.nt;  // bin tiles per side
     const int tb1 = (int)blockIdx.y / nt, tb2 = (int)blockIdx.y % nt;
     const float *px, *py;
     pair_planes(a, pair, px, py);
@@ -519,6 +524,176 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
     }
 }
 
+// Edge bins for B = 33..40: every output (b1, b2) of the B x B blocks with
+// b1 >= T or b2 >= T (T = 32, the extent of the one MFMA tile), for the
+// slice's centres, written into the slice's partial block like the tiles.
+// One workgroup per (slice, catalog pair) x order n: the four Upsilon_mu
+// (NK = false) or N_n (NK = true).  Per block of kEdgeBlk centres the
+// workgroup forms the operands of every bin in FP32 with the arithmetic of
+// the MFMA kernel (X = -c G_{n-3}, -c* G_{n-1}, -c conj G_{-n-1}; Y =
+// G_{-n-3}, G_{-n-1}, G_{n-1}; N: X = w W_n, Y = W_n), stores them in LDS,
+// and each thread adds the products of its outputs in FP64.  There are
+// E = B^2 - T^2 <= 576 outputs per (mu, n), at most kEdgeAcc per thread.
+// Staging thread (e, item): centre e = tid mod 16 of the block and the
+// (array, bin) items tid / 16 + 16 u; the loads of block b + 1 are issued
+// before the products of block b.
+constexpr int kEdgeMaxBins = 40;
+constexpr int kEdgeT = 32;
+constexpr int kEdgeBlk = 16;
+constexpr int kEdgeRow = kEdgeBlk + 1;  // LDS row (array, bin) of kEdgeBlk centres, padded
+constexpr int kEdgeAcc = (4 * (kEdgeMaxBins * kEdgeMaxBins - kEdgeT * kEdgeT) + 255) / 256;
+
+// output e of one (mu, n) block -> (b1, b2): first the rows T..B-1 (every
+// column), then the columns T..B-1 of the rows 0..T-1
+__device__ __forceinline__ void edge_output(int e, int B, int &b1, int &b2)
+{
+    const int r = B - kEdgeT;
+    if (e < r * B) {
+        b1 = kEdgeT + e / B;
+        b2 = e % B;
+    } else {
+        e -= r * B;
+        b1 = e / r;
+        b2 = kEdgeT + e % r;
+    }
+}
+
+template <bool NK>
+__global__ __launch_bounds__(256) void k_contract_edge(ContractArgs a)
+{
+    constexpr int NA = NK ? 2 : 6;  // complex operand arrays: X side, then Y side
+    constexpr int NI = (NA * kEdgeMaxBins + 15) / 16;  // staging items per thread
+    __shared__ float2 op[NA * kEdgeMaxBins * kEdgeRow];
+    const int pairs = a.n_z * a.n_z;
+    const int pair = (int)blockIdx.x % pairs, sl = (int)blockIdx.x / pairs;
+    const int n = blockIdx.y;
+    const int B = a.B, nm = a.n_max, tid = threadIdx.x;
+    const float *px, *py;
+    pair_planes(a, pair, px, py);
+    const int i_begin = sl * a.slice;
+    const int i_end = min(i_begin + a.slice, a.n_c);
+    const int E = B * B - kEdgeT * kEdgeT;
+    const int nout = (NK ? 1 : 4) * E;
+    const unsigned KB = (unsigned)a.K * (unsigned)B;  // floats per plane
+
+    // staging items: (array k, bin b) = kb / B, kb % B with kb = tid / 16 + 16 u
+    const int e = tid & 15;
+    unsigned off[NI];  // float offset of (plane, centre 0, bin) in its catalog's planes
+    int kbp[NI];       // 64 k + b, or -1 past the last item
+#pragma unroll
+    for (int u = 0; u < NI; ++u) {
+        const int kb = (tid >> 4) + 16 * u;
+        kbp[u] = -1;
+        off[u] = 0;
+        if (kb < NA * B) {
+            const int k = kb / B, b = kb % B;
+            int pl;
+            if constexpr (NK)
+                pl = plane_w(n, nm);
+            else
+                pl = k == 0 ? plane_g(n - 3, nm) : k == 1 ? plane_g(n - 1, nm) : k == 2 ? plane_g(-n - 1, nm)
+                   : k == 3 ? plane_g(-n - 3, nm) : k == 4 ? plane_g(-n - 1, nm) : plane_g(n - 1, nm);
+            kbp[u] = 64 * k + b;
+            off[u] = (unsigned)chunk_offset(pl, 0, b, a.K, B);
+        }
+    }
+    // this thread's outputs: LDS rows of X (bits 0-11) and Y (bits 12-23)
+    // and the conjugation of Y (bit 24)
+    int xyo[kEdgeAcc];
+#pragma unroll
+    for (int k = 0; k < kEdgeAcc; ++k) {
+        const int o = tid + 256 * k;
+        xyo[k] = 0;
+        if (o < nout) {
+            const int mu = NK ? 4 : o / E;
+            int b1, b2;
+            edge_output(o % E, B, b1, b2);
+            const int ia = NK ? 0 : (mu == 3 ? 0 : mu);
+            const int ib = NK ? 1 : ((mu == 0 || mu == 2) ? 3 : (mu == 1 ? 4 : 5));
+            xyo[k] = (ia * kEdgeMaxBins + b1) * kEdgeRow | (ib * kEdgeMaxBins + b2) * kEdgeRow << 12 |
+                     (NK || mu == 3) << 24;
+        }
+    }
+
+    float g[NI][2];
+    float4 cw;
+    auto load = [&](int i0) {
+        const int ic = min(i0 + e, i_end - 1);  // clamped: masked when formed
+        const unsigned co = (unsigned)(ic >> 2) * 4u * (unsigned)B + (unsigned)(ic & 3);
+        cw = a.ccw[ic];
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            const float *sp = (kbp[u] >> 6) < NA / 2 ? px : py;
+            g[u][0] = sp[off[u] + co];
+            g[u][1] = sp[off[u] + co + KB];
+        }
+    };
+    auto stage = [&](int i0) {
+        const bool ok = i0 + e < i_end;
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            if (kbp[u] < 0) continue;
+            const int k = kbp[u] >> 6, b = kbp[u] & 63;
+            float ar, ai;
+            if constexpr (NK) {
+                ar = k == 0 ? cw.z : 1.0f;
+                ai = 0.0f;
+            } else {
+                ar = k < 3 ? -cw.x : 1.0f;
+                ai = k < 3 ? (k == 1 ? cw.y : -cw.y) : 0.0f;
+            }
+            const float gr = g[u][0], gi = (!NK && k == 2) ? -g[u][1] : g[u][1];
+            float2 v = make_float2(fmaf(ar, gr, -ai * gi), fmaf(ar, gi, ai * gr));
+            if (!ok) v = make_float2(0.f, 0.f);
+            op[(k * kEdgeMaxBins + b) * kEdgeRow + e] = v;
+        }
+    };
+
+    double accr[kEdgeAcc], acci[kEdgeAcc];
+#pragma unroll
+    for (int k = 0; k < kEdgeAcc; ++k) accr[k] = acci[k] = 0.0;
+    load(i_begin);
+    for (int i0 = i_begin; i0 < i_end; i0 += kEdgeBlk) {
+        stage(i0);
+        __syncthreads();
+        if (i0 + kEdgeBlk < i_end) load(i0 + kEdgeBlk);
+#pragma unroll
+        for (int k = 0; k < kEdgeAcc; ++k) {
+            if (tid + 256 * k < nout) {
+                double sr = 0.0, si = 0.0;
+                const float2 *xp = op + (xyo[k] & 4095), *yp = op + ((xyo[k] >> 12) & 4095);
+                const double ys = (xyo[k] >> 24) ? -1.0 : 1.0;
+#pragma unroll 4
+                for (int c = 0; c < kEdgeBlk; ++c) {
+                    const float2 x = xp[c], y = yp[c];
+                    const double xr = x.x, xi = x.y, yr = y.x, yi = ys * (double)y.y;
+                    sr = fma(xr, yr, fma(-xi, yi, sr));
+                    si = fma(xr, yi, fma(xi, yr, si));
+                }
+                accr[k] += sr;
+                acci[k] += si;
+            }
+        }
+        __syncthreads();
+    }
+    const int nq = 4 * (nm + 1) + a.w_max + 1;
+    double *base = a.partial + ((size_t)pair * a.S + sl) * nq * B * B * 2;
+#pragma unroll
+    for (int k = 0; k < kEdgeAcc; ++k) {
+        const int o = tid + 256 * k;
+        if (o < nout) {
+            const int mu = NK ? 4 : o / E;
+            int b1, b2;
+            edge_output(o % E, B, b1, b2);
+            const int q = mu < 4 ? mu * (nm + 1) + n : 4 * (nm + 1) + n;
+            double2 v;
+            v.x = accr[k];
+            v.y = acci[k];
+            *reinterpret_cast<double2 *>(base + ((size_t)q * B * B + (size_t)b1 * B + b2) * 2) = v;
+        }
+    }
+}
+
 // Row scales for FP16X3, in two steps.  k_fp16_max: for every order n,
 // operand array (the three X and three Y arrays of the Upsilon kernel) and
 // bin, the largest |Re| or |Im| over the chunk's centres, formed with exactly
@@ -699,6 +874,11 @@ __global__ void k_reduce(const double *partial, int S, int n_max, int w_max, int
     out[2 * t + 1] += im;
 }
 
+// MFMA tiles per side of a B x B block: B = 33..40 keeps one tile and sums
+// the bins past it in k_contract_edge.
+int mfma_tiles(int B) { return B <= kEdgeMaxBins ? 1 : (B + kRows - 1) / kRows; }
+bool edge_bins(int B) { return B > kEdgeT && B <= kEdgeMaxBins; }
+
 __global__ void k_zero(double *p, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -727,7 +907,7 @@ int zero_doubles(double *p, size_t n, hipStream_t s)
 // of the others: 5-bin tomography stage 2 at 1.24 s instead of 0.9 s.)
 int contract_slice(const ChunkLayout &L, int n_z)
 {
-    const int64_t nt = (L.B + kRows - 1) / kRows;
+    const int64_t nt = mfma_tiles(L.B);
     const int64_t per_slice = (int64_t)(L.n_max + 1) * n_z * n_z * nt * nt;
     const int64_t slots_xcd = 2 * 32;
     int best = kSliceStep;
@@ -784,8 +964,9 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
     a.slice = slice;
     a.S = S;
     a.partial = plan->partial.as<double>();
+    a.nt = mfma_tiles(L.B);
     const int S8 = 8 * ((S + 7) / 8);  // slices padded to whole XCD rounds
-    const unsigned nt = (unsigned)((L.B + kRows - 1) / kRows);  // bin tiles per side (grid.y: tile pairs)
+    const unsigned nt = (unsigned)a.nt;  // bin tiles per side (grid.y: tile pairs)
     const dim3 gy((unsigned)((L.n_max + 1) * S8 * pairs), nt * nt);
     const dim3 gn((unsigned)((L.w_max + 2) / 2 * S8 * pairs), nt * nt);
     const dim3 blk(256);
@@ -815,6 +996,12 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
     T3_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL((k_contract<T3_PREC_FP32, true>), gn, blk, 0, s, a);
     T3_HIP_CHECK(hipGetLastError());
+    if (edge_bins(L.B)) {
+        hipLaunchKernelGGL(k_contract_edge<false>, dim3((unsigned)(S * pairs), L.n_max + 1), blk, 0, s, a);
+        T3_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_contract_edge<true>, dim3((unsigned)(S * pairs), L.w_max + 1), blk, 0, s, a);
+        T3_HIP_CHECK(hipGetLastError());
+    }
     if (jk) {
         hipLaunchKernelGGL(k_diag, dim3(L.B, n_z, kDiagSplit), dim3(256), 0, s, planes, zstride, a.ccw, n_c,
                            L.K, L.B, L.plane_D(0), n_z, plan->diag.as<double>());

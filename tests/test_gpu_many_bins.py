@@ -196,3 +196,29 @@ def test_combined_40_bins(t3, method):
     n_err = max(np.linalg.norm(got[4 * (nm + 1) + k] - ref[4 * (nm + 1) + k]) / n0 for k in range(nm + 1))
     print(f"combined B=40 ({method}): Upsilon {u_err:.2e}, N_n/N_0 {n_err:.2e}", flush=True)
     assert u_err <= FP32_TOL and n_err <= FP32_TOL
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16x3", SPLIT_TOL), ("fp16x3", SPLIT_TOL), ("bf16x6", FP32_TOL)])
+def test_forward_33_bins_split_precision(t3, prec, tol):
+    """33 bins: the first 32 x 32 tile on split-precision MFMA, the 65 outputs
+    per block that involve bin 32 in FP64 on the vector ALUs, with N_n to
+    2 n_max (edge correction) so that the N side covers more orders than
+    Upsilon."""
+    from oracle import multipole as mp
+    cat = random_catalog(2800, 45.0, seed=4700)
+    edges = np.geomspace(0.6, 18.0, 34)
+    nm = 6
+    lo, size = box_for(45.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size, precision=prec, edge_correct=True, chunk_centres=1024)
+    ups, npairs = plan.forward(t3.DeviceCatalog.from_catalog(cat))
+    o = mp.multipoles(cat, edges, nm, w_max=2 * nm)
+    assert npairs == o["npairs"]
+    got = ups.cpu().numpy()
+    ref_u = o["ups"][:, nm:]
+    e = rel_fro(got[:4 * (nm + 1)].reshape(4, nm + 1, 33, 33), ref_u)
+    n_ref = o["N"][2 * nm:]
+    n_got = got[4 * (nm + 1):]
+    n0 = np.linalg.norm(n_ref[0])
+    en = max(np.linalg.norm(n_got[k] - n_ref[k]) / n0 for k in range(2 * nm + 1))
+    print(f"B=33 {prec}: Upsilon {e.max():.2e}, N_n/N_0 {en:.2e}", flush=True)
+    assert e.max() <= tol and en <= FP32_TOL
