@@ -141,8 +141,13 @@ __global__ void k_cen_slot(const int *__restrict__ perm, int64_t n, const int *_
 }
 
 // Copy the planes of one level's bins from each centre's pixel into the
-// chunk layout.  Threads run in output order (coalesced stores); loads
-// gather from the pixel planes.
+// chunk layout.  One thread per (centre quad, bin) and group of
+// kGatherPlanes planes (grid.y): the four centres' pixel offsets are found
+// once, then each plane takes four gathered loads and one 16-byte store
+// (threads in output order, so the stores of a wavefront are contiguous per
+// quad).
+constexpr int kGatherPlanes = 8;
+
 struct GatherArgs {
     const float *src;     // pixel planes, layout (Kp, nb)
     float *dst;           // chunk planes, layout (K, B)
@@ -152,22 +157,37 @@ struct GatherArgs {
 
 __global__ void k_grid_gather(GatherArgs a)
 {
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t K4 = (size_t)(a.K >> 2);
-    const size_t total = (size_t)a.n_planes * K4 * a.nb * 4;
-    if (t >= total) return;
-    const int r = (int)(t & 3);
-    size_t rest = t >> 2;
-    const int bb = (int)(rest % a.nb);
-    rest /= a.nb;
-    const size_t q = rest % K4;
-    const int p = (int)(rest / K4);
-    const int i = (int)(4 * q) + r;
-    if (i >= a.n_c) return;
-    const int sl = a.slot[i];
-    const size_t src = (((size_t)p * (a.Kp >> 2) + (size_t)(sl >> 2)) * a.nb + bb) * 4 + (sl & 3);
-    const size_t dst = (((size_t)p * K4 + q) * a.B + a.b_lo + bb) * 4 + r;
-    a.dst[dst] = a.src[src];
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned nb = (unsigned)a.nb;
+    if (t >= (unsigned)(a.K >> 2) * nb) return;
+    const int bb = (int)(t % nb);
+    const int q = (int)(t / nb);
+    const int i0 = 4 * q;
+    if (i0 >= a.n_c) return;
+    const int nv = min(4, a.n_c - i0);
+    size_t so[4];  // offset of (pixel, bin bb) in a pixel plane
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int sl = a.slot[min(i0 + r, a.n_c - 1)];
+        so[r] = ((size_t)(sl >> 2) * nb + bb) * 4 + (sl & 3);
+    }
+    const size_t sp = (size_t)(a.Kp >> 2) * nb * 4;  // floats per pixel plane
+    const size_t dp = (size_t)(a.K >> 2) * a.B * 4;  // floats per chunk plane
+    const size_t d0 = ((size_t)q * a.B + a.b_lo + bb) * 4;
+    const int p0 = (int)blockIdx.y * kGatherPlanes, p1 = min(p0 + kGatherPlanes, a.n_planes);
+#pragma unroll 4
+    for (int p = p0; p < p1; ++p) {
+        const float *src = a.src + (size_t)p * sp;
+        float *dst = a.dst + (size_t)p * dp + d0;
+        const float4 v = make_float4(src[so[0]], src[so[1]], src[so[2]], src[so[3]]);
+        if (nv == 4) {
+            *reinterpret_cast<float4 *>(dst) = v;
+        } else {
+            dst[0] = v.x;
+            if (nv > 1) dst[1] = v.y;
+            if (nv > 2) dst[2] = v.z;
+        }
+    }
 }
 
 int prepare_counters(t3_plan *plan, hipStream_t s)
@@ -355,8 +375,11 @@ int forward_grid(t3_plan *plan, const t3_catalog &cat, int64_t delta, const int3
             g.nb = lv.nb;
             g.b_lo = lv.b_lo;
             g.n_planes = L.n_planes();
-            const size_t total = (size_t)g.n_planes * (size_t)(L.K >> 2) * g.nb * 4;
-            hipLaunchKernelGGL(k_grid_gather, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g);
+            const size_t per_group = (size_t)(L.K >> 2) * g.nb;
+            hipLaunchKernelGGL(k_grid_gather,
+                               dim3((unsigned)((per_group + 255) / 256),
+                                    (unsigned)((g.n_planes + kGatherPlanes - 1) / kGatherPlanes)),
+                               dim3(256), 0, s, g);
             T3_HIP_CHECK(hipGetLastError());
         }
         T3_TRY(timing_mark(plan, 1, false, s));
