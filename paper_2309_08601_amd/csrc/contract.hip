@@ -528,12 +528,14 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
 // b1 >= T or b2 >= T (T = 32, the extent of the one MFMA tile), for the
 // slice's centres, written into the slice's partial block like the tiles.
 // One workgroup per (slice, catalog pair) x order n: the four Upsilon_mu
-// (NK = false) or N_n (NK = true).  Per block of kEdgeBlk centres the
-// workgroup forms the operands of every bin in FP32 with the arithmetic of
-// the MFMA kernel (X = -c G_{n-3}, -c* G_{n-1}, -c conj G_{-n-1}; Y =
-// G_{-n-3}, G_{-n-1}, G_{n-1}; N: X = w W_n, Y = W_n), stores them in LDS,
-// and each thread adds the products of its outputs in FP64.  There are
-// E = B^2 - T^2 <= 576 outputs per (mu, n), at most kEdgeAcc per thread.
+// and N_n of order n <= n_max (NK = false), or N_n alone for the orders
+// n_max < n <= w_max of the edge correction (NK = true).  Per block of
+// kEdgeBlk centres the workgroup forms the operands of every bin in FP32
+// with the arithmetic of the MFMA kernel (X = -c G_{n-3}, -c* G_{n-1},
+// -c conj G_{-n-1}; Y = G_{-n-3}, G_{-n-1}, G_{n-1}; N: X = w W_n, Y = W_n),
+// stores them in LDS, and each thread adds the products of its outputs in
+// FP64.  There are E = B^2 - T^2 <= 576 outputs per (mu, n), at most
+// kEdgeAcc per thread.
 // Staging thread (e, item): centre e = tid mod 16 of the block and the
 // (array, bin) items tid / 16 + 16 u; the loads of block b + 1 are issued
 // before the products of block b.
@@ -541,7 +543,7 @@ constexpr int kEdgeMaxBins = 40;
 constexpr int kEdgeT = 32;
 constexpr int kEdgeBlk = 16;
 constexpr int kEdgeRow = kEdgeBlk + 1;  // LDS row (array, bin) of kEdgeBlk centres, padded
-constexpr int kEdgeAcc = (4 * (kEdgeMaxBins * kEdgeMaxBins - kEdgeT * kEdgeT) + 255) / 256;
+constexpr int kEdgeAcc = (5 * (kEdgeMaxBins * kEdgeMaxBins - kEdgeT * kEdgeT) + 255) / 256;
 
 // output e of one (mu, n) block -> (b1, b2): first the rows T..B-1 (every
 // column), then the columns T..B-1 of the rows 0..T-1
@@ -559,21 +561,23 @@ __device__ __forceinline__ void edge_output(int e, int B, int &b1, int &b2)
 }
 
 template <bool NK>
-__global__ __launch_bounds__(256) void k_contract_edge(ContractArgs a)
+__global__ __launch_bounds__(256, 2) void k_contract_edge(ContractArgs a)
 {
-    constexpr int NA = NK ? 2 : 6;  // complex operand arrays: X side, then Y side
+    // complex operand arrays: Upsilon X0..X2 (px), Y0..Y2 (py), then N's X (px)
+    // and Y (py); NK: N's X and Y only
+    constexpr int NA = NK ? 2 : 8;
     constexpr int NI = (NA * kEdgeMaxBins + 15) / 16;  // staging items per thread
     __shared__ float2 op[NA * kEdgeMaxBins * kEdgeRow];
     const int pairs = a.n_z * a.n_z;
     const int pair = (int)blockIdx.x % pairs, sl = (int)blockIdx.x / pairs;
-    const int n = blockIdx.y;
+    const int n = NK ? a.n_max + 1 + (int)blockIdx.y : (int)blockIdx.y;
     const int B = a.B, nm = a.n_max, tid = threadIdx.x;
     const float *px, *py;
     pair_planes(a, pair, px, py);
     const int i_begin = sl * a.slice;
     const int i_end = min(i_begin + a.slice, a.n_c);
     const int E = B * B - kEdgeT * kEdgeT;
-    const int nout = (NK ? 1 : 4) * E;
+    const int nout = (NK ? 1 : 5) * E;
     const unsigned KB = (unsigned)a.K * (unsigned)B;  // floats per plane
 
     // staging items: (array k, bin b) = kb / B, kb % B with kb = tid / 16 + 16 u
@@ -592,13 +596,14 @@ __global__ __launch_bounds__(256) void k_contract_edge(ContractArgs a)
                 pl = plane_w(n, nm);
             else
                 pl = k == 0 ? plane_g(n - 3, nm) : k == 1 ? plane_g(n - 1, nm) : k == 2 ? plane_g(-n - 1, nm)
-                   : k == 3 ? plane_g(-n - 3, nm) : k == 4 ? plane_g(-n - 1, nm) : plane_g(n - 1, nm);
+                   : k == 3 ? plane_g(-n - 3, nm) : k == 4 ? plane_g(-n - 1, nm) : k == 5 ? plane_g(n - 1, nm)
+                   : plane_w(n, nm);
             kbp[u] = 64 * k + b;
             off[u] = (unsigned)chunk_offset(pl, 0, b, a.K, B);
         }
     }
-    // this thread's outputs: LDS rows of X (bits 0-11) and Y (bits 12-23)
-    // and the conjugation of Y (bit 24)
+    // this thread's outputs: LDS rows of X (bits 0-12) and Y (bits 13-25)
+    // and the conjugation of Y (bit 26)
     int xyo[kEdgeAcc];
 #pragma unroll
     for (int k = 0; k < kEdgeAcc; ++k) {
@@ -608,10 +613,10 @@ __global__ __launch_bounds__(256) void k_contract_edge(ContractArgs a)
             const int mu = NK ? 4 : o / E;
             int b1, b2;
             edge_output(o % E, B, b1, b2);
-            const int ia = NK ? 0 : (mu == 3 ? 0 : mu);
-            const int ib = NK ? 1 : ((mu == 0 || mu == 2) ? 3 : (mu == 1 ? 4 : 5));
-            xyo[k] = (ia * kEdgeMaxBins + b1) * kEdgeRow | (ib * kEdgeMaxBins + b2) * kEdgeRow << 12 |
-                     (NK || mu == 3) << 24;
+            const int ia = NK ? 0 : (mu == 4 ? 6 : (mu == 3 ? 0 : mu));
+            const int ib = NK ? 1 : (mu == 4 ? 7 : ((mu == 0 || mu == 2) ? 3 : (mu == 1 ? 4 : 5)));
+            xyo[k] = (ia * kEdgeMaxBins + b1) * kEdgeRow | (ib * kEdgeMaxBins + b2) * kEdgeRow << 13 |
+                     (mu >= 3) << 26;
         }
     }
 
@@ -623,7 +628,9 @@ __global__ __launch_bounds__(256) void k_contract_edge(ContractArgs a)
         cw = a.ccw[ic];
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
-            const float *sp = (kbp[u] >> 6) < NA / 2 ? px : py;
+            const int k = kbp[u] >> 6;
+            const bool ysd = NK ? k == 1 : ((k >= 3 && k <= 5) || k == 7);
+            const float *sp = ysd ? py : px;
             g[u][0] = sp[off[u] + co];
             g[u][1] = sp[off[u] + co + KB];
         }
@@ -639,7 +646,7 @@ __global__ __launch_bounds__(256) void k_contract_edge(ContractArgs a)
                 ar = k == 0 ? cw.z : 1.0f;
                 ai = 0.0f;
             } else {
-                ar = k < 3 ? -cw.x : 1.0f;
+                ar = k < 3 ? -cw.x : (k == 6 ? cw.z : 1.0f);
                 ai = k < 3 ? (k == 1 ? cw.y : -cw.y) : 0.0f;
             }
             const float gr = g[u][0], gi = (!NK && k == 2) ? -g[u][1] : g[u][1];
@@ -661,8 +668,8 @@ __global__ __launch_bounds__(256) void k_contract_edge(ContractArgs a)
         for (int k = 0; k < kEdgeAcc; ++k) {
             if (tid + 256 * k < nout) {
                 double sr = 0.0, si = 0.0;
-                const float2 *xp = op + (xyo[k] & 4095), *yp = op + ((xyo[k] >> 12) & 4095);
-                const double ys = (xyo[k] >> 24) ? -1.0 : 1.0;
+                const float2 *xp = op + (xyo[k] & 8191), *yp = op + ((xyo[k] >> 13) & 8191);
+                const double ys = (xyo[k] >> 26) ? -1.0 : 1.0;
 #pragma unroll 4
                 for (int c = 0; c < kEdgeBlk; ++c) {
                     const float2 x = xp[c], y = yp[c];
@@ -999,8 +1006,10 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
     if (edge_bins(L.B)) {
         hipLaunchKernelGGL(k_contract_edge<false>, dim3((unsigned)(S * pairs), L.n_max + 1), blk, 0, s, a);
         T3_HIP_CHECK(hipGetLastError());
-        hipLaunchKernelGGL(k_contract_edge<true>, dim3((unsigned)(S * pairs), L.w_max + 1), blk, 0, s, a);
-        T3_HIP_CHECK(hipGetLastError());
+        if (L.w_max > L.n_max) {
+            hipLaunchKernelGGL(k_contract_edge<true>, dim3((unsigned)(S * pairs), L.w_max - L.n_max), blk, 0, s, a);
+            T3_HIP_CHECK(hipGetLastError());
+        }
     }
     if (jk) {
         hipLaunchKernelGGL(k_diag, dim3(L.B, n_z, kDiagSplit), dim3(256), 0, s, planes, zstride, a.ccw, n_c,
