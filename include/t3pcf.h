@@ -72,7 +72,8 @@ extern "C" {
 
 /* Precision of the contraction over centres (stage 2).  With 33 to 40   */
 /* radial bins, the outputs involving a bin index of 32 or more are      */
-/* summed in FP64 (products of the FP32 operands) in every precision.    */
+/* summed on the vector ALUs in FP32 runs of 16 centres promoted to FP64 */
+/* (the FP32 error model) in every precision.                            */
 #define T3_PREC_FP32 0    /* FP32 MFMA products, FP32 runs promoted to FP64 */
 #define T3_PREC_BF16X3 1  /* x = hi + lo in bf16; hi*hi + hi*lo + lo*hi for  */
                           /* Upsilon_0..3, FP32 for the normaliser N_n      */

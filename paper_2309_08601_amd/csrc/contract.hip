@@ -15,7 +15,8 @@
 // centres and one 32 x 32 tile of the B x B block (grid.y; one tile for
 // B <= 40, four for B = 41..64).  For B = 33..40 only the first tile runs on
 // MFMA: the outputs with a bin index of 32 or more (at most 8 rows and
-// columns) are summed by k_contract_edge on the vector ALUs in FP64, rather
+// columns) are summed by k_contract_edge on the vector ALUs (FP32 runs of
+// 16 centres promoted to FP64, as the FP32 MFMA runs), rather
 // than by three more MFMA tiles holding at most 8 real rows or columns each.
 // The operands the four products share (mu = 0
 // and 3 have the same X, mu = 0 and 2 the same Y) are formed once per block
@@ -533,8 +534,9 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
 // kEdgeBlk centres the workgroup forms the operands of every bin in FP32
 // with the arithmetic of the MFMA kernel (X = -c G_{n-3}, -c* G_{n-1},
 // -c conj G_{-n-1}; Y = G_{-n-3}, G_{-n-1}, G_{n-1}; N: X = w W_n, Y = W_n),
-// stores them in LDS, and each thread adds the products of its outputs in
-// FP64.  There are E = B^2 - T^2 <= 576 outputs per (mu, n), at most
+// stores them in LDS, and each thread sums the products of its outputs in
+// FP32 over the block and adds that run into FP64 accumulators (the error
+// model of the FP32 MFMA runs).  There are E = B^2 - T^2 <= 576 outputs per (mu, n), at most
 // kEdgeAcc per thread.
 // Staging thread (e, item): centre e = tid mod 16 of the block and the
 // (array, bin) items tid / 16 + 16 u; the loads of block b + 1 are issued
@@ -667,18 +669,18 @@ __global__ __launch_bounds__(256, 2) void k_contract_edge(ContractArgs a)
 #pragma unroll
         for (int k = 0; k < kEdgeAcc; ++k) {
             if (tid + 256 * k < nout) {
-                double sr = 0.0, si = 0.0;
+                float sr = 0.0f, si = 0.0f;
                 const float2 *xp = op + (xyo[k] & 8191), *yp = op + ((xyo[k] >> 13) & 8191);
-                const double ys = (xyo[k] >> 26) ? -1.0 : 1.0;
+                const float ys = (xyo[k] >> 26) ? -1.0f : 1.0f;
 #pragma unroll 4
                 for (int c = 0; c < kEdgeBlk; ++c) {
                     const float2 x = xp[c], y = yp[c];
-                    const double xr = x.x, xi = x.y, yr = y.x, yi = ys * (double)y.y;
-                    sr = fma(xr, yr, fma(-xi, yi, sr));
-                    si = fma(xr, yi, fma(xi, yr, si));
+                    const float yi = ys * y.y;
+                    sr = fmaf(x.x, y.x, fmaf(-x.y, yi, sr));
+                    si = fmaf(x.x, yi, fmaf(x.y, y.x, si));
                 }
-                accr[k] += sr;
-                acci[k] += si;
+                accr[k] += (double)sr;
+                acci[k] += (double)si;
             }
         }
         __syncthreads();

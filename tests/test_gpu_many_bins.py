@@ -47,10 +47,12 @@ def test_forward_40_bins(t3, prec, tol):
     _check(ups.cpu().numpy(), mp.pack_nonneg(o["ups"], o["N"], nm), tol, f"B=40 {prec}")
 
 
-@pytest.mark.parametrize("B,keep_jk", [(33, False), (64, True), (64, False)])
+@pytest.mark.parametrize("B,keep_jk", [(33, False), (37, True), (41, False), (64, True), (64, False)])
 def test_forward_33_and_64_bins(t3, B, keep_jk):
-    """One bin past a tile, and the largest plan (with and without the j = k
-    terms, which touch only the diagonal blocks of the tiles)."""
+    """One bin past a tile (edge bins on the vector ALUs), 37 bins with the
+    j = k terms kept (their diagonal entries 32-36 come from the edge sums),
+    41 bins (the first size with four MFMA tiles) and the largest plan (with
+    and without the j = k terms, which touch only the diagonal blocks)."""
     from oracle import multipole as mp
     cat = random_catalog(2500, 45.0, seed=4100 + B)
     edges = np.geomspace(0.5, 18.0, B + 1)
