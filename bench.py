@@ -395,7 +395,8 @@ def bench_tomo(t3, torch, dev):
 def bench_grad(t3, torch, dev):
     """500k galaxies in 7 deg x 7 deg, 15 bins 1'-60', n_max 20: forward and
     hand-written backward of the chi^2 loss of Gamma_n against a second-seed
-    target."""
+    target; the backward recomputing stage 1, and taking the planes the
+    forward kept (T3_FLAG_KEEP_PLANES)."""
     from paper_2309_08601_amd.synth import LATTICE_UNIT, WORKLOADS, make_catalogs
     wl = WORKLOADS["grad_500k"]
     cat = make_catalogs(wl)[0]
@@ -407,23 +408,27 @@ def bench_grad(t3, torch, dev):
     om = om.expand_as(T.real).contiguous()
     x = torch.from_numpy(cat.x).to(dev)
     y = torch.from_numpy(cat.y).to(dev)
+    plan_keep = t3.Plan(wl.edges(), wl.n_max, box_size=box, keep_planes=True)
     res = {}
-    for rep in range(2):
-        g1 = torch.from_numpy(cat.g1.copy()).to(dev).requires_grad_(True)
-        g2 = torch.from_numpy(cat.g2.copy()).to(dev).requires_grad_(True)
-        w = torch.from_numpy(cat.w.copy()).to(dev).requires_grad_(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        gam = torch.view_as_complex(t3.GammaMultipoles.apply(g1, g2, w, x, y, plan))
-        d = gam - T
-        L = torch.sum(om * (d.real ** 2 + d.imag ** 2))
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        L.backward()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        res = {"forward_s": t1 - t0, "backward_s": t2 - t1}
-    log(f"[bench] gradient: forward {res['forward_s']:.3f} s, backward {res['backward_s']:.3f} s")
+    for key, p in (("", plan), ("_kept", plan_keep)):
+        for rep in range(2):
+            g1 = torch.from_numpy(cat.g1.copy()).to(dev).requires_grad_(True)
+            g2 = torch.from_numpy(cat.g2.copy()).to(dev).requires_grad_(True)
+            w = torch.from_numpy(cat.w.copy()).to(dev).requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gam = torch.view_as_complex(t3.GammaMultipoles.apply(g1, g2, w, x, y, p))
+            d = gam - T
+            L = torch.sum(om * (d.real ** 2 + d.imag ** 2))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            L.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            res["forward" + key + "_s"] = t1 - t0
+            res["backward" + key + "_s"] = t2 - t1
+    log(f"[bench] gradient: forward {res['forward_s']:.3f} s, backward {res['backward_s']:.3f} s; with kept "
+        f"planes forward {res['forward_kept_s']:.3f} s, backward {res['backward_kept_s']:.3f} s")
     res["workload"] = ("grad_500k: 500000 galaxies in 420' x 420', 15 log bins 1'-60', n_max=20; "
                        "L = sum omega |Gamma_n - T|^2, dL/d(g1, g2, w) of every galaxy")
     return res

@@ -92,6 +92,15 @@ extern "C" {
 #define T3_FLAG_NO_LANE 16u /* stage 1: one wavefront per centre for every bin  */
                             /* (default: bins with at most 128 expected         */
                             /* neighbours per centre run one lane per centre)   */
+#define T3_FLAG_KEEP_PLANES 32u /* t3_forward over every galaxy of one catalog   */
+                                /* keeps the harmonic planes of every chunk      */
+                                /* (n x (4 n_max + 2 w_max + 15) x B floats of   */
+                                /* device memory, owned by the plan); the next   */
+                                /* t3_backward, if no other call has rebuilt the */
+                                /* plan's catalog in between and it is given the */
+                                /* same catalog (same pointers and n, contents   */
+                                /* unchanged), uses them instead of recomputing  */
+                                /* stage 1.                                      */
 
 typedef struct {
     int32_t n_bins;        /* 1 <= B <= 64                                   */
@@ -308,7 +317,10 @@ int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets,
                           const double *grad_gamma_n, double *grad_ups, void *stream);
 
 /* Adjoint of the non-tomographic forward pass over all galaxies of cat as
- * centres (hand-written; the harmonic sums are recomputed, not stored).
+ * centres (hand-written; the harmonic sums are recomputed, or, with
+ * T3_FLAG_KEEP_PLANES, taken from the planes the last t3_forward kept when
+ * it ran over this same catalog and no call rebuilt the plan's catalog
+ * since).
  * grad_ups: DEVICE, layout of the t3_forward output, holding dL/dRe and
  * dL/dIm of every Upsilon_{mu,n} and N_n entry (n >= 0).
  * grad_g1, grad_g2, grad_w: DEVICE float [cat->n], overwritten with dL/dg1,

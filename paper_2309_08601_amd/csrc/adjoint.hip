@@ -556,9 +556,18 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
     T3_TRY(plan->counter.reserve(sizeof(unsigned long long) * 4));
     T3_HIP_CHECK(hipMemsetAsync(plan->flag.ptr, 0, sizeof(int) * 4, s));
     SortedCatalog &sc = plan->cats[0];
-    T3_TRY(build_cells(plan, sc, cat, choose_grid(plan, cat.n), s));
-    T3_TRY(gather_sorted_centres(plan, sc, plan->centres, s));
-    T3_TRY(check_flag(plan, s, "t3_backward"));
+    // planes kept by the last forward over this very catalog: its sorted
+    // catalog, centres and chunk layout are still the plan's
+    const t3_catalog &kc = plan->kept_cat;
+    const bool kept = (plan->flags & T3_FLAG_KEEP_PLANES) && plan->kept_seq == plan->cells_seq &&
+                      kc.n == cat.n && kc.x == cat.x && kc.y == cat.y && kc.g1 == cat.g1 && kc.g2 == cat.g2 &&
+                      kc.w == cat.w && plan->kept_L.B == plan->B && plan->kept_L.n_max == plan->n_max;
+    CentreSet &cen = kept ? plan->csets[0] : plan->centres;
+    if (!kept) {
+        T3_TRY(build_cells(plan, sc, cat, choose_grid(plan, cat.n), s));
+        T3_TRY(gather_sorted_centres(plan, sc, plan->centres, s));
+        T3_TRY(check_flag(plan, s, "t3_backward"));
+    }
     const int64_t n = cat.n;
     if (n == 0) return T3_OK;
 
@@ -576,11 +585,12 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
     L.K = choose_chunk(plan, L);
     if (plan->chunk_req <= 0 && (int64_t)L.K > n)  // small catalogs, small buffers
         L.K = (int)std::max<int64_t>(256, ((int64_t)n + 255) & ~(int64_t)255);
+    if (kept) L = plan->kept_L;
     const int CS = coef_size(sv->cap);
     // scratch: nb_gc [2][n], nb_gw [n], cen_gc [2n], cen_gw [n]
     T3_TRY(plan->misc.reserve(sizeof(float) * 6 * (size_t)n));
     T3_TRY(plan->misc2.reserve(sizeof(float) * (size_t)L.K * L.B * CS));
-    T3_TRY(plan->chunk.reserve(sizeof(float) * L.floats()));
+    if (!kept) T3_TRY(plan->chunk.reserve(sizeof(float) * L.floats()));
     float *nb_gc = plan->misc.as<float>();
     float *nb_gw = nb_gc + 2 * n;
     float2 *cen_gc = reinterpret_cast<float2 *>(nb_gw + n);
@@ -597,18 +607,21 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
         T3_HIP_CHECK(hipFuncSetAttribute((const void *)k_adj_coef,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int n_lane = 0;
-    T3_TRY(lane_bins(plan, sc, 0, B, kLaneNeighbours, s, &n_lane));
+    if (!kept) T3_TRY(lane_bins(plan, sc, 0, B, kLaneNeighbours, s, &n_lane));
     for (int64_t c0 = 0; c0 < n; c0 += L.K) {
         const int nc = (int)((n - c0) < L.K ? (n - c0) : L.K);
-        T3_TRY(timing_mark(plan, 1, true, s));
-        const SortedCatalog *cl[1] = {&sc};
-        T3_TRY(scan_chunk(plan, cl, nullptr, 1, plan->centres, c0, nc, L, plan->chunk.as<float>(), 0, nullptr,
-                          plan->scan_mode, s, 0, B, n_lane));
-        T3_TRY(timing_mark(plan, 1, false, s));
+        const float *planes = kept ? plan->kept.as<float>() + (size_t)(c0 / L.K) * L.floats() : plan->chunk.as<float>();
+        if (!kept) {
+            T3_TRY(timing_mark(plan, 1, true, s));
+            const SortedCatalog *cl[1] = {&sc};
+            T3_TRY(scan_chunk(plan, cl, nullptr, 1, plan->centres, c0, nc, L, plan->chunk.as<float>(), 0, nullptr,
+                              plan->scan_mode, s, 0, B, n_lane));
+            T3_TRY(timing_mark(plan, 1, false, s));
+        }
         T3_TRY(timing_mark(plan, 2, true, s));
         CoefArgs ca{};
-        ca.planes = plan->chunk.as<float>();
-        ca.ccw = plan->centres.cw.as<float4>() + c0;
+        ca.planes = planes;
+        ca.ccw = cen.cw.as<float4>() + c0;
         ca.gups = grad_ups;
         ca.n_c = nc;
         ca.K = L.K;
@@ -628,7 +641,7 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
         sa.sw.ncw = sc.cw.as<float4>();
         sa.sw.cell_start = sc.cell_start.as<int>();
         sa.sw.g = sc.grid;
-        sa.cpos = plan->centres.pos.as<int2>() + c0;
+        sa.cpos = cen.pos.as<int2>() + c0;
         sa.coef = plan->misc2.as<float>();
         sa.n_c = nc;
         sa.B = B;

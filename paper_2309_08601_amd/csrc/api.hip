@@ -196,6 +196,13 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
     const bool jk = !(plan->flags & T3_FLAG_KEEP_JK);
     const bool timing = (plan->flags & T3_FLAG_TIMING) != 0;
     const bool graph = !timing && !(plan->flags & T3_FLAG_NO_GRAPH);
+    // every chunk's planes in a buffer of their own, for t3_backward
+    const bool keep = (plan->flags & T3_FLAG_KEEP_PLANES) && n_z == 1 && n_centres[0] < 0;
+    plan->kept_seq = -1;
+    if (keep) {
+        const int64_t n_chunks = (plan->csets[0].n + L.K - 1) / L.K;
+        T3_TRY(plan->kept.reserve(sizeof(float) * zstride * (size_t)std::max<int64_t>(n_chunks, 1)));
+    }
 
     auto schedule = [&](hipStream_t q) -> int {
         T3_TRY(zero_doubles(ups_out, n_out, q));
@@ -204,12 +211,13 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
             double *out = ups_out + per_set * (size_t)n_z * n_z * z1;
             for (int64_t c0 = 0; c0 < cs.n; c0 += L.K) {
                 const int n = (int)((cs.n - c0) < L.K ? (cs.n - c0) : L.K);
+                float *planes = keep ? plan->kept.as<float>() + (size_t)(c0 / L.K) * zstride : plan->chunk.as<float>();
                 T3_TRY(timing_mark(plan, 1, true, q));
-                T3_TRY(scan_chunk(plan, cl, order, n_z, cs, c0, n, L, plan->chunk.as<float>(), zstride,
+                T3_TRY(scan_chunk(plan, cl, order, n_z, cs, c0, n, L, planes, zstride,
                                   plan->counter.as<unsigned long long>(), plan->scan_mode, q, 0, plan->B, n_lane));
                 T3_TRY(timing_mark(plan, 1, false, q));
                 T3_TRY(timing_mark(plan, 2, true, q));
-                T3_TRY(contract_chunk(plan, cs, c0, n, L, plan->chunk.as<float>(), zstride, n_z, jk, out, q));
+                T3_TRY(contract_chunk(plan, cs, c0, n, L, planes, zstride, n_z, jk, out, q));
                 T3_TRY(timing_mark(plan, 2, false, q));
             }
         }
@@ -245,6 +253,11 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
     T3_HIP_CHECK(hipStreamSynchronize(s));
     T3_TRY(timing_end_call(plan));
     if (n_pairs) *n_pairs = (int64_t)pairs;
+    if (keep) {
+        plan->kept_L = L;
+        plan->kept_cat = cats[0];
+        plan->kept_seq = plan->cells_seq;
+    }
     return T3_OK;
 }
 
@@ -280,7 +293,8 @@ int t3_plan_create(const t3_params *p, t3_plan **out)
         if (p->n_max < 0 || p->n_max > 64) return fail(T3_ERANGE, "t3_plan_create: n_max must be in [0, 64]");
         if (p->precision < T3_PREC_FP32 || p->precision > T3_PREC_BF16X6)
             return fail(T3_EINVAL, "t3_plan_create: unknown precision");
-        if (p->flags & ~(T3_FLAG_KEEP_JK | T3_FLAG_TIMING | T3_FLAG_NO_GRAPH | T3_FLAG_EDGE_CORRECT | T3_FLAG_NO_LANE))
+        if (p->flags & ~(T3_FLAG_KEEP_JK | T3_FLAG_TIMING | T3_FLAG_NO_GRAPH | T3_FLAG_EDGE_CORRECT | T3_FLAG_NO_LANE |
+                         T3_FLAG_KEEP_PLANES))
             return fail(T3_EINVAL, "t3_plan_create: unknown flag");
         const double unit = p->lattice_unit == 0.0 ? std::ldexp(1.0, -16) : p->lattice_unit;
         if (!(unit > 0.0) || !std::isfinite(unit)) return fail(T3_EINVAL, "t3_plan_create: bad lattice unit");
@@ -346,6 +360,7 @@ void t3_plan_destroy(t3_plan *plan)
     plan->centres.pos.release();
     plan->centres.cw.release();
     plan->chunk.release();
+    plan->kept.release();
     plan->partial.release();
     plan->diag.release();
     plan->flag.release();

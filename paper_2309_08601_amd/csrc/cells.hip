@@ -208,6 +208,7 @@ CellGrid choose_grid(const t3_plan *plan, int64_t n_gal)
 int build_cells(t3_plan *plan, SortedCatalog &sc, const t3_catalog &cat, const CellGrid &g,
                 hipStream_t s)
 {
+    ++plan->cells_seq;  // invalidates planes kept by an earlier forward
     sc.n = cat.n;
     sc.grid = g;
     const int64_t n = cat.n;

@@ -167,6 +167,13 @@ struct t3_plan {
     t3::DevBuf misc2;
     t3::DevBuf sph_a, sph_b, sph_out;  // sphere patches: projection, compaction, per-patch output
     t3::GridLevel grid[t3::kMaxGridLevels];  // grid-based estimator, level l at grid[l - 1]
+    // T3_FLAG_KEEP_PLANES: stage-1 planes of every chunk of the last forward
+    // (chunk c at c * kept_L.floats()), valid while cells_seq == kept_seq
+    t3::DevBuf kept;
+    t3::ChunkLayout kept_L;
+    t3_catalog kept_cat{};
+    int64_t cells_seq = 0;   // build_cells calls on this plan
+    int64_t kept_seq = -1;
     int scan_var = -1;          // stage-1 variant index (see scan.hip)
     size_t scan_dest_off[3] = {0, 0, 0};  // main passes, then the W extension
 

@@ -30,6 +30,7 @@ T3_FLAG_TIMING = 2
 T3_FLAG_NO_GRAPH = 4
 T3_FLAG_EDGE_CORRECT = 8
 T3_FLAG_NO_LANE = 16
+T3_FLAG_KEEP_PLANES = 32
 
 
 class t3_params(ctypes.Structure):
@@ -176,7 +177,8 @@ class Plan:
     def __init__(self, edges: Sequence[float], n_max: int, box_lo=(0, 0), box_size: int = 1 << 30,
                  precision: str = "fp32", keep_jk: bool = False, lattice_unit: float = 0.0,
                  cell_arcmin: float = 0.0, chunk_centres: int = 0, timing: bool = False,
-                 graph: bool = True, scan_mode: int = 0, edge_correct: bool = False, lane: bool = True):
+                 graph: bool = True, scan_mode: int = 0, edge_correct: bool = False, lane: bool = True,
+                 keep_planes: bool = False):
         self.edges = np.ascontiguousarray(edges, dtype=np.float64)
         self.B = len(self.edges) - 1
         self.n_max = int(n_max)
@@ -186,7 +188,7 @@ class Plan:
                       PRECISIONS[precision],
                       (T3_FLAG_KEEP_JK if keep_jk else 0) | (T3_FLAG_TIMING if timing else 0)
                       | (0 if graph else T3_FLAG_NO_GRAPH) | (T3_FLAG_EDGE_CORRECT if edge_correct else 0)
-                      | (0 if lane else T3_FLAG_NO_LANE),
+                      | (0 if lane else T3_FLAG_NO_LANE) | (T3_FLAG_KEEP_PLANES if keep_planes else 0),
                       float(lattice_unit),
                       int(box_lo[0]), int(box_lo[1]), int(box_size), float(cell_arcmin),
                       int(chunk_centres), int(scan_mode))

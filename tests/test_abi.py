@@ -64,7 +64,7 @@ def _params(**kw):
     (dict(n_max=65), -2),
     (dict(n_max=-1), -2),
     (dict(precision=7), -1),
-    (dict(flags=32), -1),
+    (dict(flags=64), -1),
     (dict(box_size=0), -1),
     (dict(box_size=1 << 40), -2),
 ])

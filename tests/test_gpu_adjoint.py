@@ -68,7 +68,11 @@ def test_normalise_backward_matches_autograd(t3):
     assert torch.allclose(got, u.grad, rtol=1e-12, atol=1e-12)
 
 
-def test_backward_matches_fp64_autograd_oracle(t3):
+@pytest.mark.parametrize("keep", [False, True])
+def test_backward_matches_fp64_autograd_oracle(t3, keep):
+    """keep: the backward takes the planes the forward kept (three chunks of
+    512 centres, the last ragged; forward as a captured graph) instead of
+    recomputing stage 1."""
     from oracle import autodiff as ad
     cat = random_catalog(1500, 40.0, seed=501)
     tgt = random_catalog(1500, 40.0, seed=502)
@@ -86,7 +90,7 @@ def test_backward_matches_fp64_autograd_oracle(t3):
     Lr = ad.loss(ad.gamma(u, N), T, om)
     Lr.backward()
     lo, size = box_for(40.0)
-    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size, keep_planes=keep, chunk_centres=512 if keep else 0)
     L, _, d1, d2, dw = _gpu_loss_and_grad(t3, plan, cat, T, om)
     assert abs(float(L) - float(Lr)) < 1e-5 * float(Lr)
     for got, ref, name in ((d1, g1.grad, "g1"), (d2, g2.grad, "g2"), (dw, w.grad, "w")):
@@ -95,6 +99,46 @@ def test_backward_matches_fp64_autograd_oracle(t3):
         m = np.abs(got - ref).max() / np.abs(ref).max()
         print(f"grad {name}: rel-norm {e:.2e}, rel-max {m:.2e}", flush=True)
         assert e < 2e-5 and m < 1e-4, (name, e, m)
+
+
+def test_kept_planes_follow_the_catalog(t3):
+    """With kept planes the backward reuses the last forward's planes only
+    when it is given that forward's catalog and nothing rebuilt the plan's
+    catalog in between; otherwise it recomputes stage 1.  Gradients agree
+    with a plan that keeps nothing either way (to rounding: FP32 atomics)."""
+    rng = np.random.default_rng(7)
+    cats = [random_catalog(1200, 35.0, seed=s) for s in (601, 602)]
+    edges = np.geomspace(1.0, 10.0, 6)
+    nm = 6
+    lo, size = box_for(35.0)
+    keep = t3.Plan(edges, nm, box_lo=lo, box_size=size, keep_planes=True, chunk_centres=512, timing=True)
+    ref = t3.Plan(edges, nm, box_lo=lo, box_size=size, chunk_centres=512)
+    dA, dB = (t3.DeviceCatalog.from_catalog(c) for c in cats)
+    gups = torch.from_numpy(rng.standard_normal((5, nm + 1, 5, 5)) + 1j * rng.standard_normal((5, nm + 1, 5, 5)))
+    gups = gups.cuda()
+
+    def close(a, b):
+        for x, y in zip(a, b):
+            x, y = x.cpu().numpy(), y.cpu().numpy()
+            assert np.linalg.norm(x - y) <= 1e-5 * np.linalg.norm(y)
+
+    def stage1_launches():
+        return keep.stage_times()[1][1]
+
+    keep.forward(dA)
+    got = keep.backward(dA, gups)
+    assert stage1_launches() == 0
+    close(got, ref.backward(dA, gups))
+    keep.forward(dB)
+    got = keep.backward(dA, gups)  # kept planes are B's: recompute
+    assert stage1_launches() > 0
+    close(got, ref.backward(dA, gups))
+    got = keep.backward(dA, gups)  # the last call rebuilt the catalog: recompute
+    assert stage1_launches() > 0
+    keep.forward(dB)
+    got = keep.backward(dB, gups)
+    assert stage1_launches() == 0
+    close(got, ref.backward(dB, gups))
 
 
 def test_backward_largest_order_matches_fp64_autograd_oracle(t3):
