@@ -328,8 +328,8 @@ int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets,
  * FP32 atomics, so results can differ between calls at rounding level.
  * Synchronises the stream before returning. */
 /* (Not available for plans with T3_FLAG_EDGE_CORRECT: T3_EINVAL.  The
- * per-centre coefficient step holds B (3 n_max + 8) complex doubles in LDS:
- * above 160 KiB, i.e. n_max > 50 at B = 64, T3_ERANGE.) */
+ * per-centre coefficient step holds B (3 n_max + 8) complex floats in LDS,
+ * at most 101 KiB for B = n_max = 64.) */
 int t3_backward(t3_plan *plan, const t3_catalog *cat, const double *grad_ups,
                 float *grad_g1, float *grad_g2, float *grad_w, void *stream);
 

@@ -61,22 +61,26 @@ struct CoefArgs {
     float *cen_gw;         // [n_c] centre part of grad w
 };
 
-// One wavefront per centre.
+// One wavefront per centre.  The operands (FP32 planes) and the gradient
+// accumulators of the harmonics (a few terms each, stored as FP32
+// coefficients) are FP32 in LDS, 8 B (3 n_max + 8) per bin, so that LDS
+// leaves about four workgroups per SIMD; products and the sums over bins are
+// FP64.
 __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
 {
-    extern __shared__ double2 sm[];
+    extern __shared__ float2 sm[];
     const int B = a.B, nm = a.n_max;
     const int n_g = 2 * nm + 3;
-    double2 *Gb = sm;                     // [B][n_g]   index m + nm + 3
-    double2 *Wb = Gb + B * n_g;           // [B][nm+1]
-    double2 *Db = Wb + B * (nm + 1);      // [B][4]
-    double2 *Xs = Db + B * 4;             // [kMaxRadialBins]
-    double2 *Ys = Xs + kMaxRadialBins;    // [kMaxRadialBins]
+    float2 *Gb = sm;                      // [B][n_g]   index m + nm + 3
+    float2 *Wb = Gb + B * n_g;            // [B][nm+1]
+    float2 *Db = Wb + B * (nm + 1);       // [B][4]
+    float2 *Xs = Db + B * 4;              // [kMaxRadialBins]
+    float2 *Ys = Xs + kMaxRadialBins;     // [kMaxRadialBins]
     const int lane = threadIdx.x;
     const int i = blockIdx.x;
     if (i >= a.n_c) return;
     const int K = a.K;
-    for (int t = lane; t < B * (n_g + nm + 1 + 4); t += 64) sm[t] = make_double2(0.0, 0.0);
+    for (int t = lane; t < B * (n_g + nm + 1 + 4); t += 64) sm[t] = make_float2(0.0f, 0.0f);
 
     const float4 f = a.ccw[i];
     const double cr = f.x, ci = f.y, w = f.z;
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
             const int t = lane + 64 * r;
             if (t < 2 * B) {
                 const bool ty_side = t >= B;
-                (ty_side ? Ys : Xs)[ty_side ? t - B : t] = make_double2(pre[r][0], pre[r][1]);
+                (ty_side ? Ys : Xs)[ty_side ? t - B : t] = make_float2(pre[r][0], pre[r][1]);
             }
         }
         if (it + 1 < n_it) fetch(it + 1);  // in flight during this iteration
@@ -159,7 +163,8 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     if (k0 + q < B) {
-                        const double2 o = side_y ? Xs[k0 + q] : Ys[k0 + q];
+                        const float2 of = side_y ? Xs[k0 + q] : Ys[k0 + q];
+                        const double2 o = make_double2(of.x, of.y);
                         ur += ugr[q] * o.x + ugi[q] * o.y;  // Ub * conj(o)
                         ui += ugi[q] * o.x - ugr[q] * o.y;
                     }
@@ -170,7 +175,7 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
             double gr = ar * ur + ai * ui, gi = ar * ui - ai * ur;
             if (!side_y) {
                 // grad alpha += conj(X(b1)) u(b1)
-                const double2 x = Xs[b];
+                const double2 x = make_double2(Xs[b].x, Xs[b].y);
                 ga_r[mu] += x.x * ur + x.y * ui;
                 ga_i[mu] += x.x * ui - x.y * ur;
             }
@@ -185,8 +190,8 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
                     const int b = (lane & 31) + 32 * g;
                     if (b >= B) break;
                     const int m = side ? ym : xm;
-                    double2 *t = mu < 4 ? &Gb[b * n_g + (m + nm + 3)] : &Wb[b * (nm + 1) + n];
-                    *t = make_double2(t->x + gops[g].x, t->y + gops[g].y);
+                    float2 *t = mu < 4 ? &Gb[b * n_g + (m + nm + 3)] : &Wb[b * (nm + 1) + n];
+                    *t = make_float2((float)(t->x + gops[g].x), (float)(t->y + gops[g].y));
                 }
             }
             __syncthreads();
@@ -228,10 +233,10 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
         gD(2, r2, i2);
         gD(3, r3, i3);
         gD(4, r4, i4);
-        Db[bb * 4 + 0] = make_double2(r0, i0);
-        Db[bb * 4 + 1] = make_double2(r1, i1);
-        Db[bb * 4 + 2] = make_double2(r2 + r3, i2 + i3);
-        Db[bb * 4 + 3] = make_double2(r4, i4);
+        Db[bb * 4 + 0] = make_float2((float)r0, (float)i0);
+        Db[bb * 4 + 1] = make_float2((float)r1, (float)i1);
+        Db[bb * 4 + 2] = make_float2((float)(r2 + r3), (float)(i2 + i3));
+        Db[bb * 4 + 3] = make_float2((float)r4, (float)i4);
         auto sub = [&](int mu, double dr, double di) {
             ga_r[mu] -= dr * dsum_r[mu] + di * dsum_i[mu];
             ga_i[mu] -= dr * dsum_i[mu] - di * dsum_r[mu];
@@ -271,26 +276,26 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
         if (k < 4 * M) {
             const int m = k / 4 + 1, q = k % 4;
             double2 gp = make_double2(0.0, 0.0), gm = make_double2(0.0, 0.0);
-            if (m <= nm - 1) gp = Gb[bb * n_g + (m + nm + 3)];
-            if (m <= nm + 3) gm = Gb[bb * n_g + (-m + nm + 3)];
+            if (m <= nm - 1) gp = make_double2(Gb[bb * n_g + (m + nm + 3)].x, Gb[bb * n_g + (m + nm + 3)].y);
+            if (m <= nm + 3) gm = make_double2(Gb[bb * n_g + (-m + nm + 3)].x, Gb[bb * n_g + (-m + nm + 3)].y);
             // s = gp + gm ; d = i (gm - gp) = (-(gm.y - gp.y), gm.x - gp.x)
             const double val = q == 0 ? gp.x + gm.x : q == 1 ? gp.y + gm.y
                              : q == 2 ? -(gm.y - gp.y) : (gm.x - gp.x);
             v = (float)val;
         } else if (k < 4 * M + 2) {
             if (nm >= 1) {
-                const double2 g0 = Gb[bb * n_g + (nm + 3)];
+                const float2 g0 = Gb[bb * n_g + (nm + 3)];
                 v = (float)(k == 4 * M ? g0.x : g0.y);
             }
         } else if (k < 4 * M + 2 + 2 * (C + 1)) {
             const int kk = k - 4 * M - 2, m = kk / 2;
             if (m <= nm) {
-                const double2 wv = Wb[bb * (nm + 1) + m];
+                const float2 wv = Wb[bb * (nm + 1) + m];
                 v = (float)(kk % 2 == 0 ? wv.x : wv.y);
             }
         } else {
             const int kk = k - 4 * M - 2 - 2 * (C + 1);  // 0..6
-            const double2 d = Db[bb * 4 + (kk < 6 ? kk / 2 : 3)];
+            const float2 d = Db[bb * 4 + (kk < 6 ? kk / 2 : 3)];
             v = (float)(kk == 6 ? d.x : (kk % 2 == 0 ? d.x : d.y));
         }
         a.coef[((size_t)i * B + bb) * CS + k] = v;
@@ -600,8 +605,8 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
     T3_HIP_CHECK(hipGetLastError());
     const bool jk = !(plan->flags & T3_FLAG_KEEP_JK);
     const int B = plan->B, nm = plan->n_max;
-    const size_t lds = sizeof(double2) * ((size_t)B * ((2 * nm + 3) + (nm + 1) + 4) + 2 * kMaxRadialBins);
-    if (lds > 160 * 1024)  // a workgroup's LDS limit on gfx950 (B = 64 allows n_max <= 50)
+    const size_t lds = sizeof(float2) * ((size_t)B * ((2 * nm + 3) + (nm + 1) + 4) + 2 * kMaxRadialBins);
+    if (lds > 160 * 1024)  // a workgroup's LDS limit on gfx950 (B = n_max = 64 needs 101 KiB)
         return fail(T3_ERANGE, "t3_backward: n_bins (3 n_max + 8) above the coefficient kernel's LDS");
     if (lds > 64 * 1024)
         T3_HIP_CHECK(hipFuncSetAttribute((const void *)k_adj_coef,

@@ -224,3 +224,44 @@ def test_forward_33_bins_split_precision(t3, prec, tol):
     en = max(np.linalg.norm(n_got[k] - n_ref[k]) / n0 for k in range(2 * nm + 1))
     print(f"B=33 {prec}: Upsilon {e.max():.2e}, N_n/N_0 {en:.2e}", flush=True)
     assert e.max() <= tol and en <= FP32_TOL
+
+
+def test_adjoint_64_bins_large_order(t3):
+    """64 bins at n_max = 40: the coefficient step's LDS (64 KiB and more)
+    needs the raised dynamic-LDS limit; gradient against the FP64 autograd
+    oracle, with the planes kept by the forward."""
+    from oracle import autodiff as ad
+    cat = random_catalog(700, 30.0, seed=4801)
+    tgt = random_catalog(700, 30.0, seed=4802)
+    edges = np.geomspace(0.8, 12.0, 65)
+    nm = 40
+    pl = ad.pairs(cat.x, cat.y, edges)
+    t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))  # noqa: E731
+    uT, NT = ad.multipoles(tgt.x, tgt.y, t(tgt.g1), t(tgt.g2), t(tgt.w), edges, nm)
+    T = ad.gamma(uT, NT).detach()
+    om = ad.loss_weights(T)
+    g1 = t(cat.g1).requires_grad_(True)
+    g2 = t(cat.g2).requires_grad_(True)
+    w = t(cat.w).requires_grad_(True)
+    u, N = ad.multipoles(cat.x, cat.y, g1, g2, w, edges, nm, pair_list=pl)
+    Lr = ad.loss(ad.gamma(u, N), T, om)
+    Lr.backward()
+    lo, size = box_for(30.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size, keep_planes=True)
+    dev = "cuda"
+    x = torch.from_numpy(cat.x).to(dev)
+    y = torch.from_numpy(cat.y).to(dev)
+    q1 = torch.from_numpy(cat.g1.copy()).to(dev).requires_grad_(True)
+    q2 = torch.from_numpy(cat.g2.copy()).to(dev).requires_grad_(True)
+    qw = torch.from_numpy(cat.w.copy()).to(dev).requires_grad_(True)
+    gam = torch.view_as_complex(t3.GammaMultipoles.apply(q1, q2, qw, x, y, plan))
+    d = gam - T.to(dev)
+    L = torch.sum(om.to(dev) * (d.real ** 2 + d.imag ** 2))
+    L.backward()
+    assert abs(float(L) - float(Lr)) < 1e-5 * float(Lr)
+    for got, ref, name in ((q1.grad, g1.grad, "g1"), (q2.grad, g2.grad, "g2"), (qw.grad, w.grad, "w")):
+        got = got.cpu().numpy()
+        ref = ref.numpy()
+        e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"B=64 n_max=40 grad {name}: rel-norm {e:.2e}", flush=True)
+        assert e < 2e-5, (name, e)
