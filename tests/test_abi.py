@@ -79,10 +79,13 @@ def test_plan_create_rejects(lib, kw, code):
     assert len(t3._lib.t3_last_error_message()) > 0
 
 
-def test_plan_create_and_destroy_ok(lib):
+@pytest.mark.parametrize("flags", [0, 1 | 16, 32, 1 | 2 | 4 | 8 | 16 | 32])
+def test_plan_create_and_destroy_ok(lib, flags):
+    """Every defined flag bit, alone and together (keep j = k, timing, no
+    graph, edge correction, no lane kernel, keep planes)."""
     pytest.importorskip("torch")
     from paper_2309_08601_amd import t3
-    p, edges = _params()
+    p, edges = _params(flags=flags)
     h = ctypes.c_void_p()
     assert t3._lib.t3_plan_create(ctypes.byref(p), ctypes.byref(h)) == 0
     assert h.value
