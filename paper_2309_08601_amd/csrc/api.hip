@@ -188,7 +188,9 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
     const size_t n_out = per_set * (size_t)n_z * n_z * n_z;
     const size_t zstride = L.floats();
     // every buffer the schedule touches is reserved before it is recorded
-    T3_TRY(plan->chunk.reserve(sizeof(float) * zstride * (size_t)n_z));
+    // (with kept planes the chunk buffer is not used)
+    const bool keep = (plan->flags & T3_FLAG_KEEP_PLANES) && n_z == 1 && n_centres[0] < 0;
+    if (!keep) T3_TRY(plan->chunk.reserve(sizeof(float) * zstride * (size_t)n_z));
     T3_TRY(reserve_contract(plan, L, n_z));
     T3_TRY(plan->queue.reserve(sizeof(unsigned) * 4));
     const SortedCatalog *cl[8];
@@ -197,7 +199,6 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
     const bool timing = (plan->flags & T3_FLAG_TIMING) != 0;
     const bool graph = !timing && !(plan->flags & T3_FLAG_NO_GRAPH);
     // every chunk's planes in a buffer of their own, for t3_backward
-    const bool keep = (plan->flags & T3_FLAG_KEEP_PLANES) && n_z == 1 && n_centres[0] < 0;
     plan->kept_seq = -1;
     if (keep) {
         const int64_t n_chunks = (plan->csets[0].n + L.K - 1) / L.K;
