@@ -30,11 +30,17 @@ def _bin_of(r2: np.ndarray, e2: np.ndarray) -> np.ndarray:
 
 def triplets(x, y, g1, g2, w, edges: Sequence[float], n_max: int,
              phi_edges: Optional[np.ndarray] = None, in_lattice_units: bool = True,
-             phi_weight=None):
+             phi_weight=None, labels=None, roles=None):
     """Returns dict(ups[4, 2n_max+1, B, B], N[2n_max+1, B, B]) and, when
     phi_edges is given, the angularly binned sums ups_phi[4, B, B, K],
     N_phi[B, B, K] (eqs. TripletUpsilon, TripletNorm).  ``phi_weight(psi)``
-    (-> [T, K]) replaces the bin indicator of psi by arbitrary weights."""
+    (-> [T, K]) replaces the bin indicator of psi by arbitrary weights.
+
+    Tomography (Sect. 3.5, eq. tomoGn): with per-galaxy source-bin
+    ``labels`` and ``roles = (z1, z2, z3)``, only the triplets whose vertex
+    X_1 (galaxy i, the centre) lies in bin z1, whose vertex X_2 (galaxy j,
+    at separation theta_ij in radial bin b1) lies in z2 and whose vertex X_3
+    (galaxy k, theta_ik in b2) lies in z3 are summed."""
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     gc = np.asarray(g1, dtype=np.float64) + 1j * np.asarray(g2, dtype=np.float64)
@@ -52,21 +58,27 @@ def triplets(x, y, g1, g2, w, edges: Sequence[float], n_max: int,
     if K is not None:
         ups_phi = np.zeros((4, B, B, K), dtype=np.complex128)
         N_phi = np.zeros((B, B, K), dtype=np.float64)
+    if (labels is None) != (roles is None):
+        raise ValueError("labels and roles go together")
+    lab = None if labels is None else np.asarray(labels)
     for i in range(n):
+        if lab is not None and lab[i] != roles[0]:
+            continue
         dx = x - x[i]
         dy = y - y[i]
         b = _bin_of(dx * dx + dy * dy, e2)
-        sel = np.nonzero(b >= 0)[0]
-        if sel.size < 2:
+        inb = b >= 0
+        sel_j = np.nonzero(inb if lab is None else inb & (lab == roles[1]))[0]
+        sel_k = np.nonzero(inb if lab is None else inb & (lab == roles[2]))[0]
+        if sel_j.size == 0 or sel_k.size == 0:
             continue
-        phi = np.arctan2(dy[sel], dx[sel])
-        bs = b[sel]
-        J, Kk = np.meshgrid(np.arange(sel.size), np.arange(sel.size), indexing="ij")
-        keep = J != Kk
-        J, Kk = J[keep], Kk[keep]
-        j, k = sel[J], sel[Kk]
-        p1, p2 = phi[J], phi[Kk]
-        b1, b2 = bs[J], bs[Kk]
+        J, Kk = np.meshgrid(sel_j, sel_k, indexing="ij")
+        keep = J != Kk                      # pairwise distinct: j != k
+        j, k = J[keep], Kk[keep]
+        if j.size == 0:
+            continue
+        p1, p2 = np.arctan2(dy[j], dx[j]), np.arctan2(dy[k], dx[k])
+        b1, b2 = b[j], b[k]
         # projected, weighted shears gamma(X; zeta) = -gamma_c e^{-2 i zeta}
         e_z1 = np.exp(-1j * (p1 + p2))       # e^{-2 i zeta_1}
         e_z2 = np.exp(-2j * p1)

@@ -242,8 +242,6 @@ def test_tomographic_linearity(oracle_lib):
     u = mp.multipoles(union, edges, 5)
     assert _rel(t["ups"].sum(axis=(0, 1, 2)), u["ups"]) < 1e-12
     assert _rel(t["N"].sum(axis=(0, 1, 2)), u["N"]) < 1e-12
-    # each triple against brute force on the union restricted by bin labels
-    lab = np.concatenate([np.full(c.n, z) for z, c in enumerate(cats)])
     assert t["ups"].shape[:3] == (3, 3, 3)
     # swapping Z2 <-> Z3 with n -> -n and b1 <-> b2 (Appendix A symmetries)
     for z1 in range(3):
@@ -252,7 +250,37 @@ def test_tomographic_linearity(oracle_lib):
                 for n in range(6):
                     assert _rel(t["ups"][z1, z2, z3, 0, 5 - n], t["ups"][z1, z3, z2, 0, 5 + n].T) < 1e-11
                     assert _rel(t["ups"][z1, z2, z3, 2, 5 - n], t["ups"][z1, z3, z2, 3, 5 + n].T) < 1e-11
-    del lab
+
+
+def test_tomographic_roles_against_bruteforce(oracle_lib):
+    """Every ordered triple (Z1, Z2, Z3) of the tomographic oracle equals the
+    O(N^3) triplet sum over the union catalog restricted by source-bin labels:
+    centre i in Z1, vertex j (theta_ij in Theta_1) in Z2, vertex k
+    (theta_ik in Theta_2) in Z3 (eq. tomoGn).  The sum over all triples and
+    the Z2 <-> Z3 symmetry both hold with the roles of Z2 and Z3 swapped;
+    this comparison does not, which the last assertions demonstrate."""
+    cats = [random_catalog(n, 16.0, seed=40 + z) for z, n in enumerate([26, 34, 30])]
+    # distinct signal per bin: one bin carries a constant shear on top of
+    # its noise, so exchanging the b1-side and b2-side catalogs changes Upsilon
+    c1 = cats[1]
+    cats[1] = Catalog(c1.x, c1.y, (c1.g1 + 0.6).astype(np.float32), c1.g2, c1.w)
+    edges = np.geomspace(1.0, 8.0, 4)
+    nm = 4
+    t = mp.multipoles_tomo(cats, edges, nm)
+    lab = np.concatenate([np.full(c.n, z) for z, c in enumerate(cats)])
+    cat = lambda f: np.concatenate([getattr(c, f) for c in cats])  # noqa: E731
+    x, y, g1, g2, w = (cat(f) for f in ("x", "y", "g1", "g2", "w"))
+    worst_swapped = 0.0
+    for z1 in range(3):
+        for z2 in range(3):
+            for z3 in range(3):
+                o0 = brute.triplets(x, y, g1, g2, w, edges, nm, labels=lab, roles=(z1, z2, z3))
+                for mu in range(4):
+                    assert _rel(t["ups"][z1, z2, z3, mu], o0["ups"][mu]) < 1e-12, (z1, z2, z3, mu)
+                assert _rel(t["N"][z1, z2, z3], o0["N"]) < 1e-12, (z1, z2, z3)
+                if z2 != z3:
+                    worst_swapped = max(worst_swapped, _rel(t["ups"][z1, z3, z2, 0], o0["ups"][0]))
+    assert worst_swapped > 1e-2
 
 
 def _fourier_kernel(n_max, phi_edges):
@@ -520,6 +548,62 @@ def test_aperture_statistics_parity_and_linear_algebra():
     g = 0.5 * (g + np.conj(g[..., ::-1]))  # phi_k <-> 2 pi - phi_k
     st = aperture_stats(correlators(g, edges, pe, [(2.0, 2.0, 2.0), (1.5, 1.5, 1.5)]))
     assert np.max(np.abs(st[:, [1, 2, 3, 7]])) < 1e-12 * np.max(np.abs(st))
+
+
+def _smooth_gamma_cent(t1, t2, phi):
+    """A smooth, b1/b2-asymmetric test function for the four Gamma^cent_mu.
+    The factor P^2 (P = |q_1|^2 |q_2|^2 |q_3|^2) cancels the bounded but
+    direction-dependent behaviour of the filters where a centroid vector
+    vanishes, so the integrand is smooth and every quadrature rule converges
+    at its textbook order."""
+    from oracle.aperture import q_vectors
+    q = q_vectors(t1, t2, phi)
+    P = np.abs(q[0]) ** 2 * np.abs(q[1]) ** 2 * np.abs(q[2]) ** 2
+    base = (t1 * np.exp(-t1 / 2.5) * t2 ** 2 * np.exp(-t2 / 3.5)
+            * (1 + 0.6 * np.cos(phi) + 0.3j * np.sin(2 * phi) + 0.2 * np.cos(3 * phi + 0.4)))
+    return np.stack([(1 + 0.25 * mu + 0.5j) * (1 + 0.1 * mu * t1) * base * P ** 2 for mu in range(4)])
+
+
+def test_aperture_quadrature_converges_to_independent_integral():
+    """The correlators of eqs. MFrom3pcfTheory / MFrom3pcfTheoryb,
+    integral over (vartheta_1, vartheta_2, phi) of Gamma^cent_mu F_mu, as the
+    oracle computes them (midpoint rule on radial and angular bins) against
+    an independent rule: Gauss-Legendre in both radii and the periodic
+    trapezoid in phi, for an analytic Gamma^cent and asymmetric apertures.
+    The midpoint error must fall as h^2 (ratio 4 per halving), its Richardson
+    extrapolation must reach the independent integral, log-spaced bins must
+    converge to it too, and the transposed input (b1 <-> b2) must not: a
+    scale factor, a wrong bin-width weight or a transposition fails here."""
+    from oracle.aperture import correlators, filters
+    lo, hi = 0.3, 14.0
+    aps = [(1.1, 1.7, 2.4), (2.0, 1.3, 1.6)]
+    x, wt = np.polynomial.legendre.leggauss(96)
+    t = 0.5 * (hi - lo) * x + 0.5 * (hi + lo)
+    wt = wt * 0.5 * (hi - lo)
+    nphi = 96
+    ph = 2 * np.pi * (np.arange(nphi) + 0.5) / nphi
+    T1, T2, PH = np.meshgrid(t, t, ph, indexing="ij")
+    wq = wt[:, None, None] * wt[None, :, None] * (2 * np.pi / nphi)
+    g = _smooth_gamma_cent(T1, T2, PH)
+    ref = np.array([np.sum(g * filters(T1, T2, PH, *a) * wq[None], axis=(1, 2, 3)) for a in aps])
+
+    def midpoint(edges, K, transpose=False):
+        pe = 2 * np.pi * np.arange(K + 1) / K
+        tc = 0.5 * (edges[:-1] + edges[1:])
+        pc = 0.5 * (pe[:-1] + pe[1:])
+        A, Bm, C = np.meshgrid(tc, tc, pc, indexing="ij")
+        gm = _smooth_gamma_cent(A, Bm, C)
+        if transpose:
+            gm = np.swapaxes(gm, 1, 2)
+        return correlators(gm, edges, pe, aps)
+
+    rel = lambda c: np.abs(c - ref).max() / np.abs(ref).max()  # noqa: E731
+    c = [midpoint(np.linspace(lo, hi, n + 1), n) for n in (24, 48, 96)]
+    e = [rel(v) for v in c]
+    assert 3.6 < e[0] / e[1] < 4.4 and 3.6 < e[1] / e[2] < 4.4, e
+    assert rel((4 * c[2] - c[1]) / 3) < 2e-6
+    assert rel(midpoint(np.geomspace(lo, hi, 97), 96)) < 5e-3
+    assert rel(midpoint(np.linspace(lo, hi, 97), 96, transpose=True)) > 1e-1
 
 
 def test_sphere_rotation_and_shear_transport():
