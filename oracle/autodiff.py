@@ -44,9 +44,13 @@ def pairs(x: np.ndarray, y: np.ndarray, edges: Sequence[float], chunk: int = 204
 
 
 def multipoles(x, y, g1: torch.Tensor, g2: torch.Tensor, w: torch.Tensor, edges, n_max: int,
-               pair_list=None, diag: bool = True):
+               pair_list=None, diag: bool = True, centres=None):
     """Upsilon [4, n_max+1, B, B] and N [n_max+1, B, B] (orders n >= 0),
-    complex128, differentiable in g1, g2, w (float64 tensors)."""
+    complex128, differentiable in g1, g2, w (float64 tensors).
+
+    ``centres`` (indices, optional): the sum over centres i of
+    eq. Upsilon0_Derivation taken over that set only (an index listed twice
+    counts twice); every galaxy remains a neighbour."""
     B = len(edges) - 1
     n = int(g1.shape[0])
     I, J, Bn, DX, DY = pair_list if pair_list is not None else pairs(x, y, edges)
@@ -72,8 +76,13 @@ def multipoles(x, y, g1: torch.Tensor, g2: torch.Tensor, w: torch.Tensor, edges,
     G = G.reshape(n, B, -1)
     W = W.reshape(n, B, -1)
     gi = lambda m: m - m_lo  # noqa: E731
-    a = c
-    ac = torch.conj(c)
+    if centres is None:
+        sel = torch.ones(n, dtype=torch.float64)
+    else:
+        sel = torch.zeros(n, dtype=torch.float64).index_add(
+            0, torch.as_tensor(np.asarray(centres, dtype=np.int64)), torch.ones(len(centres), dtype=torch.float64))
+    a = c * sel
+    ac = torch.conj(c) * sel
     ups = []
     for nn in range(n_max + 1):
         u0 = -torch.einsum("i,ia,ib->ab", a, G[:, :, gi(nn - 3)], G[:, :, gi(-nn - 3)])
@@ -82,7 +91,7 @@ def multipoles(x, y, g1: torch.Tensor, g2: torch.Tensor, w: torch.Tensor, edges,
         u3 = -torch.einsum("i,ia,ib->ab", a, G[:, :, gi(nn - 3)], torch.conj(G[:, :, gi(nn - 1)]))
         ups.append(torch.stack([u0, u1, u2, u3]))
     ups = torch.stack(ups, dim=1)  # [4, n_max+1, B, B]
-    wc = w.to(torch.complex128)
+    wc = (w * sel).to(torch.complex128)
     N = torch.stack([torch.einsum("i,ia,ib->ab", wc, W[:, :, k], torch.conj(W[:, :, k]))
                      for k in range(n_max + 1)])
     if diag:

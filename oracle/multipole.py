@@ -129,6 +129,12 @@ def harmonics(cen: Catalog, nb: Catalog, edges: Sequence[float], n_max: int,
     return dict(G=to_c(G), W=to_c(W), D=to_c(D), npairs=npairs, m_lo=m_lo, w_max=w_max)
 
 
+def _centre_sum(a: np.ndarray, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """sum_i a_i X[i, b1] Y[i, b2] -> [b1, b2], the sum over centres of
+    eq. Upsilon0_Derivation, as one matrix product (a X)^T Y."""
+    return (a[:, None] * X).T @ Y
+
+
 def upsilon_from_harmonics(c_cen: np.ndarray, w_cen: np.ndarray, h1: dict, h2: dict, n_max: int,
                            diag: bool = True):
     """Upsilon_{mu,n} and N_n for every |n| <= n_max (N for |n| <= w_max).
@@ -150,15 +156,14 @@ def upsilon_from_harmonics(c_cen: np.ndarray, w_cen: np.ndarray, h1: dict, h2: d
     ups = np.zeros((4, 2 * n_max + 1, B, B), dtype=np.complex128)
     for n in range(-n_max, n_max + 1):
         k = n + n_max
-        ups[0, k] = -np.einsum("i,ia,ib->ab", a, G1[:, :, gi(n - 3)], G2[:, :, gi(-n - 3)])
-        ups[1, k] = -np.einsum("i,ia,ib->ab", ac, G1[:, :, gi(n - 1)], G2[:, :, gi(-n - 1)])
-        ups[2, k] = -np.einsum("i,ia,ib->ab", a, np.conj(G1[:, :, gi(-n - 1)]), G2[:, :, gi(-n - 3)])
-        ups[3, k] = -np.einsum("i,ia,ib->ab", a, G1[:, :, gi(n - 3)], np.conj(G2[:, :, gi(n - 1)]))
+        ups[0, k] = -_centre_sum(a, G1[:, :, gi(n - 3)], G2[:, :, gi(-n - 3)])
+        ups[1, k] = -_centre_sum(ac, G1[:, :, gi(n - 1)], G2[:, :, gi(-n - 1)])
+        ups[2, k] = -_centre_sum(a, np.conj(G1[:, :, gi(-n - 1)]), G2[:, :, gi(-n - 3)])
+        ups[3, k] = -_centre_sum(a, G1[:, :, gi(n - 3)], np.conj(G2[:, :, gi(n - 1)]))
     N = np.zeros((2 * w_max + 1, B, B), dtype=np.complex128)
     wc = w_cen.astype(np.float64)
     for n in range(-w_max, w_max + 1):
-        N[n + w_max] = np.einsum("i,ia,ib->ab", wc, W1[:, :, n + h1["w_max"]],
-                                 np.conj(W2[:, :, n + h2["w_max"]]))
+        N[n + w_max] = _centre_sum(wc, W1[:, :, n + h1["w_max"]], np.conj(W2[:, :, n + h2["w_max"]]))
     if diag:
         D = h1["D"]
         idx = np.arange(B)
