@@ -101,6 +101,13 @@ extern "C" {
                                 /* same catalog (same pointers and n, contents   */
                                 /* unchanged), uses them instead of recomputing  */
                                 /* stage 1.                                      */
+#define T3_FLAG_DETERMINISTIC 64u /* t3_backward: neighbour gradient terms are   */
+                                  /* summed as 64-bit fixed-point integers (one  */
+                                  /* power-of-two scale per centre chunk, set    */
+                                  /* from a bound on that chunk's terms) and the */
+                                  /* chunks in FP64 in a fixed order, so the     */
+                                  /* gradients are bitwise reproducible.  The    */
+                                  /* forward pass is always reproducible.        */
 
 typedef struct {
     int32_t n_bins;        /* 1 <= B <= 64                                   */
@@ -119,6 +126,12 @@ typedef struct {
                            /* launch per neighbour catalog; 1 one persistent  */
                            /* launch over all (centre, catalog) tasks with a  */
                            /* work queue                                      */
+    int64_t max_workspace_bytes; /* >= 0; 0 = no limit.  Upper bound on the    */
+                           /* device memory the plan holds at any time (the   */
+                           /* sum of its internal buffers, checked before     */
+                           /* each allocation).  A call that would exceed it  */
+                           /* returns T3_ENOMEM without allocating; see       */
+                           /* t3_workspace_bytes.                             */
 } t3_params;
 
 typedef struct {
@@ -159,6 +172,17 @@ int t3_plan_create(const t3_params *params, t3_plan **out);
 
 /* Release the plan and its workspace (synchronises the device first). */
 void t3_plan_destroy(t3_plan *plan);
+
+/* Device memory the plan currently holds (in_use, HOST, optional) and the
+ * largest amount it has held (peak, HOST, optional), in bytes; never more
+ * than params.max_workspace_bytes when that is set.  Buffers grow on demand
+ * and are kept until t3_plan_destroy, so the peak of a fresh plan after one
+ * call is what that call needs: a plan created with that limit runs the
+ * same call without T3_ENOMEM.  A call refused for the limit returns
+ * T3_ENOMEM before the allocation it would need; t3_forward,
+ * t3_forward_tomo and t3_backward then have launched nothing that writes
+ * their outputs. */
+int t3_workspace_bytes(const t3_plan *plan, int64_t *in_use, int64_t *peak);
 
 /* Non-tomographic forward pass (Sect. 3.1, eq. Upsilon0_Derivation).
  * cat:       the neighbour catalog; centres are drawn from the same catalog.
@@ -316,22 +340,31 @@ int t3_aperture_stats(t3_plan *plan, const double *gamma_phi_cent, int32_t n_set
 int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets,
                           const double *grad_gamma_n, double *grad_ups, void *stream);
 
-/* Adjoint of the non-tomographic forward pass over all galaxies of cat as
- * centres (hand-written; the harmonic sums are recomputed, or, with
- * T3_FLAG_KEEP_PLANES, taken from the planes the last t3_forward kept when
- * it ran over this same catalog and no call rebuilt the plan's catalog
- * since).
+/* Adjoint of the non-tomographic forward pass (hand-written; the harmonic
+ * sums are recomputed, or, with T3_FLAG_KEEP_PLANES and every galaxy as a
+ * centre, taken from the planes the last t3_forward over all centres kept
+ * when it ran over this same catalog and no call rebuilt the plan's
+ * catalog since).  The multilinear structure of eq. (Upsilon0_Derivation):
+ * each galaxy enters as a centre factor and, linearly, in the harmonic sums
+ * of its neighbours.
+ * centres, n_centres: the centre set of the forward pass, with the
+ *   t3_forward convention (n_centres < 0: every galaxy, centres NULL;
+ *   0: none, the gradients are 0).  Gradients still reach every galaxy
+ *   that is a neighbour of a listed centre (a centre shard of the forward
+ *   pass has the adjoint of that shard).
  * grad_ups: DEVICE, layout of the t3_forward output, holding dL/dRe and
  * dL/dIm of every Upsilon_{mu,n} and N_n entry (n >= 0).
  * grad_g1, grad_g2, grad_w: DEVICE float [cat->n], overwritten with dL/dg1,
  * dL/dg2, dL/dw of every galaxy.  Neighbour contributions are summed with
- * FP32 atomics, so results can differ between calls at rounding level.
+ * FP32 atomics, so results can differ between calls at rounding level,
+ * unless the plan has T3_FLAG_DETERMINISTIC (then they are bitwise
+ * reproducible for a centre list without repeated indices).
  * Synchronises the stream before returning. */
 /* (Not available for plans with T3_FLAG_EDGE_CORRECT: T3_EINVAL.  The
  * per-centre coefficient step holds B (3 n_max + 8) complex floats in LDS,
  * at most 101 KiB for B = n_max = 64.) */
-int t3_backward(t3_plan *plan, const t3_catalog *cat, const double *grad_ups,
-                float *grad_g1, float *grad_g2, float *grad_w, void *stream);
+int t3_backward(t3_plan *plan, const t3_catalog *cat, const int32_t *centres, int64_t n_centres,
+                const double *grad_ups, float *grad_g1, float *grad_g2, float *grad_w, void *stream);
 
 /* Autotuner.  Times the forward pass of this plan on a deterministic sample
  * of at most sample_per_bin centres of every catalog (cats: HOST array of

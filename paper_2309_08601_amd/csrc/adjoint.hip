@@ -35,7 +35,11 @@
 // The transpose scan walks the same annuli as the forward scan (sweep.h),
 // every lane one neighbour, and adds its three gradient terms with
 // hardware FP32 atomics into per-galaxy buffers (summation order therefore
-// varies between runs at the level of FP32 rounding).
+// varies between runs at the level of FP32 rounding).  In deterministic mode
+// the terms are rounded to 64-bit fixed point instead -- scale 2^e per
+// centre chunk with e set from a bound on the chunk's largest term, so that
+// no sum can overflow -- and added with integer atomics, which are
+// associative; the chunks are then summed in FP64 in chunk order.
 #include "sweep.h"
 
 namespace t3 {
@@ -59,7 +63,26 @@ struct CoefArgs {
     float *coef;           // [n_c][B][coef_size(cap)]
     float2 *cen_gc;        // [n_c] centre part of grad c (chunk-relative)
     float *cen_gw;         // [n_c] centre part of grad w
+    unsigned *coef_max;    // deterministic mode: largest |coefficient| of the chunk (float bits); else null
 };
+
+// Deterministic mode: exponent e of the fixed-point scale 2^e of one chunk.
+// A pair's three terms are each at most (1 + 4 cmax) times the sum of the
+// absolute entries of the centre's coefficient block (|z^m| = 1, cmax =
+// max(1, |Re c| + |Im c|, w) over the catalog), a galaxy receives at most one
+// pair term per centre, so every per-galaxy sum is below
+// n_c * coef_size * max|coef| * 8 cmax = bound < 2^ex, and with e = 61 - ex
+// the scaled sums stay below 2^61.
+__device__ __forceinline__ int det_exponent(const unsigned *hdr, int n_c, int cs)
+{
+    const double mc = (double)__uint_as_float(hdr[0]);
+    const double cm = (double)__uint_as_float(hdr[1]);
+    const double bound = mc * (double)cs * 8.0 * cm * (double)n_c;
+    if (!(bound > 0.0)) return 0;
+    int ex = 0;
+    (void)frexp(bound, &ex);
+    return 61 - ex;
+}
 
 // One wavefront per centre.  The operands (FP32 planes) and the gradient
 // accumulators of the harmonics (a few terms each, stored as FP32
@@ -270,6 +293,7 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
     }
     // coefficient blocks
     const int C = a.cap, M = C + 3, CS = coef_size(C);
+    float vmax = 0.0f;
     for (int t = lane; t < B * CS; t += 64) {
         const int bb = t / CS, k = t % CS;
         float v = 0.0f;
@@ -299,6 +323,12 @@ __global__ __launch_bounds__(64) void k_adj_coef(CoefArgs a)
             v = (float)(kk == 6 ? d.x : (kk % 2 == 0 ? d.x : d.y));
         }
         a.coef[((size_t)i * B + bb) * CS + k] = v;
+        vmax = fmaxf(vmax, fabsf(v));
+    }
+    if (a.coef_max) {
+        // an integer maximum of non-negative float bits: order-independent
+        for (int d = 32; d > 0; d >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, d, 64));
+        if (lane == 0) atomicMax(a.coef_max, __float_as_uint(vmax));
     }
 }
 
@@ -309,6 +339,8 @@ struct ScatterArgs {
     int n_c, B, jk;
     float *nb_gc;         // [2][n] grad c of neighbours (sorted index): real parts, then imaginary
     float *nb_gw;         // [n]
+    unsigned long long *det_acc;  // deterministic mode: [3][n] fixed-point sums (else null)
+    const unsigned *det_hdr;      // deterministic mode: max |coef| and cmax (float bits)
     int64_t n_nb;         // neighbours n
     double e2[65];
 };
@@ -423,6 +455,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_scatter(ScatterArgs a)
     if (threadIdx.x < kWaves) cpk[threadIdx.x] = a.cpos[c0 + min((int)threadIdx.x, nk - 1)];
     const double D = ceil(dmax) + 2.0;  // covers the roundings of the square roots below
     const SweepLDS lds{q_xyc[wv], q_wi[wv], spans[wv]};
+    const double det_scale = a.det_acc ? ldexp(1.0, det_exponent(a.det_hdr, a.n_c, CS)) : 0.0;
 
     for (int b = 0; b < a.B; ++b) {
         __syncthreads();
@@ -463,9 +496,20 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_scatter(ScatterArgs a)
                         // neighbours are mostly consecutive sorted indices,
                         // so each atomic instruction covers few, fully used
                         // cache lines
-                        unsafeAtomicAdd(a.nb_gc + gi, gr);
-                        unsafeAtomicAdd(a.nb_gc + a.n_nb + gi, gim);
-                        unsafeAtomicAdd(a.nb_gw + gi, gw);
+                        if (a.det_acc) {
+                            // two's-complement fixed point: integer sums do not
+                            // depend on the order of the atomics
+                            const long long vr = llrint((double)gr * det_scale);
+                            const long long vi = llrint((double)gim * det_scale);
+                            const long long vw = llrint((double)gw * det_scale);
+                            atomicAdd(a.det_acc + gi, (unsigned long long)vr);
+                            atomicAdd(a.det_acc + a.n_nb + gi, (unsigned long long)vi);
+                            atomicAdd(a.det_acc + 2 * a.n_nb + gi, (unsigned long long)vw);
+                        } else {
+                            unsafeAtomicAdd(a.nb_gc + gi, gr);
+                            unsafeAtomicAdd(a.nb_gc + a.n_nb + gi, gim);
+                            unsafeAtomicAdd(a.nb_gw + gi, gw);
+                        }
                     }
                 },
                 wv, kWaves);
@@ -473,6 +517,52 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_scatter(ScatterArgs a)
     }
 }
 
+// Deterministic mode: the chunk's fixed-point sums into the FP64 totals
+// (chunk order), clearing them for the next chunk.
+__global__ void k_det_fold(unsigned long long *acc, double *tot, int64_t n3, const unsigned *hdr, int n_c, int cs)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n3) return;
+    const double inv = ldexp(1.0, -det_exponent(hdr, n_c, cs));
+    tot[t] += (double)(long long)acc[t] * inv;
+    acc[t] = 0ull;
+}
+
+// Deterministic mode: FP64 totals to the FP32 neighbour arrays of k_adj_combine.
+__global__ void k_det_out(const double *tot, int64_t n3, float *nb)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n3) nb[t] = (float)tot[t];
+}
+
+// cmax = max(1, |Re c| + |Im c|, w) over the sorted catalog (float bits, order-independent max).
+__global__ void k_cat_cmax(const float4 *cw, int64_t n, unsigned *out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float m = 1.0f;
+    if (t < n) {
+        const float4 c = cw[t];
+        m = fmaxf(m, fmaxf(fabsf(c.x) + fabsf(c.y), fabsf(c.z)));
+    }
+    for (int d = 32; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+__global__ void k_set_u32(unsigned *p, unsigned v) { *p = v; }
+
+__global__ void k_zero_u64(unsigned long long *p, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0ull;
+}
+
+__global__ void k_zero_d(double *p, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0.0;
+}
+
+// cen_gc / cen_gw null: the centre terms are added separately (centre lists).
 __global__ void k_adj_combine(const int *perm, int64_t n, const float *nb_gc, const float *nb_gw,
                               const float2 *cen_gc, const float *cen_gw, const float *g1, const float *g2,
                               const float *w, float *out_g1, float *out_g2, float *out_w)
@@ -480,13 +570,30 @@ __global__ void k_adj_combine(const int *perm, int64_t n, const float *nb_gc, co
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int i = perm[s];
-    const float gcr = nb_gc[s] + cen_gc[s].x;
-    const float gci = nb_gc[n + s] + cen_gc[s].y;
-    const float gwd = nb_gw[s] + cen_gw[s];
+    const float gcr = nb_gc[s] + (cen_gc ? cen_gc[s].x : 0.0f);
+    const float gci = nb_gc[n + s] + (cen_gc ? cen_gc[s].y : 0.0f);
+    const float gwd = nb_gw[s] + (cen_gw ? cen_gw[s] : 0.0f);
     const float wi = w[i];
     out_g1[i] = wi * gcr;
     out_g2[i] = wi * gci;
     out_w[i] = gwd + g1[i] * gcr + g2[i] * gci;
+}
+
+// Centre terms of a centre list: centre k is galaxy idx[k] (c = w gamma chain
+// rule as in k_adj_combine, which it follows).  A repeated index adds its
+// terms once per occurrence, in an unspecified order.
+__global__ void k_adj_centre_add(const int32_t *idx, int64_t n_c, const float2 *cen_gc, const float *cen_gw,
+                                 const float *g1, const float *g2, const float *w, float *out_g1, float *out_g2,
+                                 float *out_w)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_c) return;
+    const int i = idx[k];
+    const float gcr = cen_gc[k].x, gci = cen_gc[k].y;
+    const float wi = w[i];
+    atomicAdd(out_g1 + i, wi * gcr);
+    atomicAdd(out_g2 + i, wi * gci);
+    atomicAdd(out_w + i, cen_gw[k] + g1[i] * gcr + g2[i] * gci);
 }
 
 __global__ void k_zero_f(float *p, size_t n)
@@ -553,29 +660,24 @@ int normalise_backward(t3_plan *plan, const double *ups, const double *ggam, int
     return T3_OK;
 }
 
-int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float *gg1, float *gg2,
-             float *gw, hipStream_t s)
+int backward(t3_plan *plan, const t3_catalog &cat, const int32_t *centres, int64_t n_centres,
+             const double *grad_ups, float *gg1, float *gg2, float *gw, hipStream_t s)
 {
     T3_TRY(timing_begin_call(plan));
     T3_TRY(plan->flag.reserve(sizeof(int) * 4));
     T3_TRY(plan->counter.reserve(sizeof(unsigned long long) * 4));
     T3_HIP_CHECK(hipMemsetAsync(plan->flag.ptr, 0, sizeof(int) * 4, s));
     SortedCatalog &sc = plan->cats[0];
-    // planes kept by the last forward over this very catalog: its sorted
-    // catalog, centres and chunk layout are still the plan's
+    const bool all = n_centres < 0;
+    // planes kept by the last forward over every galaxy of this very
+    // catalog: its sorted catalog, centres and chunk layout are still the plan's
     const t3_catalog &kc = plan->kept_cat;
-    const bool kept = (plan->flags & T3_FLAG_KEEP_PLANES) && plan->kept_seq == plan->cells_seq &&
+    const bool kept = all && (plan->flags & T3_FLAG_KEEP_PLANES) && plan->kept_seq == plan->cells_seq &&
                       kc.n == cat.n && kc.x == cat.x && kc.y == cat.y && kc.g1 == cat.g1 && kc.g2 == cat.g2 &&
                       kc.w == cat.w && plan->kept_L.B == plan->B && plan->kept_L.n_max == plan->n_max;
     CentreSet &cen = kept ? plan->csets[0] : plan->centres;
-    if (!kept) {
-        T3_TRY(build_cells(plan, sc, cat, choose_grid(plan, cat.n), s));
-        T3_TRY(gather_sorted_centres(plan, sc, plan->centres, s));
-        T3_TRY(check_flag(plan, s, "t3_backward"));
-    }
     const int64_t n = cat.n;
-    if (n == 0) return T3_OK;
-
+    const int64_t n_c = all ? n : n_centres;
     const ScatterVariant *sv = nullptr;
     for (const auto &v : kScatter)
         if (v.cap >= plan->n_max) {
@@ -583,38 +685,72 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
             break;
         }
     if (!sv) return fail(T3_ERANGE, "t3_backward: n_max above the compiled variants");
+    const int B = plan->B, nm = plan->n_max;
+    const size_t lds = sizeof(float2) * ((size_t)B * ((2 * nm + 3) + (nm + 1) + 4) + 2 * kMaxRadialBins);
+    if (lds > 160 * 1024)  // a workgroup's LDS limit on gfx950 (B = n_max = 64 needs 101 KiB)
+        return fail(T3_ERANGE, "t3_backward: n_bins (3 n_max + 8) above the coefficient kernel's LDS");
     ChunkLayout L;
     L.n_max = plan->n_max;
     L.w_max = plan->w_max;
     L.B = plan->B;
     L.K = choose_chunk(plan, L);
-    if (plan->chunk_req <= 0 && (int64_t)L.K > n)  // small catalogs, small buffers
-        L.K = (int)std::max<int64_t>(256, ((int64_t)n + 255) & ~(int64_t)255);
+    if (plan->chunk_req <= 0 && (int64_t)L.K > n_c)  // small centre sets, small buffers
+        L.K = (int)std::max<int64_t>(256, ((int64_t)n_c + 255) & ~(int64_t)255);
     if (kept) L = plan->kept_L;
     const int CS = coef_size(sv->cap);
-    // scratch: nb_gc [2][n], nb_gw [n], cen_gc [2n], cen_gw [n]
-    T3_TRY(plan->misc.reserve(sizeof(float) * 6 * (size_t)n));
+    const bool det = (plan->flags & T3_FLAG_DETERMINISTIC) != 0;
+    // every buffer is reserved before the first launch that writes an output:
+    // a call refused for the workspace limit leaves the gradients untouched
+    // scratch: nb_gc [2][n], nb_gw [n], cen_gc [2 n_c], cen_gw [n_c]
+    T3_TRY(plan->misc.reserve(sizeof(float) * (3 * (size_t)n + 3 * (size_t)n_c + 4)));
     T3_TRY(plan->misc2.reserve(sizeof(float) * (size_t)L.K * L.B * CS));
     if (!kept) T3_TRY(plan->chunk.reserve(sizeof(float) * L.floats()));
+    // deterministic mode: header (max |coef|, cmax), fixed-point sums [3n], FP64 totals [3n]
+    if (det) T3_TRY(plan->det.reserve(16 + 16 * 3 * (size_t)n + 64));
+    if (!kept) {
+        T3_TRY(build_cells(plan, sc, cat, choose_grid(plan, cat.n), s));
+        if (all)
+            T3_TRY(gather_sorted_centres(plan, sc, plan->centres, s));
+        else
+            T3_TRY(gather_centres(plan, cat, centres, n_centres, plan->centres, s));
+        T3_TRY(check_flag(plan, s, "t3_backward"));
+    }
+    if (n == 0) return T3_OK;
+
     float *nb_gc = plan->misc.as<float>();
     float *nb_gw = nb_gc + 2 * n;
-    float2 *cen_gc = reinterpret_cast<float2 *>(nb_gw + n);
-    float *cen_gw = reinterpret_cast<float *>(cen_gc + n);
-    hipLaunchKernelGGL(k_zero_f, dim3((unsigned)((6 * n + 255) / 256)), dim3(256), 0, s, nb_gc,
-                       (size_t)(6 * n));
+    float *cen_base = nb_gw + n;
+    // float2 alignment of the centre terms
+    float2 *cen_gc = reinterpret_cast<float2 *>(cen_base + ((reinterpret_cast<uintptr_t>(cen_base) & 7) ? 1 : 0));
+    float *cen_gw = reinterpret_cast<float *>(cen_gc + n_c);
+    hipLaunchKernelGGL(k_zero_f, dim3((unsigned)((3 * n + 3 * n_c + 4 + 255) / 256)), dim3(256), 0, s, nb_gc,
+                       (size_t)(3 * n + 3 * n_c + 4));
     T3_HIP_CHECK(hipGetLastError());
+    unsigned *det_hdr = nullptr;
+    unsigned long long *det_acc = nullptr;
+    double *det_tot = nullptr;
+    if (det) {
+        det_hdr = plan->det.as<unsigned>();
+        det_acc = reinterpret_cast<unsigned long long *>(plan->det.as<char>() + 16);
+        det_tot = reinterpret_cast<double *>(det_acc + 3 * n);
+        hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, s, det_acc, 3 * n);
+        T3_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_zero_d, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, s, det_tot, 3 * n);
+        T3_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, det_hdr + 1, 0u);
+        T3_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_cat_cmax, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           (const float4 *)sc.cw.as<float4>(), n, det_hdr + 1);
+        T3_HIP_CHECK(hipGetLastError());
+    }
     const bool jk = !(plan->flags & T3_FLAG_KEEP_JK);
-    const int B = plan->B, nm = plan->n_max;
-    const size_t lds = sizeof(float2) * ((size_t)B * ((2 * nm + 3) + (nm + 1) + 4) + 2 * kMaxRadialBins);
-    if (lds > 160 * 1024)  // a workgroup's LDS limit on gfx950 (B = n_max = 64 needs 101 KiB)
-        return fail(T3_ERANGE, "t3_backward: n_bins (3 n_max + 8) above the coefficient kernel's LDS");
     if (lds > 64 * 1024)
         T3_HIP_CHECK(hipFuncSetAttribute((const void *)k_adj_coef,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int n_lane = 0;
-    if (!kept) T3_TRY(lane_bins(plan, sc, 0, B, kLaneNeighbours, s, &n_lane));
-    for (int64_t c0 = 0; c0 < n; c0 += L.K) {
-        const int nc = (int)((n - c0) < L.K ? (n - c0) : L.K);
+    if (!kept && n_c > 0) T3_TRY(lane_bins(plan, sc, 0, B, kLaneNeighbours, s, &n_lane));
+    for (int64_t c0 = 0; c0 < n_c; c0 += L.K) {
+        const int nc = (int)((n_c - c0) < L.K ? (n_c - c0) : L.K);
         const float *planes = kept ? plan->kept.as<float>() + (size_t)(c0 / L.K) * L.floats() : plan->chunk.as<float>();
         if (!kept) {
             T3_TRY(timing_mark(plan, 1, true, s));
@@ -624,6 +760,10 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
             T3_TRY(timing_mark(plan, 1, false, s));
         }
         T3_TRY(timing_mark(plan, 2, true, s));
+        if (det) {
+            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, det_hdr, 0u);
+            T3_HIP_CHECK(hipGetLastError());
+        }
         CoefArgs ca{};
         ca.planes = planes;
         ca.ccw = cen.cw.as<float4>() + c0;
@@ -637,6 +777,7 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
         ca.coef = plan->misc2.as<float>();
         ca.cen_gc = cen_gc + c0;
         ca.cen_gw = cen_gw + c0;
+        ca.coef_max = det_hdr;
         hipLaunchKernelGGL(k_adj_coef, dim3(nc), dim3(64), lds, s, ca);
         T3_HIP_CHECK(hipGetLastError());
         T3_TRY(timing_mark(plan, 2, false, s));
@@ -653,18 +794,37 @@ int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float
         sa.jk = jk ? 1 : 0;
         sa.nb_gc = nb_gc;
         sa.nb_gw = nb_gw;
+        sa.det_acc = det_acc;
+        sa.det_hdr = det_hdr;
         sa.n_nb = n;
         for (int b = 0; b <= B; ++b) sa.e2[b] = plan->e2[b];
         int nwg = (nc + kWaves - 1) / kWaves;
         nwg = (nwg + 7) & ~7;
         hipLaunchKernelGGL(sv->kernel, dim3((unsigned)nwg), dim3(64 * kWaves), 0, s, sa);
         T3_HIP_CHECK(hipGetLastError());
+        if (det) {
+            hipLaunchKernelGGL(k_det_fold, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, s, det_acc, det_tot,
+                               3 * n, (const unsigned *)det_hdr, nc, CS);
+            T3_HIP_CHECK(hipGetLastError());
+        }
         T3_TRY(timing_mark(plan, 3, false, s));
+    }
+    if (det) {
+        // nb_gc [2n] and nb_gw [n] are contiguous, as are the three totals
+        hipLaunchKernelGGL(k_det_out, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, s,
+                           (const double *)det_tot, 3 * n, nb_gc);
+        T3_HIP_CHECK(hipGetLastError());
     }
     hipLaunchKernelGGL(k_adj_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        (const int *)sc.perm.as<int>(), n, (const float *)nb_gc, (const float *)nb_gw,
-                       (const float2 *)cen_gc, (const float *)cen_gw, cat.g1, cat.g2, cat.w, gg1, gg2, gw);
+                       all ? (const float2 *)cen_gc : nullptr, all ? (const float *)cen_gw : nullptr, cat.g1, cat.g2,
+                       cat.w, gg1, gg2, gw);
     T3_HIP_CHECK(hipGetLastError());
+    if (!all && n_c > 0) {
+        hipLaunchKernelGGL(k_adj_centre_add, dim3((unsigned)((n_c + 255) / 256)), dim3(256), 0, s, centres, n_c,
+                           (const float2 *)cen_gc, (const float *)cen_gw, cat.g1, cat.g2, cat.w, gg1, gg2, gw);
+        T3_HIP_CHECK(hipGetLastError());
+    }
     T3_HIP_CHECK(hipStreamSynchronize(s));
     T3_TRY(timing_end_call(plan));
     return T3_OK;

@@ -21,12 +21,27 @@ int fail(int code, const std::string &msg)
     return code;
 }
 
+static thread_local Budget *g_budget = nullptr;
+
+Budget *active_budget() { return g_budget; }
+
+BudgetScope::BudgetScope(Budget *b) : prev(g_budget) { g_budget = b; }
+
+BudgetScope::~BudgetScope() { g_budget = prev; }
+
 int DevBuf::reserve(size_t want)
 {
     if (want <= bytes && ptr) return T3_OK;
+    const size_t b = want < 256 ? 256 : want;
+    Budget *bg = g_budget;
+    // the limit is checked before the old buffer is given up, so a refused
+    // request leaves the plan as it was
+    if (bg && bg->limit > 0 && bg->used - (int64_t)bytes + (int64_t)b > bg->limit)
+        return fail(T3_ENOMEM, "workspace limit: " + std::to_string(b) + " bytes more would exceed "
+                                   "max_workspace_bytes = " + std::to_string(bg->limit) + " (in use " +
+                                   std::to_string(bg->used) + ")");
     if (ptr) (void)hipDeviceSynchronize();  // earlier launches may still read the old buffer
     release();
-    size_t b = want < 256 ? 256 : want;
     if (hipMalloc(&ptr, b) != hipSuccess) {
         (void)hipGetLastError();
         ptr = nullptr;
@@ -34,12 +49,19 @@ int DevBuf::reserve(size_t want)
         return fail(T3_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
     }
     bytes = b;
+    if (bg) {
+        bg->used += (int64_t)b;
+        bg->peak = std::max(bg->peak, bg->used);
+    }
     return T3_OK;
 }
 
 void DevBuf::release()
 {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) {
+        (void)hipFree(ptr);
+        if (g_budget) g_budget->used -= (int64_t)bytes;
+    }
     ptr = nullptr;
     bytes = 0;
 }
@@ -295,8 +317,9 @@ int t3_plan_create(const t3_params *p, t3_plan **out)
         if (p->precision < T3_PREC_FP32 || p->precision > T3_PREC_BF16X6)
             return fail(T3_EINVAL, "t3_plan_create: unknown precision");
         if (p->flags & ~(T3_FLAG_KEEP_JK | T3_FLAG_TIMING | T3_FLAG_NO_GRAPH | T3_FLAG_EDGE_CORRECT | T3_FLAG_NO_LANE |
-                         T3_FLAG_KEEP_PLANES))
+                         T3_FLAG_KEEP_PLANES | T3_FLAG_DETERMINISTIC))
             return fail(T3_EINVAL, "t3_plan_create: unknown flag");
+        if (p->max_workspace_bytes < 0) return fail(T3_EINVAL, "t3_plan_create: max_workspace_bytes must be >= 0");
         const double unit = p->lattice_unit == 0.0 ? std::ldexp(1.0, -16) : p->lattice_unit;
         if (!(unit > 0.0) || !std::isfinite(unit)) return fail(T3_EINVAL, "t3_plan_create: bad lattice unit");
         for (int b = 0; b <= p->n_bins; ++b)
@@ -330,6 +353,7 @@ int t3_plan_create(const t3_params *p, t3_plan **out)
         plan->cell_arcmin = p->cell_arcmin;
         plan->chunk_req = p->chunk_centres;
         plan->scan_mode = p->scan_mode;
+        plan->budget.limit = p->max_workspace_bytes;
         plan->edges_lat.resize(p->n_bins + 1);
         plan->e2.resize(p->n_bins + 1);
         for (int b = 0; b <= p->n_bins; ++b) {
@@ -370,6 +394,7 @@ void t3_plan_destroy(t3_plan *plan)
     plan->counter.release();
     plan->misc.release();
     plan->misc2.release();
+    plan->det.release();
     for (auto e : plan->events) (void)hipEventDestroy(e);
     for (auto &c : plan->csets) {
         c.pos.release();
@@ -392,6 +417,7 @@ int t3_forward(t3_plan *plan, const t3_catalog *cat, const int32_t *centres, int
 {
     try {
         if (!plan || !ups_out) return fail(T3_EINVAL, "t3_forward: null argument");
+        BudgetScope budget_scope(&plan->budget);
         T3_TRY(check_catalog(cat, "t3_forward"));
         if (n_centres < 0 && centres)
             return fail(T3_EINVAL, "t3_forward: n_centres < 0 (all galaxies) needs centres == NULL");
@@ -410,6 +436,7 @@ int t3_forward_tomo(t3_plan *plan, const t3_catalog *cats, int32_t n_z, const in
 {
     try {
         if (!plan || !cats || !ups_out) return fail(T3_EINVAL, "t3_forward_tomo: null argument");
+        BudgetScope budget_scope(&plan->budget);
         if (n_z < 1 || n_z > 8) return fail(T3_ERANGE, "t3_forward_tomo: n_z must be in [1, 8]");
         for (int z = 0; z < n_z; ++z) T3_TRY(check_catalog(&cats[z], "t3_forward_tomo"));
         if (centres && !n_centres) return fail(T3_EINVAL, "t3_forward_tomo: centres without counts");
@@ -434,6 +461,7 @@ int t3_harmonics(t3_plan *plan, const t3_catalog *cat, const int32_t *centres, i
     try {
         if (!plan || !G_out || !W_out || !D_out || (n_centres > 0 && !centres))
             return fail(T3_EINVAL, "t3_harmonics: null argument");
+        BudgetScope budget_scope(&plan->budget);
         T3_TRY(check_catalog(cat, "t3_harmonics"));
         if (n_centres < 0 || n_centres > (int64_t)0x7fffffff)
             return fail(T3_EINVAL, "t3_harmonics: bad centre count");
@@ -468,6 +496,7 @@ int t3_normalise_resum(t3_plan *plan, const double *ups, int32_t n_sets, int32_t
                        double *gamma_n, double *gamma_phi, void *stream)
 {
     if (!plan || !ups || !gamma_n) return fail(T3_EINVAL, "t3_normalise_resum: null argument");
+    BudgetScope budget_scope(&plan->budget);
     if (n_sets < 1) return fail(T3_EINVAL, "t3_normalise_resum: n_sets must be >= 1");
     int n_z = 1;
     while (n_z * n_z * n_z < n_sets) ++n_z;
@@ -481,6 +510,7 @@ int t3_x_to_centroid(t3_plan *plan, const double *gamma_phi_x, int32_t n_sets, i
                      const double *theta, double *gamma_phi_cent, void *stream)
 {
     if (!plan || !gamma_phi_x || !gamma_phi_cent) return fail(T3_EINVAL, "t3_x_to_centroid: null argument");
+    BudgetScope budget_scope(&plan->budget);
     if (n_sets < 1) return fail(T3_EINVAL, "t3_x_to_centroid: n_sets must be >= 1");
     if (n_phi < 1 || n_phi > 4096) return fail(T3_ERANGE, "t3_x_to_centroid: n_phi must be in [1, 4096]");
     if (theta)
@@ -496,6 +526,7 @@ int t3_forward_sphere(t3_plan *plan, const t3_sphere_catalog *cat, const t3_patc
     try {
         if (!plan || !cat || !patches || !ups_out || !n_pairs)
             return fail(T3_EINVAL, "t3_forward_sphere: null argument");
+        BudgetScope budget_scope(&plan->budget);
         if (n_patches < 1) return fail(T3_EINVAL, "t3_forward_sphere: need at least one patch");
         if (cat->n < 0 || cat->n > (int64_t)0x7fffffff)
             return fail(T3_EINVAL, "t3_forward_sphere: catalog size out of range");
@@ -539,6 +570,7 @@ int t3_forward_grid(t3_plan *plan, const t3_catalog *cat, int64_t delta, const i
 {
     try {
         if (!plan || !levels || !ups_out) return fail(T3_EINVAL, "t3_forward_grid: null argument");
+        BudgetScope budget_scope(&plan->budget);
         T3_TRY(check_catalog(cat, "t3_forward_grid"));
         if (method != T3_GRID_AUTO && method != T3_GRID_DIRECT && method != T3_GRID_FFT)
             return fail(T3_EINVAL, "t3_forward_grid: unknown method");
@@ -569,6 +601,7 @@ int t3_aperture_stats(t3_plan *plan, const double *gamma_phi_cent, int32_t n_set
 {
     if (!plan || !gamma_phi_cent || !apertures || !corr_out)
         return fail(T3_EINVAL, "t3_aperture_stats: null argument");
+    BudgetScope budget_scope(&plan->budget);
     if (n_sets < 1 || n_ap < 1) return fail(T3_EINVAL, "t3_aperture_stats: n_sets and n_ap must be >= 1");
     if (n_phi < 1 || n_phi > 4096) return fail(T3_ERANGE, "t3_aperture_stats: n_phi must be in [1, 4096]");
     if (n_ap > 65535) return fail(T3_ERANGE, "t3_aperture_stats: at most 65535 aperture triples per call");
@@ -584,6 +617,7 @@ int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets, cons
 {
     if (!plan || !ups || !grad_gamma_n || !grad_ups)
         return fail(T3_EINVAL, "t3_normalise_backward: null argument");
+    BudgetScope budget_scope(&plan->budget);
     if (plan->flags & T3_FLAG_EDGE_CORRECT)
         return fail(T3_EINVAL, "t3_normalise_backward: no adjoint of the edge-corrected normalisation");
     if (n_sets < 1) return fail(T3_EINVAL, "t3_normalise_backward: n_sets must be >= 1");
@@ -595,6 +629,7 @@ int t3_autotune(t3_plan *plan, const t3_catalog *cats, int32_t n_z, int64_t samp
 {
     try {
         if (!plan || !cats) return fail(T3_EINVAL, "t3_autotune: null argument");
+        BudgetScope budget_scope(&plan->budget);
         if (n_z < 1 || n_z > 8) return fail(T3_ERANGE, "t3_autotune: n_z must be in [1, 8]");
         if (sample_per_bin < 1) return fail(T3_EINVAL, "t3_autotune: sample_per_bin must be >= 1");
         for (int z = 0; z < n_z; ++z) T3_TRY(check_catalog(&cats[z], "t3_autotune"));
@@ -691,6 +726,14 @@ int t3_autotune(t3_plan *plan, const t3_catalog *cats, int32_t n_z, int64_t samp
     }
 }
 
+int t3_workspace_bytes(const t3_plan *plan, int64_t *in_use, int64_t *peak)
+{
+    if (!plan) return fail(T3_EINVAL, "t3_workspace_bytes: null plan");
+    if (in_use) *in_use = plan->budget.used;
+    if (peak) *peak = plan->budget.peak;
+    return T3_OK;
+}
+
 int t3_stage_times(const t3_plan *plan, double *ms, int64_t *launches)
 {
     if (!plan || !ms) return fail(T3_EINVAL, "t3_stage_times: null argument");
@@ -702,16 +745,21 @@ int t3_stage_times(const t3_plan *plan, double *ms, int64_t *launches)
     return T3_OK;
 }
 
-int t3_backward(t3_plan *plan, const t3_catalog *cat, const double *grad_ups, float *grad_g1,
-                float *grad_g2, float *grad_w, void *stream)
+int t3_backward(t3_plan *plan, const t3_catalog *cat, const int32_t *centres, int64_t n_centres,
+                const double *grad_ups, float *grad_g1, float *grad_g2, float *grad_w, void *stream)
 {
     try {
         if (!plan || !grad_ups || !grad_g1 || !grad_g2 || !grad_w)
             return fail(T3_EINVAL, "t3_backward: null argument");
+        BudgetScope budget_scope(&plan->budget);
         if (plan->flags & T3_FLAG_EDGE_CORRECT)
             return fail(T3_EINVAL, "t3_backward: no adjoint for plans with T3_FLAG_EDGE_CORRECT");
         T3_TRY(check_catalog(cat, "t3_backward"));
-        return backward(plan, *cat, grad_ups, grad_g1, grad_g2, grad_w, (hipStream_t)stream);
+        if (n_centres < 0 && centres)
+            return fail(T3_EINVAL, "t3_backward: n_centres < 0 (all galaxies) needs centres == NULL");
+        if (n_centres > 0 && !centres) return fail(T3_EINVAL, "t3_backward: null centre list");
+        if (n_centres > (int64_t)0x7fffffff) return fail(T3_EINVAL, "t3_backward: bad centre count");
+        return backward(plan, *cat, centres, n_centres, grad_ups, grad_g1, grad_g2, grad_w, (hipStream_t)stream);
     } catch (...) {
         return fail(T3_EINVAL, "t3_backward: exception");
     }

@@ -29,6 +29,22 @@ int fail(int code, const std::string &msg);
     } while (0)
 
 // ---------------------------------------------------------------- device buffers
+// Device memory budget of a plan (t3_params.max_workspace_bytes).  Every
+// entry point that can allocate installs its plan's budget for the calling
+// thread (a plan is never used from two threads at once); DevBuf::reserve
+// checks the limit before it calls hipMalloc and keeps the running total.
+struct Budget {
+    int64_t limit = 0;  // bytes, 0 = unlimited
+    int64_t used = 0;   // bytes held by the plan's buffers
+    int64_t peak = 0;   // largest value of used
+};
+Budget *active_budget();
+struct BudgetScope {
+    Budget *prev;
+    explicit BudgetScope(Budget *b);
+    ~BudgetScope();
+};
+
 // Grow-only device allocation owned by a plan.
 struct DevBuf {
     void *ptr = nullptr;
@@ -174,6 +190,8 @@ struct t3_plan {
     t3_catalog kept_cat{};
     int64_t cells_seq = 0;   // build_cells calls on this plan
     int64_t kept_seq = -1;
+    t3::Budget budget;       // device memory held against max_workspace_bytes
+    t3::DevBuf det;          // T3_FLAG_DETERMINISTIC adjoint: fixed-point and FP64 accumulators
     int scan_var = -1;          // stage-1 variant index (see scan.hip)
     size_t scan_dest_off[3] = {0, 0, 0};  // main passes, then the W extension
 
@@ -242,8 +260,8 @@ int harmonics_export(t3_plan *plan, const CentreSet &cs, const ChunkLayout &L, c
                      int64_t c0, int n_c, float *G, float *W, float *D, hipStream_t s);
 int normalise_backward(t3_plan *plan, const double *ups, const double *ggam, int n_sets, double *gups,
                        hipStream_t s);
-int backward(t3_plan *plan, const t3_catalog &cat, const double *grad_ups, float *gg1, float *gg2,
-             float *gw, hipStream_t s);
+int backward(t3_plan *plan, const t3_catalog &cat, const int32_t *centres, int64_t n_centres,
+             const double *grad_ups, float *gg1, float *gg2, float *gw, hipStream_t s);
 
 // Stage timing helpers (no-ops unless the plan has T3_FLAG_TIMING).
 int timing_begin_call(t3_plan *plan);

@@ -31,6 +31,7 @@ T3_FLAG_NO_GRAPH = 4
 T3_FLAG_EDGE_CORRECT = 8
 T3_FLAG_NO_LANE = 16
 T3_FLAG_KEEP_PLANES = 32
+T3_FLAG_DETERMINISTIC = 64
 
 
 class t3_params(ctypes.Structure):
@@ -39,7 +40,7 @@ class t3_params(ctypes.Structure):
                 ("lattice_unit", ctypes.c_double), ("box_lo_x", ctypes.c_int32),
                 ("box_lo_y", ctypes.c_int32), ("box_size", ctypes.c_int64),
                 ("cell_arcmin", ctypes.c_double), ("chunk_centres", ctypes.c_int32),
-                ("scan_mode", ctypes.c_int32)]
+                ("scan_mode", ctypes.c_int32), ("max_workspace_bytes", ctypes.c_int64)]
 
 
 class t3_catalog(ctypes.Structure):
@@ -65,7 +66,7 @@ class T3Error(RuntimeError):
 
 EXPORTED = ["t3_plan_create", "t3_plan_destroy", "t3_forward", "t3_forward_tomo", "t3_harmonics",
             "t3_normalise_resum", "t3_normalise_backward", "t3_backward", "t3_autotune", "t3_stage_times",
-            "t3_error_string",
+            "t3_workspace_bytes", "t3_error_string",
             "t3_last_error_message", "t3_version"]
 
 
@@ -101,12 +102,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.t3_aperture_stats.restype = ctypes.c_int
     lib.t3_normalise_backward.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
     lib.t3_normalise_backward.restype = ctypes.c_int
-    lib.t3_backward.argtypes = [vp, P(t3_catalog), vp, vp, vp, vp, vp]
+    lib.t3_backward.argtypes = [vp, P(t3_catalog), vp, ctypes.c_int64, vp, vp, vp, vp, vp]
     lib.t3_backward.restype = ctypes.c_int
     lib.t3_autotune.argtypes = [vp, P(t3_catalog), ctypes.c_int32, ctypes.c_int64, P(ctypes.c_double), vp]
     lib.t3_autotune.restype = ctypes.c_int
     lib.t3_stage_times.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
     lib.t3_stage_times.restype = ctypes.c_int
+    lib.t3_workspace_bytes.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64)]
+    lib.t3_workspace_bytes.restype = ctypes.c_int
     lib.t3_error_string.argtypes = [ctypes.c_int]
     lib.t3_error_string.restype = ctypes.c_char_p
     lib.t3_last_error_message.argtypes = []
@@ -178,7 +181,7 @@ class Plan:
                  precision: str = "fp32", keep_jk: bool = False, lattice_unit: float = 0.0,
                  cell_arcmin: float = 0.0, chunk_centres: int = 0, timing: bool = False,
                  graph: bool = True, scan_mode: int = 0, edge_correct: bool = False, lane: bool = True,
-                 keep_planes: bool = False):
+                 keep_planes: bool = False, deterministic: bool = False, max_workspace_bytes: int = 0):
         self.edges = np.ascontiguousarray(edges, dtype=np.float64)
         self.B = len(self.edges) - 1
         self.n_max = int(n_max)
@@ -188,10 +191,11 @@ class Plan:
                       PRECISIONS[precision],
                       (T3_FLAG_KEEP_JK if keep_jk else 0) | (T3_FLAG_TIMING if timing else 0)
                       | (0 if graph else T3_FLAG_NO_GRAPH) | (T3_FLAG_EDGE_CORRECT if edge_correct else 0)
-                      | (0 if lane else T3_FLAG_NO_LANE) | (T3_FLAG_KEEP_PLANES if keep_planes else 0),
+                      | (0 if lane else T3_FLAG_NO_LANE) | (T3_FLAG_KEEP_PLANES if keep_planes else 0)
+                      | (T3_FLAG_DETERMINISTIC if deterministic else 0),
                       float(lattice_unit),
                       int(box_lo[0]), int(box_lo[1]), int(box_size), float(cell_arcmin),
-                      int(chunk_centres), int(scan_mode))
+                      int(chunk_centres), int(scan_mode), int(max_workspace_bytes))
         h = ctypes.c_void_p()
         _check(_lib.t3_plan_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h
@@ -391,15 +395,27 @@ class Plan:
         _check(_lib.t3_stage_times(self._h, ms, nl))
         return list(ms), list(nl)
 
-    def backward(self, cat: DeviceCatalog, grad_ups: torch.Tensor):
+    def workspace_bytes(self):
+        """(in use, peak) device bytes held by the plan."""
+        used = ctypes.c_int64(0)
+        peak = ctypes.c_int64(0)
+        _check(_lib.t3_workspace_bytes(self._h, ctypes.byref(used), ctypes.byref(peak)))
+        return int(used.value), int(peak.value)
+
+    def backward(self, cat: DeviceCatalog, grad_ups: torch.Tensor, centres: Optional[torch.Tensor] = None):
+        """dL/d(g1, g2, w) of every galaxy from dL/dUpsilon (real view [..., 2]);
+        centres: the forward pass's centre list (None: every galaxy)."""
         g = torch.view_as_real(grad_ups).contiguous() if grad_ups.is_complex() else grad_ups.contiguous()
         dev = cat.x.device
         gg1 = torch.empty(cat.n, dtype=torch.float32, device=dev)
         gg2 = torch.empty(cat.n, dtype=torch.float32, device=dev)
         gw = torch.empty(cat.n, dtype=torch.float32, device=dev)
         cs = cat.c_struct()
-        _check(_lib.t3_backward(self._h, ctypes.byref(cs), _ptr(g), _ptr(gg1), _ptr(gg2), _ptr(gw),
-                                _stream()))
+        if centres is not None:
+            centres = centres.to(torch.int32).contiguous()
+        _check(_lib.t3_backward(self._h, ctypes.byref(cs), _ptr(centres),
+                                -1 if centres is None else int(centres.numel()), _ptr(g), _ptr(gg1), _ptr(gg2),
+                                _ptr(gw), _stream()))
         return gg1, gg2, gw
 
 
@@ -423,13 +439,19 @@ class GammaMultipoles(torch.autograd.Function):
         ups, _ = plan.forward(cat)
         gn, _ = plan.normalise_resum(ups, with_phi=False)
         ctx.plan = plan
-        ctx.cat = cat
-        ctx.save_for_backward(torch.view_as_real(ups))
+        # the inputs go through save_for_backward so that autograd's version
+        # check raises if any of them is modified in place before backward
+        # (the adjoint reads them again, and kept planes must match them)
+        ctx.save_for_backward(torch.view_as_real(ups), g1, g2, w, x, y)
         return torch.view_as_real(gn).clone()
 
     @staticmethod
     def backward(ctx, grad_out):
-        (ups,) = ctx.saved_tensors
+        ups, g1, g2, w, x, y = ctx.saved_tensors
+        cat = DeviceCatalog.__new__(DeviceCatalog)
+        cat.x, cat.y = x.contiguous(), y.contiguous()
+        cat.g1, cat.g2, cat.w = g1.detach().contiguous(), g2.detach().contiguous(), w.detach().contiguous()
+        cat.n = int(x.shape[0])
         gups = ctx.plan.normalise_backward(ups, grad_out.contiguous())
-        gg1, gg2, gw = ctx.plan.backward(ctx.cat, gups)
+        gg1, gg2, gw = ctx.plan.backward(cat, gups)
         return gg1, gg2, gw, None, None, None

@@ -49,7 +49,7 @@ def _params(**kw):
     edges = np.asarray(kw.pop("edges", [1.0, 2.0, 4.0]), dtype=np.float64)
     p = t3_params(len(edges) - 1, edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                   kw.pop("n_max", 4), kw.pop("precision", 0), kw.pop("flags", 0), 0.0, 0, 0,
-                  kw.pop("box_size", 1 << 20), 0.0, 0)
+                  kw.pop("box_size", 1 << 20), 0.0, 0, 0, kw.pop("max_workspace_bytes", 0))
     for k, v in kw.items():
         setattr(p, k, v)
     return p, edges
@@ -64,7 +64,8 @@ def _params(**kw):
     (dict(n_max=65), -2),
     (dict(n_max=-1), -2),
     (dict(precision=7), -1),
-    (dict(flags=64), -1),
+    (dict(flags=128), -1),
+    (dict(max_workspace_bytes=-1), -1),
     (dict(box_size=0), -1),
     (dict(box_size=1 << 40), -2),
 ])
@@ -79,10 +80,10 @@ def test_plan_create_rejects(lib, kw, code):
     assert len(t3._lib.t3_last_error_message()) > 0
 
 
-@pytest.mark.parametrize("flags", [0, 1 | 16, 32, 1 | 2 | 4 | 8 | 16 | 32])
+@pytest.mark.parametrize("flags", [0, 1 | 16, 32, 64, 1 | 2 | 4 | 8 | 16 | 32 | 64])
 def test_plan_create_and_destroy_ok(lib, flags):
     """Every defined flag bit, alone and together (keep j = k, timing, no
-    graph, edge correction, no lane kernel, keep planes)."""
+    graph, edge correction, no lane kernel, keep planes, deterministic)."""
     pytest.importorskip("torch")
     from paper_2309_08601_amd import t3
     p, edges = _params(flags=flags)
@@ -171,5 +172,47 @@ def test_forward_grid_argument_errors(lib):
         assert call(64, lv(0, 1)) == -2                  # 16384 pixels along the box
         assert call(1 << 14, lv(0, 1), 3) == -1          # unknown method
         assert t3._lib.t3_forward_grid(h, ctypes.byref(cat), 1 << 14, lv(0, 1), 0, None, None, None) == -1
+    finally:
+        t3._lib.t3_plan_destroy(h)
+
+
+def test_workspace_limit_refuses_before_allocating(lib):
+    """A plan whose max_workspace_bytes is below what a call needs returns
+    T3_ENOMEM from the limit check itself, before any device allocation or
+    launch (so this runs without a GPU), and holds no memory afterwards."""
+    pytest.importorskip("torch")
+    from paper_2309_08601_amd import t3
+    p, edges = _params(max_workspace_bytes=64)
+    h = ctypes.c_void_p()
+    assert t3._lib.t3_plan_create(ctypes.byref(p), ctypes.byref(h)) == 0
+    try:
+        cat = t3.t3_catalog(0, None, None, None, None, None)
+        out = ctypes.c_void_p(16)
+        npairs = ctypes.c_int64(0)
+        assert t3._lib.t3_forward(h, ctypes.byref(cat), None, -1, out, ctypes.byref(npairs), None) == t3.T3_ENOMEM
+        assert b"max_workspace_bytes" in t3._lib.t3_last_error_message()
+        g = ctypes.c_void_p(16)
+        assert t3._lib.t3_backward(h, ctypes.byref(cat), None, -1, g, g, g, g, None) == t3.T3_ENOMEM
+        assert b"max_workspace_bytes" in t3._lib.t3_last_error_message()
+        used, peak = ctypes.c_int64(-1), ctypes.c_int64(-1)
+        assert t3._lib.t3_workspace_bytes(h, ctypes.byref(used), ctypes.byref(peak)) == 0
+        assert used.value == 0 and peak.value == 0
+    finally:
+        t3._lib.t3_plan_destroy(h)
+    assert t3._lib.t3_workspace_bytes(None, None, None) == t3.T3_EINVAL
+
+
+def test_backward_centre_argument_errors(lib):
+    pytest.importorskip("torch")
+    from paper_2309_08601_amd import t3
+    p, edges = _params()
+    h = ctypes.c_void_p()
+    assert t3._lib.t3_plan_create(ctypes.byref(p), ctypes.byref(h)) == 0
+    try:
+        cat = t3.t3_catalog(0, None, None, None, None, None)
+        g = ctypes.c_void_p(16)
+        assert t3._lib.t3_backward(h, ctypes.byref(cat), g, -1, g, g, g, g, None) == t3.T3_EINVAL
+        assert t3._lib.t3_backward(h, ctypes.byref(cat), None, 5, g, g, g, g, None) == t3.T3_EINVAL
+        assert t3._lib.t3_backward(h, ctypes.byref(cat), g, 1 << 31, g, g, g, g, None) == t3.T3_EINVAL
     finally:
         t3._lib.t3_plan_destroy(h)
