@@ -7,6 +7,9 @@ from paper_2309_08601_amd.synth import LATTICE_UNIT
 
 FP32_TOL = 1e-6     # relative Frobenius error per (mu, n), FP32 path
 SPLIT_TOL = 1e-5    # split-precision contraction
+FP32_MAX_TOL = 2e-6   # largest entry error per (mu, n) over the largest |entry|, FP32 path
+SPLIT_MAX_TOL = 2e-5  # the same for the two-part bf16 split
+N_OWN_TOL = 5e-6      # N_n (n >= 1) against its own Frobenius norm, every precision
 
 
 def rel_fro(a: np.ndarray, b: np.ndarray, axes=(-2, -1)) -> np.ndarray:
@@ -25,6 +28,17 @@ def rel_max(a: np.ndarray, b: np.ndarray, axes=(-2, -1)) -> np.ndarray:
 def box_for(side_arcmin: float, margin_steps: int = 0):
     """Lattice box [0, side) as (lo, size) in lattice steps."""
     return (-margin_steps, -margin_steps), int(round(side_arcmin / LATTICE_UNIT)) + 2 * margin_steps
+
+
+def multipole_max_errors(gpu: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """Element-wise companion of ``multipole_errors``: per (mu, n) the largest
+    |entry error| over the largest |entry| of the oracle's block (N_n with
+    n >= 1 against the largest |N_0| entry, as there)."""
+    m = rel_max(gpu, ref)
+    n0 = np.max(np.abs(ref[..., 4, 0, :, :]), axis=(-2, -1))
+    dn = np.max(np.abs(gpu[..., 4, :, :, :] - ref[..., 4, :, :, :]), axis=(-2, -1))
+    m[..., 4, 1:] = dn[..., 1:] / np.where(n0 > 0, n0, 1.0)[..., None]
+    return m
 
 
 def multipole_errors(gpu: np.ndarray, ref: np.ndarray):

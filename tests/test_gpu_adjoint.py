@@ -3,7 +3,9 @@
 * elementwise against the FP64 autograd oracle on a small catalog;
 * against central finite differences of the GPU forward (exact for the
   shears: the loss is quadratic in each gamma_j);
-* on the 500k-galaxy, 7 deg x 7 deg workload (15 bins 1'-60', n_max 20),
+* on the 500k-galaxy, 7 deg x 7 deg workload (15 bins 1'-60', n_max 20):
+  finite differences of the GPU forward on 64 random galaxies of the full
+  catalog, the FP64 autograd oracle on a 5,000-galaxy sub-catalog, and
   exact identities that hold at any size:
     - Gamma is homogeneous of degree 3 in the shears:
           sum_j g . dL/dg_j = 6 sum omega Re(conj(Gamma - T) Gamma);
@@ -18,7 +20,7 @@ full-size identities (FP32 gradients summed over 5e5 galaxies).
 import numpy as np
 import pytest
 
-from paper_2309_08601_amd.synth import WORKLOADS, make_catalogs, random_catalog
+from paper_2309_08601_amd.synth import LATTICE_UNIT, WORKLOADS, make_catalogs, random_catalog
 from _util import box_for
 
 pytestmark = pytest.mark.gpu
@@ -239,3 +241,92 @@ def test_backward_exact_identities_at_500k(t3):
     lhs2 = float(np.dot(g1, d2) - np.dot(g2, d1))
     print(f"phase rotation: {lhs2:.6e} vs {rhs2:.6e}", flush=True)
     assert abs(lhs2 - rhs2) <= 1e-4 * max(abs(rhs2), 1e-3 * abs(rhs))
+
+
+def test_backward_fp64_gradient_on_5k_subcatalog_of_500k(t3):
+    """The differentiation workload's shear and weight model (7 deg x 7 deg,
+    15 bins 1'-60', n_max 20) on a random 5,000-galaxy sub-catalog of the
+    500k catalog: every galaxy's gradient against the FP64 autograd oracle,
+    the target from the same sub-catalog of the second-seed catalog."""
+    from oracle import autodiff as ad
+    from paper_2309_08601_amd.synth import centre_sample
+    wl = WORKLOADS["grad_500k"]
+    sub = centre_sample(wl.n_gal[0], 5000, seed=77)
+    cat = make_catalogs(wl)[0].subset(sub)
+    tgt = make_catalogs(wl, seed_offset=100)[0].subset(sub)
+    edges, nm = wl.edges(), wl.n_max
+    t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))  # noqa: E731
+    uT, NT = ad.multipoles(tgt.x, tgt.y, t(tgt.g1), t(tgt.g2), t(tgt.w), edges, nm)
+    T = ad.gamma(uT, NT).detach()
+    om = ad.loss_weights(T)
+    g1, g2, w = (t(v).requires_grad_(True) for v in (cat.g1, cat.g2, cat.w))
+    u, N = ad.multipoles(cat.x, cat.y, g1, g2, w, edges, nm)
+    Lr = ad.loss(ad.gamma(u, N), T, om)
+    Lr.backward()
+    lo, size = box_for(wl.side)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size)
+    L, _, d1, d2, dw = _gpu_loss_and_grad(t3, plan, cat, T, om)
+    assert abs(float(L) - float(Lr)) < 1e-5 * float(Lr)
+    for got, ref, name in ((d1, g1.grad, "g1"), (d2, g2.grad, "g2"), (dw, w.grad, "w")):
+        ref = ref.numpy()
+        e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        m = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"5k sub-catalog grad {name}: rel-norm {e:.2e}, rel-max {m:.2e}", flush=True)
+        assert e < 2e-5 and m < 1e-4, (name, e, m)
+
+
+def test_backward_matches_finite_differences_at_500k(t3):
+    """Central finite differences of the GPU forward on 64 random galaxies
+    of the full 500k catalog.  After the j = k removal every distinct
+    triplet holds a galaxy at most once, so Upsilon and N_0 are linear in
+    each galaxy's c_j and w_j, and only centres within the outer bin edge of
+    galaxy j (j included) see it: the forward over exactly those centres,
+    with one parameter of j moved by +-h, gives the derivative of the full
+    Upsilon and N_0 exactly for any h (h = 10 for the shears, where the
+    moved galaxy then dominates the sums it enters, 0.4 for the weight), and
+    the loss then follows by the chain rule through Gamma = Upsilon / N_0 of
+    the full forward."""
+    wl = WORKLOADS["grad_500k"]
+    cat = make_catalogs(wl)[0]
+    tgt = make_catalogs(wl, seed_offset=100)[0]
+    edges, nm = wl.edges(), wl.n_max
+    lo, size = box_for(wl.side)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size)
+    Tu, _ = plan.forward(t3.DeviceCatalog.from_catalog(tgt))
+    T, _ = plan.normalise_resum(Tu, with_phi=False)
+    T = T.cpu()
+    om = 1.0 / torch.clamp(torch.mean(T.real ** 2 + T.imag ** 2, dim=1, keepdim=True), min=1e-300)
+    om = om.expand_as(T.real).contiguous()
+    _, _, d1, d2, dw = _gpu_loss_and_grad(t3, plan, cat, T, om)
+    dc = t3.DeviceCatalog.from_catalog(cat)
+    U0, _ = plan.forward(dc)
+    U0 = U0.cpu().numpy()
+    n0 = U0[4, 0].real
+    gam = U0[:4] / n0
+    dev = gam - T.numpy()
+    omn = om.numpy()
+    e2hi = (edges[-1] / LATTICE_UNIT) ** 2
+    x64, y64 = cat.x.astype(np.int64), cat.y.astype(np.int64)
+    rng = np.random.default_rng(19)
+    worst = {0: 0.0, 1: 0.0, 2: 0.0}
+    scales = {k: np.abs(v).max() for k, v in ((0, d1), (1, d2), (2, dw))}
+    for j in rng.choice(cat.n, 64, replace=False):
+        near = np.nonzero((x64 - x64[j]) ** 2 + (y64 - y64[j]) ** 2 < e2hi)[0].astype(np.int32)
+        cidx = torch.from_numpy(near).cuda()
+        for which, arr, h, grad in ((0, dc.g1, 10.0, d1), (1, dc.g2, 10.0, d2), (2, dc.w, 0.4, dw)):
+            v0 = float(arr[j])
+            U = []
+            for sgn in (1, -1):
+                arr[j] = v0 + sgn * h
+                u, _ = plan.forward(dc, cidx)
+                U.append(u.cpu().numpy())
+            arr[j] = v0
+            D = (U[0] - U[1]) / (2 * h)
+            dG = D[:4] / n0 if which < 2 else (D[:4] - gam * D[4, 0].real) / n0
+            fd = float(np.sum(2.0 * omn * (dev.real * dG.real + dev.imag * dG.imag)))
+            g = float(grad[j])
+            err = abs(fd - g) / max(abs(g), 0.05 * scales[which])
+            worst[which] = max(worst[which], err)
+            assert err <= (2e-4 if which < 2 else 1e-3), (int(j), which, fd, g)
+    print(f"500k finite differences, worst relative error g1 {worst[0]:.2e}, g2 {worst[1]:.2e}, "
+          f"w {worst[2]:.2e}", flush=True)

@@ -1,15 +1,29 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
-Tolerance: relative Frobenius error over (b1, b2) per (mu, n) of 1e-6 for
-the FP32 path (split-precision contractions: 1e-5).  Bin membership and
-pair counts are exact and compared bit for bit.
+Bars per (mu, n) block over (b1, b2), every one asserted:
+  * relative Frobenius error 1e-6 for the FP32 path, the three-part bf16
+    and the scaled fp16 splits on the survey-sized workloads, 1e-5 for the
+    two-part bf16 split (and for the fp16 split on the small cases);
+  * largest entry error over the largest |entry| 2e-6 (FP32, three-part
+    bf16, fp16), 2e-5 (two-part bf16);
+  * N_n (n >= 1) also against its own norm: 5e-6;
+  * the normalised Gamma_n at the FP32 bar, 2e-5 for the two-part bf16 split
+    (which reaches 1.0e-5 on single Gamma_n blocks: 1e-5 is met by the
+    three-part split).
+Bin membership and pair counts are exact and compared bit for bit.  The
+survey-sized workloads are checked on 20,000-centre samples against stored
+oracle references (tests/golden/make_fixtures.py, which calls only the
+oracle), and the production configuration (all centres, automatic
+65,536-centre chunks, the captured graph) against the oracle on a catalog
+of two full chunks and a ragged one.
 """
 import numpy as np
 import pytest
 
 from paper_2309_08601_amd.synth import (LATTICE_UNIT, WORKLOADS, Catalog, centre_sample,
                                         make_catalogs, random_catalog)
-from _util import FP32_TOL, SPLIT_TOL, box_for, multipole_errors, rel_fro, rel_max
+from _util import (FP32_MAX_TOL, FP32_TOL, N_OWN_TOL, SPLIT_MAX_TOL, SPLIT_TOL, box_for, multipole_errors,
+                   multipole_max_errors, rel_fro)
 
 pytestmark = pytest.mark.gpu
 
@@ -35,16 +49,21 @@ def _pack(o, n_max):
     return mp.pack_nonneg(o["ups"], o["N"], n_max)
 
 
-def _check(gpu, ref, tol, label=""):
-    """gpu, ref: packed multipoles [..., 5, n_max + 1, B, B]."""
+def _check(gpu, ref, tol, label="", max_tol=None):
+    """gpu, ref: packed multipoles [..., 5, n_max + 1, B, B]; tol bounds the
+    relative Frobenius error per (mu, n), max_tol (default: 2 tol) the
+    largest entry error over the largest |entry|."""
+    if max_tol is None:
+        max_tol = 2 * tol
     e, e_own = multipole_errors(gpu, ref)
-    m = rel_max(gpu, ref)
+    m = multipole_max_errors(gpu, ref)
     worst = np.unravel_index(np.argmax(e), e.shape)
     print(f"{label}: max rel-F {e.max():.3e} at {worst}, Upsilon {e[..., :4, :].max():.3e}, "
           f"N_0 {e[..., 4, 0].max():.3e}, N_n/N_0 {e[..., 4, 1:].max() if e.shape[-1] > 1 else 0:.3e}, "
           f"N_n own {e_own.max():.3e}, max rel-max {m.max():.3e}", flush=True)
     assert e.max() <= tol, (label, e.max(), worst)
-    assert e_own.max() <= 50 * tol, (label, e_own.max())
+    assert m.max() <= max_tol, (label, m.max(), np.unravel_index(np.argmax(m), m.shape))
+    assert e_own.max() <= N_OWN_TOL, (label, e_own.max())
 
 
 def test_harmonics_match_oracle(t3):
@@ -101,20 +120,72 @@ def test_forward_small_2k_workload(t3):
     _check(ups.cpu().numpy(), _pack(o, wl.n_max), FP32_TOL, "small_2k")
 
 
-def test_forward_field_1m_sampled_centres(t3):
-    """1M galaxies in 10 deg x 10 deg, 20 bins 0.5'-100', n_max 30: GPU on a
-    sample of centres against the full neighbour catalog."""
-    _, mp = _oracle()
-    wl = WORKLOADS["field_1m"]
+def _fixture(name):
+    """Stored oracle reference of a 20,000-centre sample (written by
+    tests/golden/make_fixtures.py from the oracle alone) and the regenerated
+    catalog, which must be the one the reference was computed for."""
+    import os
+    from golden.make_fixtures import catalog_sha, fixture_path
+    path = fixture_path(name)
+    if not os.path.exists(path):
+        pytest.skip(f"oracle reference {path} not written")
+    f = np.load(path, allow_pickle=False)
+    wl = WORKLOADS[name]
     cat = make_catalogs(wl)[0]
-    idx = centre_sample(cat.n, 600, seed=11)
+    assert str(f["catalog_sha256"]) == catalog_sha(cat), "regenerated catalog differs from the reference's"
+    return wl, cat, f
+
+
+# Gamma_n = Upsilon_n / N_0 weights every bin pair equally, so its relative
+# error is larger than Upsilon's where a block's few large entries dominate:
+# the two-part bf16 split (about 16 bits per operand, 2^-18 representation
+# error each) reaches 1.0e-5 on single Gamma_n blocks of the 1M field and is
+# held to 2e-5 there; the three-part split meets the FP32 bar.
+_PARITY_CASES = [("fp32", FP32_TOL, FP32_MAX_TOL, FP32_TOL), ("bf16x6", FP32_TOL, FP32_MAX_TOL, FP32_TOL),
+                 ("bf16x3", SPLIT_TOL, SPLIT_MAX_TOL, 2 * SPLIT_TOL)]
+
+
+@pytest.mark.parametrize("prec,tol,max_tol,gamma_tol", _PARITY_CASES)
+def test_forward_field_1m_20k_centres(t3, prec, tol, max_tol, gamma_tol):
+    """1M galaxies in 10 deg x 10 deg, 20 bins 0.5'-100', n_max 30: the GPU
+    on 20,000 random centres against the full neighbour catalog."""
+    wl, cat, f = _fixture("field_1m")
     lo, size = box_for(wl.side)
-    plan = t3.Plan(wl.edges(), wl.n_max, box_lo=lo, box_size=size)
-    dc = t3.DeviceCatalog.from_catalog(cat)
-    ups, npairs = plan.forward(dc, torch.from_numpy(idx).cuda())
-    o = mp.multipoles(cat, wl.edges(), wl.n_max, centres=idx)
+    plan = t3.Plan(wl.edges(), wl.n_max, box_lo=lo, box_size=size, precision=prec)
+    ups, npairs = plan.forward(t3.DeviceCatalog.from_catalog(cat), torch.from_numpy(f["idx"]).cuda())
+    assert npairs == int(f["npairs"])
+    _check(ups.cpu().numpy(), f["ref"], tol, f"field_1m 20k centres {prec}", max_tol)
+    gn, _ = plan.normalise_resum(ups, with_phi=False)
+    eg = rel_fro(gn.cpu().numpy(), f["gamma_n"])
+    print(f"field_1m 20k centres {prec}: Gamma_n max rel-F {eg.max():.3e}", flush=True)
+    assert eg.max() <= gamma_tol
+
+
+def test_production_configuration_matches_oracle(t3):
+    """The configuration the benchmark times: every galaxy a centre, the
+    automatic chunk capacity (65,536 centres at n_max 30), the chunk schedule
+    captured as one HIP graph, the stage-2 slicing and XCD balancing at full
+    chunk size: 140,000 galaxies at the 1M field's density (two full chunks
+    and a ragged one of 8,928), 8 bins 0.5'-12' (inner bins one lane per
+    centre, outer bins one wavefront per centre), n_max 30, against the
+    oracle over every centre."""
+    import dataclasses
+    _, mp = _oracle()
+    n = 140_000
+    # the 1M field's shear and weight model on a field that holds 140k
+    # galaxies at the same density
+    wl = dataclasses.replace(WORKLOADS["field_1m"], name="field_140k", n_gal=[n],
+                             side=float(np.sqrt(n / 2.78)), n_bins=8, theta_max=12.0, seed_index=6)
+    cat = make_catalogs(wl)[0]
+    edges = wl.edges()
+    nm = 30
+    side = wl.side
+    lo, size = box_for(side)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size)
+    ups, npairs = plan.forward(t3.DeviceCatalog.from_catalog(cat))
+    o = mp.multipoles(cat, edges, nm)
     assert npairs == o["npairs"]
-    _check(ups.cpu().numpy(), _pack(o, wl.n_max), FP32_TOL, "field_1m sample")
+    _check(ups.cpu().numpy(), _pack(o, nm), FP32_TOL, "production configuration, 140k centres")
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", FP32_TOL), ("bf16x3", SPLIT_TOL)])
@@ -136,36 +207,27 @@ def test_forward_field_3m_33bins_sampled_centres(t3, prec, tol):
     _check(ups.cpu().numpy(), _pack(o, wl.n_max), tol, f"field_3m_33bins sample {prec}")
 
 
-_FIELD_4M = {}
-
-
-def _field_4m_reference():
-    """4M galaxies in 20 deg x 20 deg, 30 bins 0.5'-200', n_max 40 (the
-    precision workload): oracle on a sample of centres, computed once."""
-    if not _FIELD_4M:
-        _, mp = _oracle()
-        wl = WORKLOADS["field_4m"]
-        cat = make_catalogs(wl)[0]
-        idx = centre_sample(cat.n, 160, seed=13)
-        o = mp.multipoles(cat, wl.edges(), wl.n_max, centres=idx)
-        _FIELD_4M.update(wl=wl, cat=cat, idx=idx, npairs=o["npairs"], ref=_pack(o, wl.n_max))
-    return _FIELD_4M
-
-
-@pytest.mark.parametrize("prec,tol", [("fp32", FP32_TOL), ("bf16x6", FP32_TOL), ("fp16x3", SPLIT_TOL),
-                                      ("bf16x3", 2 * SPLIT_TOL)])
-def test_forward_field_4m_sampled_centres(t3, prec, tol):
-    """n_max = 40 runs the two-pass stage-1 variant and B = 30 bins nearly
-    fills the 32-row MFMA tiles.  BF16X3 keeps about 16 bits per operand, so
-    its per-(mu, n) error reaches about 1e-5 and the maximum over the 164
-    multipoles of a 160-centre sample is allowed twice that."""
-    r = _field_4m_reference()
-    wl = r["wl"]
+@pytest.mark.parametrize("prec,tol,max_tol,gamma_tol",
+                         _PARITY_CASES + [("fp16x3", FP32_TOL, FP32_MAX_TOL, FP32_TOL)])
+def test_forward_field_4m_20k_centres(t3, prec, tol, max_tol, gamma_tol):
+    """The precision workload: 4M galaxies in 20 deg x 20 deg, 30 bins
+    0.5'-200', n_max 40 (the two-pass stage-1 variant; B = 30 nearly fills
+    the 32-row MFMA tiles), on 20,000 random centres.  The two-part bf16
+    split keeps about 16 bits of each operand: its Frobenius error stays
+    below 1e-5 per (mu, n) of Upsilon, its largest entry error and its
+    Gamma_n error below 2e-5; the three-part bf16 split (all 24 bits) and
+    the scaled fp16 split meet the FP32 bars."""
+    wl, cat, f = _fixture("field_4m")
     lo, size = box_for(wl.side)
     plan = t3.Plan(wl.edges(), wl.n_max, box_lo=lo, box_size=size, precision=prec)
-    ups, npairs = plan.forward(t3.DeviceCatalog.from_catalog(r["cat"]), torch.from_numpy(r["idx"]).cuda())
-    assert npairs == r["npairs"]
-    _check(ups.cpu().numpy(), r["ref"], tol, f"field_4m sample {prec}")
+    ups, npairs = plan.forward(t3.DeviceCatalog.from_catalog(cat), torch.from_numpy(f["idx"]).cuda())
+    assert npairs == int(f["npairs"])
+    _check(ups.cpu().numpy(), f["ref"], tol, f"field_4m 20k centres {prec}", max_tol)
+    gn, _ = plan.normalise_resum(ups, with_phi=False)
+    eg = rel_fro(gn.cpu().numpy(), f["gamma_n"])
+    print(f"field_4m 20k centres {prec}: Gamma_n max rel-F {eg.max():.3e}, per mu "
+          f"{[float(f'{v:.3e}') for v in eg.max(axis=1)]}", flush=True)
+    assert eg.max() <= gamma_tol
 
 
 @pytest.mark.parametrize("prec,tol", [("bf16x3", SPLIT_TOL), ("fp16x3", SPLIT_TOL), ("bf16x6", FP32_TOL)])
