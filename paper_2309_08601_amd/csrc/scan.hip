@@ -77,9 +77,11 @@ struct PassShape {
 };
 
 // One neighbour through the recurrence.  acc layout: [4*NG S-sums][2*NW W][NX extras]
-template <int GA, int GB, int WA, int WB, bool EXTRA, int V>
+// SEG > 0 (order segments, see k_scan_seg): when upper is set the orders are
+// SEG + GA .. SEG + GB (the chain starts from the FP64 power z^SEG), else GA .. GB.
+template <int GA, int GB, int WA, int WB, bool EXTRA, int V, int SEG = 0>
 __device__ __forceinline__ void accumulate(float (&acc)[V], int dx, int dy, float cr, float ci,
-                                           float wt)
+                                           float wt, bool upper = false, bool with_extra = true)
 {
     using S = PassShape<GA, GB, WA, WB, EXTRA>;
     static_assert(V == S::V, "accumulator size");
@@ -93,8 +95,28 @@ __device__ __forceinline__ void accumulate(float (&acc)[V], int dx, int dy, floa
     const double z2r = fma(zr, zr, -zi * zi), z2i = 2.0 * zr * zi;
     const double z4r = fma(z2r, z2r, -z2i * z2i), z4i = 2.0 * z2r * z2i;
     const double z8r = fma(z4r, z4r, -z4i * z4i), z8i = 2.0 * z4r * z4i;
-    // running FP64 anchor a = z^{M0}
+    // running FP64 anchor a = z^{M0} (times z^SEG for the upper segment)
     double ar = 1.0, ai = 0.0;
+    if constexpr (SEG > 0) {
+        static_assert(S::M0 == 0 && SEG < 64, "segments start at order 1");
+        // z^SEG from the binary powers z, z^2, z^4, ... (FP64)
+        double pr = zr, pi = zi, br = 1.0, bi = 0.0;
+#pragma unroll
+        for (int bit = 0; (1 << bit) <= SEG; ++bit) {
+            if (SEG & (1 << bit)) {
+                const double tr = fma(br, pr, -bi * pi);
+                bi = fma(br, pi, bi * pr);
+                br = tr;
+            }
+            if ((2 << bit) <= SEG) {
+                const double qr = fma(pr, pr, -pi * pi);
+                pi = 2.0 * pr * pi;
+                pr = qr;
+            }
+        }
+        ar = upper ? br : 1.0;
+        ai = upper ? bi : 0.0;
+    }
 #pragma unroll
     for (int k = 0; k < S::M0 / kAnchor; ++k) {
         const double tr = fma(ar, z8r, -ai * z8i);
@@ -152,7 +174,7 @@ __device__ __forceinline__ void accumulate(float (&acc)[V], int dx, int dy, floa
         down1(b0 + 8, (float)ar, (float)ai);
         if (b0 + 8 <= S::MTOP) add(b0 + 8, (float)ar, (float)ai);
     }
-    if constexpr (EXTRA) {
+    if (EXTRA && with_extra) {
         constexpr int k = 4 * S::NG + 2 * S::NW;
         // G_0 += c ; W_0 += w (imaginary part stays 0)
         acc[k + 0] += cr;
@@ -376,6 +398,111 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
     if (lane == 0 && a.npairs) atomicAdd(a.npairs, pairs);
 }
 
+// ---------------------------------------------------------------- order segments
+// For n_max above what one pass holds in registers, a wavefront splits its
+// orders instead of sweeping every annulus twice: lanes 0-31 accumulate
+// orders 1..S of every in-bin neighbour, lanes 32-63 orders S+1..2S.  The code
+// is the same for both halves -- the upper one starts its FP64 anchor chain
+// at z^S -- and each half takes all 64 neighbours of a batch in two steps
+// (first the lower half entries 0-31 and the upper half 32-63, then the other
+// way round), so the annulus sweep, the candidate tests and the compaction run
+// once per centre and bin.  The j = k sums are accumulated in the first step
+// only, so each neighbour's are taken once, by one half or the other, and the
+// two halves' totals are added at the end.  The reduce-scatter stays within
+// each 32-lane half: permlane16 swaps for lane bit 4, then the same DPP steps
+// as the full-wave reduction.
+template <int V, int P>
+__device__ __forceinline__ void flush_half(float (&acc)[V], double (&accd)[P], int lane, int ng)
+{
+    constexpr int VP = 32 * P;
+    float v[VP];
+#pragma unroll
+    for (int k = 0; k < V; ++k) v[k] = acc[k];
+    // S -> G conversion on the lane partials (P is not even for every shape)
+#pragma unroll
+    for (int k = 0; k < V / 4; ++k)
+        if (k < ng) s_to_g(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+#pragma unroll
+    for (int k = V; k < VP; ++k) v[k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < VP / 2; ++k) v[k] = add_swap16(v[k], v[k + VP / 2]);
+    dpp_step<kDppRowRor8, VP / 4>(v, (lane & 8) != 0);
+    dpp_step<kDppRowHalfMirror, VP / 8>(v, (lane & 4) != 0);
+    dpp_step<kDppQuadXor2, VP / 16>(v, (lane & 2) != 0);
+    dpp_step<kDppQuadXor1, VP / 32>(v, (lane & 1) != 0);
+#pragma unroll
+    for (int k = 0; k < P; ++k) accd[k] += (double)v[k];
+#pragma unroll
+    for (int k = 0; k < V; ++k) acc[k] = 0.0f;
+}
+
+template <int SW>
+__device__ __forceinline__ unsigned long long scan_task_seg(const ScanArgs &a, int ci, int lane, const SweepLDS &lds)
+{
+    using S = PassShape<1, SW, 1, SW, true>;
+    constexpr int P = (S::V + 31) / 32;   // slots per lane after the half-wave reduction
+    constexpr int VP = 32 * P;
+    const int2 cp = a.cpos[ci];
+    float *out = a.out[0];
+    const bool upper = lane >= 32;
+    const int h = lane & 31;
+    unsigned long long pairs = 0;
+    for (int b = 0; b < a.n_bins; ++b) {
+        float acc[S::V];
+#pragma unroll
+        for (int k = 0; k < S::V; ++k) acc[k] = 0.0f;
+        double accd[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) accd[k] = 0.0;
+        int batches = 0;  // wave-uniform
+        pairs += (unsigned long long)sweep_annulus_halves(
+            a.sw[0], cp, a.e2[b], a.e2[b + 1], lane, lds, [&](const int4 &e, float ew, int step) {
+                accumulate<1, SW, 1, SW, true, S::V, SW>(acc, e.x, e.y, __int_as_float(e.z),
+                                                         __int_as_float(e.w), ew, upper, step == 0);
+            },
+            [&]() {
+                // two neighbours per lane per batch: FP32 runs of at most 64 terms
+                if (++batches == kFlush / 2) {
+                    flush_half<S::V, P>(acc, accd, lane, S::NG);
+                    batches = 0;
+                }
+            });
+        if (batches > 0) flush_half<S::V, P>(acc, accd, lane, S::NG);
+        // half (lane >> 5) holds slots [P h, P h + P) of its segment; the j = k
+        // sums (slots 6 S and up) are split between the halves: add them
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const double other = __shfl_xor(accd[k], 32, 64);
+            if (P * h + k >= 6 * SW) accd[k] += other;
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int pl = a.dest[(upper ? VP : 0) + P * h + k];
+            if (pl >= 0) out[chunk_offset(pl, ci, a.b_out0 + b, a.K, a.B_out)] = (float)accd[k];
+        }
+    }
+    return pairs;
+}
+
+// One wavefront per centre, two order segments per wavefront (one catalog).
+template <int SW>
+__global__ __launch_bounds__(64 * kWaves, 2) void k_scan_seg(ScanArgs a)
+{
+    __shared__ int4 q_xyc[kWaves][kRing];
+    __shared__ int2 q_wi[kWaves][kRing];
+    __shared__ int2 spans[kWaves][2 * kRowsPerBlock + 1];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const SweepLDS lds{q_xyc[wv], q_wi[wv], spans[wv]};
+    const int nwg = gridDim.x;  // multiple of 8
+    const int per = nwg >> 3;
+    const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int ci = wg * kWaves + wv;
+    if (ci >= a.n_c) return;  // whole wavefront leaves together
+    const unsigned long long pairs = scan_task_seg<SW>(a, ci, lane, lds);
+    if (lane == 0 && a.npairs) atomicAdd(a.npairs, pairs);
+}
+
 // Lane per centre, for bins with few neighbours per centre: the wavefront's
 // 64 centres are swept independently (each lane walks its own cell rows), so
 // the per-(centre, bin) cost follows the neighbour count instead of a full
@@ -529,6 +656,8 @@ struct Variant {
     int npass;
     PassDesc pass[2];
     PassDesc wext;
+    int seg = 0;                        // order-segment width of k_scan_seg (0: none)
+    void (*kernel_seg)(ScanArgs) = nullptr;
 };
 
 template <int C>
@@ -550,8 +679,10 @@ const std::vector<Variant> &variants()
         {24, 1, {make_pass<1, 27, 1, 24, true>()}, make_wext<24>()},
         {30, 1, {make_pass<1, 33, 1, 30, true>()}, make_wext<30>()},
         {32, 1, {make_pass<1, 35, 1, 32, true>()}, make_wext<32>()},
-        {40, 2, {make_pass<1, 22, 1, 20, true>(), make_pass<23, 43, 21, 40, false>()}, make_wext<40>()},
-        {48, 2, {make_pass<1, 26, 1, 24, true>(), make_pass<27, 51, 25, 48, false>()}, make_wext<48>()},
+        {40, 2, {make_pass<1, 22, 1, 20, true>(), make_pass<23, 43, 21, 40, false>()}, make_wext<40>(), 22,
+         k_scan_seg<22>},
+        {48, 2, {make_pass<1, 26, 1, 24, true>(), make_pass<27, 51, 25, 48, false>()}, make_wext<48>(), 26,
+         k_scan_seg<26>},
         {64, 2, {make_pass<1, 34, 1, 32, true>(), make_pass<35, 67, 33, 64, false>()}, make_wext<64>()},
     };
     return v;
@@ -598,6 +729,47 @@ std::vector<short> dest_table(const PassDesc &p, const ChunkLayout &L)
     return d;
 }
 
+// Destination table of k_scan_seg: [2 halves][32 P] slots -> plane or -1.
+// Half h holds orders h S + 1 .. h S + S (G pairs, then W), then the extra
+// sums, of which only the lower half's are kept; W orders above the
+// variant's capacity belong to the W-extension pass.
+std::vector<short> dest_table_seg(int S, int cap, const ChunkLayout &L)
+{
+    const int V = 6 * S + 11;
+    const int VP = 32 * ((V + 31) / 32);
+    std::vector<short> d(2 * VP, -1);
+    const int nm = L.n_max;
+    for (int h = 0; h < 2; ++h) {
+        short *t = d.data() + h * VP;
+        for (int k = 0; k < S; ++k) {
+            const int m = h * S + 1 + k;
+            if (m <= nm - 1) {
+                t[4 * k + 0] = (short)L.plane_G(m, 0);
+                t[4 * k + 2] = (short)L.plane_G(m, 1);
+            }
+            if (m <= nm + 3) {
+                t[4 * k + 1] = (short)L.plane_G(-m, 0);
+                t[4 * k + 3] = (short)L.plane_G(-m, 1);
+            }
+            if (m <= L.w_max && m <= cap) {
+                t[4 * S + 2 * k] = (short)L.plane_W(m, 0);
+                t[4 * S + 2 * k + 1] = (short)L.plane_W(m, 1);
+            }
+        }
+        if (h == 0) {
+            const int k = 6 * S;
+            if (nm >= 1) {
+                t[k + 0] = (short)L.plane_G(0, 0);
+                t[k + 1] = (short)L.plane_G(0, 1);
+            }
+            t[k + 2] = (short)L.plane_W(0, 0);
+            t[k + 3] = (short)L.plane_W(0, 1);  // stays zero
+            for (int j = 0; j < 7; ++j) t[k + 4 + j] = (short)L.plane_D(j);
+        }
+    }
+    return d;
+}
+
 }  // namespace
 
 int scan_prepare(t3_plan *plan)
@@ -623,6 +795,11 @@ int scan_prepare(t3_plan *plan)
     if (plan->w_max > vars[vi].cap) {  // W orders beyond the main passes
         plan->scan_dest_off[vars[vi].npass] = all.size();
         auto d = dest_table(vars[vi].wext, L);
+        all.insert(all.end(), d.begin(), d.end());
+    }
+    if (vars[vi].seg > 0) {  // one sweep with two order segments per wavefront
+        plan->scan_dest_off[3] = all.size();
+        auto d = dest_table_seg(vars[vi].seg, vars[vi].cap, L);
         all.insert(all.end(), d.begin(), d.end());
     }
     T3_TRY(plan->dest.reserve(all.size() * sizeof(short)));
@@ -704,10 +881,27 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
         a.queue = nullptr;
         a.grab = 0;
     }
-    for (int p = 0; p < npass; ++p) {
+    const bool seg = var.kernel_seg && !a.queue;
+    for (int p = seg ? var.npass - 1 : 0; p < npass; ++p) {
         const PassDesc &pd = p < var.npass ? var.pass[p] : var.wext;
         a.dest = plan->dest.as<short>() + plan->scan_dest_off[p];
         a.npairs = p == 0 ? npairs : nullptr;  // count pairs once
+        if (seg && p < var.npass) {
+            // every main-pass order in one sweep: k_scan_seg stands for the passes
+            a.dest = plan->dest.as<short>() + plan->scan_dest_off[3];
+            a.npairs = npairs;
+            const int nwg1 = (((n_c + kWaves - 1) / kWaves) + 7) & ~7;
+            for (int k = 0; k < n_z; ++k) {
+                ScanArgs a1 = a;
+                const int z = a.order[k];
+                a1.sw[0] = a.sw[z];
+                a1.out[0] = a.out[z];
+                a1.n_z = 1;
+                hipLaunchKernelGGL(var.kernel_seg, dim3((unsigned)nwg1), dim3(64 * kWaves), 0, s, a1);
+                T3_HIP_CHECK(hipGetLastError());
+            }
+            continue;
+        }
         if (a.queue) {
             // persistent grid over every (centre, catalog) task
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, a.queue);

@@ -111,15 +111,16 @@ __device__ __forceinline__ int locate(const int2 *span, int &t, int v)
     return s.y + (v - s.x);
 }
 
-// Sweep one annulus.  batch(e, ew, gidx, active) is called with the lane's
-// queue entry; it must not touch the LDS slices.  Returns the number of
-// in-bin neighbours (wave-uniform).  row_off, row_step: this wavefront
-// sweeps only the cell rows row_lo + row_off + k row_step (wavefronts that
-// split one annulus between them).
-template <class Batch>
-__device__ __forceinline__ int sweep_annulus(const SweepArgs &a, int2 cp, double e2lo, double e2hi,
-                                             int lane, const SweepLDS &L, Batch &&batch, int row_off = 0,
-                                             int row_step = 1)
+// Sweep one annulus: the candidate walk and the compaction into the LDS ring
+// are shared; consume(head, count) is called (wave-uniformly) whenever 64
+// neighbours are pending (count = 64) and once at the end for the remainder
+// (0 < count < 64), with the ring index of the first pending entry.
+// row_off, row_step: this wavefront sweeps only the cell rows row_lo +
+// row_off + k row_step (wavefronts that split one annulus between them).
+// Returns the number of in-bin neighbours (wave-uniform).
+template <class Consume>
+__device__ __forceinline__ int sweep_core(const SweepArgs &a, int2 cp, double e2lo, double e2hi, int lane,
+                                          const SweepLDS &L, Consume &&consume, int row_off, int row_step)
 {
     const CellGrid &g = a.g;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
@@ -184,10 +185,7 @@ __device__ __forceinline__ int sweep_annulus(const SweepArgs &a, int2 cp, double
             tail += __popcll(m);
             if (tail - head >= 64) {
                 wave_sync_lds();
-                const int slot = (head + lane) & (kRing - 1);
-                const int4 e = L.q_xyc[slot];
-                const int2 ew = L.q_wi[slot];
-                batch(e, __int_as_float(ew.x), ew.y, true);
+                consume(head, 64);
                 head += 64;
                 __builtin_amdgcn_wave_barrier();
             }
@@ -200,18 +198,65 @@ __device__ __forceinline__ int sweep_annulus(const SweepArgs &a, int2 cp, double
     }
     if (tail > head) {
         wave_sync_lds();
-        const bool act = lane < tail - head;
-        const int slot = (head + lane) & (kRing - 1);
-        int4 e = L.q_xyc[slot];
-        int2 ew = L.q_wi[slot];
-        if (!act) {
-            e = make_int4(1, 0, 0, 0);
-            ew = make_int2(0, 0);
-        }
-        batch(e, __int_as_float(ew.x), ew.y, act);
+        consume(head, tail - head);
         __builtin_amdgcn_wave_barrier();
     }
     return tail;
+}
+
+// Sweep one annulus, every lane one pending neighbour per batch.
+// batch(e, ew, gidx, active) is called with the lane's queue entry (inactive
+// lanes of the last batch get dx = 1, dy = 0 and zero factors); it must not
+// touch the LDS slices.
+template <class Batch>
+__device__ __forceinline__ int sweep_annulus(const SweepArgs &a, int2 cp, double e2lo, double e2hi,
+                                             int lane, const SweepLDS &L, Batch &&batch, int row_off = 0,
+                                             int row_step = 1)
+{
+    return sweep_core(
+        a, cp, e2lo, e2hi, lane, L,
+        [&](int head, int count) {
+            const bool act = lane < count;
+            const int slot = (head + lane) & (kRing - 1);
+            int4 e = L.q_xyc[slot];
+            int2 ew = L.q_wi[slot];
+            if (!act) {
+                e = make_int4(1, 0, 0, 0);
+                ew = make_int2(0, 0);
+            }
+            batch(e, __int_as_float(ew.x), ew.y, act);
+        },
+        row_off, row_step);
+}
+
+// Sweep one annulus, every half-wave (lanes 0-31, 32-63) taking all pending
+// neighbours of a batch in two steps: in step 0 a lower-half lane gets entry
+// (lane & 31) and an upper-half lane entry 32 + (lane & 31), in step 1 the
+// other one; item(e, ew, step) is called for each, then done() once per
+// batch.  Inactive entries as in sweep_annulus.
+template <class Item, class Done>
+__device__ __forceinline__ int sweep_annulus_halves(const SweepArgs &a, int2 cp, double e2lo, double e2hi,
+                                                    int lane, const SweepLDS &L, Item &&item, Done &&done)
+{
+    return sweep_core(
+        a, cp, e2lo, e2hi, lane, L,
+        [&](int head, int count) {
+#pragma unroll 1
+            for (int k = 0; k < 2; ++k) {
+                const int j = (((lane >> 5) ^ k) << 5) + (lane & 31);
+                const bool act = j < count;
+                const int slot = (head + j) & (kRing - 1);
+                int4 e = L.q_xyc[slot];
+                int2 ew = L.q_wi[slot];
+                if (!act) {
+                    e = make_int4(1, 0, 0, 0);
+                    ew = make_int2(0, 0);
+                }
+                item(e, __int_as_float(ew.x), k);
+            }
+            done();
+        },
+        0, 1);
 }
 
 }  // namespace t3
