@@ -173,6 +173,18 @@ int t3_plan_create(const t3_params *params, t3_plan **out);
 /* Release the plan and its workspace (synchronises the device first). */
 void t3_plan_destroy(t3_plan *plan);
 
+/* Graph statistics of the plan (HOST outputs, optional): how many times the
+ * chunk schedule of t3_forward / t3_forward_tomo was captured into a HIP
+ * graph and how many times a captured graph was launched.  A schedule is
+ * captured once per key -- the launch shapes and every address and value
+ * its kernels take (catalog and centre-set sizes, cell grid, plan buffers,
+ * lane-bin split, launch mode, precision, flags, device) -- and replayed
+ * while the key is unchanged; the cell lists and centre sets it reads are
+ * rebuilt in place before each launch and its output is copied to the
+ * caller's, so new data of the same geometry, written anywhere, replays the
+ * same graph. */
+int t3_graph_stats(const t3_plan *plan, int64_t *captures, int64_t *launches);
+
 /* Device memory the plan currently holds (in_use, HOST, optional) and the
  * largest amount it has held (peak, HOST, optional), in bytes; never more
  * than params.max_workspace_bytes when that is set.  Buffers grow on demand

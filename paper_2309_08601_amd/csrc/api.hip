@@ -227,11 +227,16 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
         T3_TRY(plan->kept.reserve(sizeof(float) * zstride * (size_t)std::max<int64_t>(n_chunks, 1)));
     }
 
+    // the captured schedule writes into a plan-owned buffer, copied to the
+    // caller's output after each launch, so that a replay does not depend
+    // on where the caller's output lives
+    if (graph) T3_TRY(plan->graph_out.reserve(sizeof(double) * n_out));
+    double *const sched_out = graph ? plan->graph_out.as<double>() : ups_out;
     auto schedule = [&](hipStream_t q) -> int {
-        T3_TRY(zero_doubles(ups_out, n_out, q));
+        T3_TRY(zero_doubles(sched_out, n_out, q));
         for (int z1 = 0; z1 < n_z; ++z1) {
             const CentreSet &cs = plan->csets[z1];
-            double *out = ups_out + per_set * (size_t)n_z * n_z * z1;
+            double *out = sched_out + per_set * (size_t)n_z * n_z * z1;
             for (int64_t c0 = 0; c0 < cs.n; c0 += L.K) {
                 const int n = (int)((cs.n - c0) < L.K ? (cs.n - c0) : L.K);
                 float *planes = keep ? plan->kept.as<float>() + (size_t)(c0 / L.K) * zstride : plan->chunk.as<float>();
@@ -248,26 +253,66 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
     };
 
     if (graph) {
-        if (!plan->cap_stream) T3_HIP_CHECK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
-        // order the capture stream after the set-up work of this call
-        T3_HIP_CHECK(hipStreamSynchronize(s));
-        if (plan->graph_exec) {
-            (void)hipGraphExecDestroy(plan->graph_exec);
-            plan->graph_exec = nullptr;
+        // The captured schedule bakes in every launch shape and kernel
+        // argument: shapes, buffer addresses, the cell grid, the lane-bin
+        // split, launch mode, precision and flags.  It is captured once per
+        // such key and replayed by later calls (the cell lists and centre
+        // sets it reads are rebuilt in place before each launch).
+        std::vector<int64_t> key;
+        auto put = [&](int64_t v) { key.push_back(v); };
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        put(dev);
+        put(n_z);
+        put(L.K);
+        put(L.n_max);
+        put(L.w_max);
+        put(L.B);
+        put(n_lane);
+        put(plan->scan_mode);
+        put(plan->scan_var);
+        put(plan->precision);
+        put((int64_t)plan->flags);
+        put(keep ? 1 : 0);
+        put(jk ? 1 : 0);
+        for (const void *p : {plan->graph_out.ptr, plan->chunk.ptr, plan->kept.ptr, plan->partial.ptr, plan->diag.ptr,
+                              plan->scales.ptr, plan->counter.ptr, plan->queue.ptr, plan->dest.ptr})
+            put((int64_t)(uintptr_t)p);
+        for (int z = 0; z < n_z; ++z) {
+            const SortedCatalog &c = plan->cats[z];
+            const CentreSet &cs = plan->csets[z];
+            for (int64_t v : {(int64_t)order[z], c.n, (int64_t)(uintptr_t)c.pos.ptr, (int64_t)(uintptr_t)c.cw.ptr,
+                              (int64_t)(uintptr_t)c.cell_start.ptr, (int64_t)c.grid.cell, (int64_t)c.grid.ncx,
+                              (int64_t)c.grid.ncy, (int64_t)c.grid.ox, (int64_t)c.grid.oy, cs.n,
+                              (int64_t)(uintptr_t)cs.pos.ptr, (int64_t)(uintptr_t)cs.cw.ptr})
+                put(v);
         }
-        T3_HIP_CHECK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
-        const int rc = schedule(plan->cap_stream);
-        hipGraph_t g = nullptr;
-        const hipError_t ec = hipStreamEndCapture(plan->cap_stream, &g);
-        if (rc != T3_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
+        if (!(plan->graph_exec && key == plan->graph_key)) {
+            if (!plan->cap_stream)
+                T3_HIP_CHECK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+            if (plan->graph_exec) {
+                (void)hipGraphExecDestroy(plan->graph_exec);
+                plan->graph_exec = nullptr;
+                plan->graph_key.clear();
+            }
+            T3_HIP_CHECK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
+            const int rc = schedule(plan->cap_stream);
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(plan->cap_stream, &g);
+            if (rc != T3_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (ec != hipSuccess) return fail(T3_EHIP, std::string("graph capture: ") + hipGetErrorString(ec));
+            const hipError_t ei = hipGraphInstantiate(&plan->graph_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) return fail(T3_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+            plan->graph_key = std::move(key);
+            ++plan->graph_captures;
         }
-        if (ec != hipSuccess) return fail(T3_EHIP, std::string("graph capture: ") + hipGetErrorString(ec));
-        const hipError_t ei = hipGraphInstantiate(&plan->graph_exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ei != hipSuccess) return fail(T3_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
         T3_HIP_CHECK(hipGraphLaunch(plan->graph_exec, s));
+        ++plan->graph_replays;
+        T3_HIP_CHECK(hipMemcpyAsync(ups_out, sched_out, sizeof(double) * n_out, hipMemcpyDeviceToDevice, s));
     } else {
         T3_TRY(schedule(s));
     }
@@ -386,6 +431,7 @@ void t3_plan_destroy(t3_plan *plan)
     plan->centres.cw.release();
     plan->chunk.release();
     plan->kept.release();
+    plan->graph_out.release();
     plan->partial.release();
     plan->diag.release();
     plan->flag.release();
@@ -724,6 +770,14 @@ int t3_autotune(t3_plan *plan, const t3_catalog *cats, int32_t n_z, int64_t samp
     } catch (...) {
         return fail(T3_EINVAL, "t3_autotune: exception");
     }
+}
+
+int t3_graph_stats(const t3_plan *plan, int64_t *captures, int64_t *launches)
+{
+    if (!plan) return fail(T3_EINVAL, "t3_graph_stats: null plan");
+    if (captures) *captures = plan->graph_captures;
+    if (launches) *launches = plan->graph_replays;
+    return T3_OK;
 }
 
 int t3_workspace_bytes(const t3_plan *plan, int64_t *in_use, int64_t *peak)

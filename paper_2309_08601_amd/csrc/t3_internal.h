@@ -169,6 +169,10 @@ struct t3_plan {
     int scan_mode = 0;          // 0: one wavefront per task, 1: persistent work queue
     hipStream_t cap_stream = nullptr;     // graph capture stream (default priority)
     hipGraphExec_t graph_exec = nullptr;  // last captured forward schedule
+    std::vector<int64_t> graph_key;       // what that schedule was captured for
+    t3::DevBuf graph_out;                 // the schedule's output, copied to the caller's
+    int64_t graph_captures = 0;           // schedules captured by this plan
+    int64_t graph_replays = 0;            // graph launches (first launch included)
     t3::DevBuf chunk;     // stage-1 planes
     t3::DevBuf partial;   // stage-2 FP64 partial tiles
     t3::DevBuf diag;      // FP64 j = k sums per chunk
@@ -193,7 +197,7 @@ struct t3_plan {
     t3::Budget budget;       // device memory held against max_workspace_bytes
     t3::DevBuf det;          // T3_FLAG_DETERMINISTIC adjoint: fixed-point and FP64 accumulators
     int scan_var = -1;          // stage-1 variant index (see scan.hip)
-    size_t scan_dest_off[3] = {0, 0, 0};  // main passes, then the W extension
+    size_t scan_dest_off[4] = {0, 0, 0, 0};  // main passes, the W extension, the order-segment kernel
 
     // optional stage timing (T3_FLAG_TIMING)
     std::vector<hipEvent_t> events;  // pool, pairs (start, stop)

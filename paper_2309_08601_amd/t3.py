@@ -66,7 +66,7 @@ class T3Error(RuntimeError):
 
 EXPORTED = ["t3_plan_create", "t3_plan_destroy", "t3_forward", "t3_forward_tomo", "t3_harmonics",
             "t3_normalise_resum", "t3_normalise_backward", "t3_backward", "t3_autotune", "t3_stage_times",
-            "t3_workspace_bytes", "t3_error_string",
+            "t3_workspace_bytes", "t3_graph_stats", "t3_error_string",
             "t3_last_error_message", "t3_version"]
 
 
@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.t3_stage_times.restype = ctypes.c_int
     lib.t3_workspace_bytes.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64)]
     lib.t3_workspace_bytes.restype = ctypes.c_int
+    lib.t3_graph_stats.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64)]
+    lib.t3_graph_stats.restype = ctypes.c_int
     lib.t3_error_string.argtypes = [ctypes.c_int]
     lib.t3_error_string.restype = ctypes.c_char_p
     lib.t3_last_error_message.argtypes = []
@@ -394,6 +396,13 @@ class Plan:
         nl = (ctypes.c_int64 * 4)()
         _check(_lib.t3_stage_times(self._h, ms, nl))
         return list(ms), list(nl)
+
+    def graph_stats(self):
+        """(captures, launches) of the plan's chunk-schedule graph."""
+        cap = ctypes.c_int64(0)
+        lau = ctypes.c_int64(0)
+        _check(_lib.t3_graph_stats(self._h, ctypes.byref(cap), ctypes.byref(lau)))
+        return int(cap.value), int(lau.value)
 
     def workspace_bytes(self):
         """(in use, peak) device bytes held by the plan."""
