@@ -210,6 +210,27 @@ int t3_workspace_bytes(const t3_plan *plan, int64_t *in_use, int64_t *peak);
 int t3_forward(t3_plan *plan, const t3_catalog *cat, const int32_t *centres,
                int64_t n_centres, double *ups_out, int64_t *n_pairs, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * t3_forward pass -- same arguments, same results -- with every internal
+ * buffer (cell list, centre set, stage-1 planes, stage-2 partial sums,
+ * counters, destination tables) carved from one static device array of
+ * 256 MiB that the library holds on each GPU it runs on until the process
+ * ends.  It calls no hipMalloc, hipFree or other allocating routine and
+ * never touches the plan's own workspace; it always launches eagerly (no
+ * graph, no timing events).  Before any launch it picks the largest chunk of
+ * centres (a multiple of 256, at most t3_forward's) whose buffers fit the
+ * array, and returns T3_ENOMEM with a message stating the bytes needed if
+ * even chunks of 256 centres do not fit (the cell list and centre set take
+ * about 57 bytes per galaxy: roughly 4.5 million galaxies, all of them
+ * centres, at n_max 30 and 20 bins).
+ * Every call on one GPU uses that GPU's array: calls that overlap in time
+ * on one GPU (other threads, other streams) race and must be serialised by
+ * the caller.  The buffers are cleared by the call itself where it needs
+ * zeros, as in t3_forward. */
+int t3_forward_noalloc(t3_plan *plan, const t3_catalog *cat, const int32_t *centres,
+                       int64_t n_centres, double *ups_out, int64_t *n_pairs, void *stream);
+
 /* Tomographic forward pass over all ordered bin triples (Sect. 3.5,
  * eq. tomoGn).  cats: HOST array of n_z catalogs (device arrays).
  * centres: HOST array of n_z DEVICE pointers, or NULL for every galaxy of

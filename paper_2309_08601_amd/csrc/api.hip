@@ -22,6 +22,7 @@ int fail(int code, const std::string &msg)
 }
 
 static thread_local Budget *g_budget = nullptr;
+static thread_local Arena *g_arena = nullptr;
 
 Budget *active_budget() { return g_budget; }
 
@@ -29,8 +30,38 @@ BudgetScope::BudgetScope(Budget *b) : prev(g_budget) { g_budget = b; }
 
 BudgetScope::~BudgetScope() { g_budget = prev; }
 
+ArenaScope::ArenaScope(Arena *a) : prev(g_arena), mine(a) { g_arena = a; }
+
+ArenaScope::~ArenaScope()
+{
+    // every buffer carved in the scope gets its plan-owned state back
+    for (auto it = mine->saved.rbegin(); it != mine->saved.rend(); ++it) *it->first = it->second;
+    mine->saved.clear();
+    g_arena = prev;
+}
+
+static bool in_arena(const Arena *ar, const void *p)
+{
+    return ar && p && (const char *)p >= ar->base && (const char *)p < ar->base + ar->size;
+}
+
 int DevBuf::reserve(size_t want)
 {
+    if (Arena *ar = g_arena) {
+        // carve from the arena: no allocation, no synchronisation
+        const bool carved = in_arena(ar, ptr);
+        if (carved && want <= bytes) return T3_OK;
+        const size_t need = arena_bytes(want);
+        if (need > ar->size - ar->used)
+            return fail(T3_ENOMEM, "scratch: " + std::to_string(need) + " more bytes needed, " +
+                                       std::to_string(ar->size - ar->used) + " of " + std::to_string(ar->size) +
+                                       " left");
+        if (!carved) ar->saved.emplace_back(this, *this);
+        ptr = ar->base + ar->used;
+        bytes = need;
+        ar->used += need;
+        return T3_OK;
+    }
     if (want <= bytes && ptr) return T3_OK;
     const size_t b = want < 256 ? 256 : want;
     Budget *bg = g_budget;
@@ -58,6 +89,11 @@ int DevBuf::reserve(size_t want)
 
 void DevBuf::release()
 {
+    if (in_arena(g_arena, ptr)) {  // carved, not allocated
+        ptr = nullptr;
+        bytes = 0;
+        return;
+    }
     if (ptr) {
         (void)hipFree(ptr);
         if (g_budget) g_budget->used -= (int64_t)bytes;
@@ -329,6 +365,50 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
     return T3_OK;
 }
 
+// Scratch of the no-allocation forward pass: one static array per GPU the
+// library runs on, held until the process ends.  Host code never passes the
+// array's name to a kernel (in host code it is a stand-in, not a device
+// address): its device address is looked up once per device with that
+// device current and kept.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[256] = {};
+
+static int scratch_of_current_device(void **out)
+{
+    int dev = 0;
+    T3_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 256) return fail(T3_EHIP, "scratch: device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(T3_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return T3_OK;
+}
+
+// Arena bytes a non-tomographic forward pass over n galaxies and n_c centres
+// reserves with chunk layout L (the reservations of forward_impl in order:
+// error flag and pair counter, destination tables, cell list, centre set,
+// lane-bin counter, chunk planes, stage-2 partial sums, work counter).
+static size_t noalloc_bytes(const t3_plan *plan, int64_t n, int64_t n_c, const CellGrid &g, const ChunkLayout &L)
+{
+    const size_t m = (size_t)(n_c > 0 ? n_c : 1);
+    return arena_bytes(sizeof(int) * 4) + arena_bytes(sizeof(unsigned long long) * 4) +
+           arena_bytes(sizeof(short) * scan_dest_entries(plan)) + cells_arena_bytes(n, g) +
+           arena_bytes(sizeof(int2) * m) + arena_bytes(sizeof(float4) * m) + arena_bytes(sizeof(unsigned) * 4) +
+           arena_bytes(sizeof(float) * L.floats()) + contract_arena_bytes(plan, L, 1) +
+           arena_bytes(sizeof(unsigned) * 4);
+}
+
 }  // namespace t3
 
 using namespace t3;
@@ -474,6 +554,72 @@ int t3_forward(t3_plan *plan, const t3_catalog *cat, const int32_t *centres, int
         return forward_impl(plan, cat, 1, cl, nl, ups_out, n_pairs, (hipStream_t)stream);
     } catch (...) {
         return fail(T3_EINVAL, "t3_forward: exception");
+    }
+}
+
+int t3_forward_noalloc(t3_plan *plan, const t3_catalog *cat, const int32_t *centres, int64_t n_centres,
+                       double *ups_out, int64_t *n_pairs, void *stream)
+{
+    try {
+        if (!plan || !ups_out) return fail(T3_EINVAL, "t3_forward_noalloc: null argument");
+        T3_TRY(check_catalog(cat, "t3_forward_noalloc"));
+        if (n_centres < 0 && centres)
+            return fail(T3_EINVAL, "t3_forward_noalloc: n_centres < 0 (all galaxies) needs centres == NULL");
+        if (n_centres > 0 && !centres) return fail(T3_EINVAL, "t3_forward_noalloc: null centre list");
+        if (n_centres > (int64_t)0x7fffffff) return fail(T3_EINVAL, "t3_forward_noalloc: bad centre count");
+        void *base = nullptr;
+        T3_TRY(scratch_of_current_device(&base));
+        // the largest chunk capacity (a multiple of 256 centres, at most the
+        // automatic one) whose buffers fit the scratch, decided before any launch
+        const int64_t n_c = n_centres < 0 ? cat->n : n_centres;
+        const CellGrid g = choose_grid(plan, cat->n);
+        ChunkLayout L;
+        L.n_max = plan->n_max;
+        L.w_max = plan->w_max;
+        L.B = plan->B;
+        const int keep_req = plan->chunk_req;
+        plan->chunk_req = 0;
+        int K = choose_chunk(plan, L);
+        plan->chunk_req = keep_req;
+        K = (int)std::min<int64_t>(K, std::max<int64_t>(256, (n_c + 255) & ~(int64_t)255));
+        size_t need = 0;
+        for (; K >= 256; K -= 256) {
+            L.K = K;
+            need = noalloc_bytes(plan, cat->n, n_c, g, L);
+            if (need <= kScratchBytes) break;
+        }
+        if (K < 256)
+            return fail(T3_ENOMEM, "t3_forward_noalloc: " + std::to_string(cat->n) + " galaxies and " +
+                                       std::to_string(n_c) + " centres need " + std::to_string(need) +
+                                       " bytes of scratch even in chunks of 256 centres, more than the " +
+                                       std::to_string(kScratchBytes) + " the library holds (use t3_forward)");
+        // t3_forward's path, every buffer carved from the scratch: eager
+        // launches (no graph capture, no timing events), the destination
+        // tables rebuilt in the scratch; the plan's own state is restored
+        const uint32_t keep_flags = plan->flags;
+        const int keep_var = plan->scan_var;
+        size_t keep_off[4];
+        for (int k = 0; k < 4; ++k) keep_off[k] = plan->scan_dest_off[k];
+        plan->chunk_req = K;
+        plan->flags = (keep_flags | T3_FLAG_NO_GRAPH) & ~(T3_FLAG_TIMING | T3_FLAG_KEEP_PLANES);
+        plan->scan_var = -1;
+        Arena arena;
+        arena.base = static_cast<char *>(base);
+        arena.size = kScratchBytes;
+        int rc;
+        {
+            ArenaScope scope(&arena);
+            const int32_t *cl[1] = {centres};
+            const int64_t nl[1] = {n_centres};
+            rc = forward_impl(plan, cat, 1, cl, nl, ups_out, n_pairs, (hipStream_t)stream);
+        }
+        plan->chunk_req = keep_req;
+        plan->flags = keep_flags;
+        plan->scan_var = keep_var;
+        for (int k = 0; k < 4; ++k) plan->scan_dest_off[k] = keep_off[k];
+        return rc;
+    } catch (...) {
+        return fail(T3_EINVAL, "t3_forward_noalloc: exception");
     }
 }
 

@@ -179,6 +179,17 @@ int exclusive_scan(int *data, int64_t n, DevBuf &tmp, hipStream_t s)
     return T3_OK;
 }
 
+size_t cells_arena_bytes(int64_t n, const CellGrid &g)
+{
+    const int64_t nc = g.ncells();
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    const int64_t nb = (nc + 1 + kScanBlock - 1) / kScanBlock;
+    return 2 * arena_bytes(sizeof(int) * (size_t)(nc + 1))                       // cell starts, counts
+           + arena_bytes(sizeof(int2) * m) + arena_bytes(sizeof(float4) * m)      // sorted positions, factors
+           + 2 * arena_bytes(sizeof(int) * m)                                     // permutation, keys
+           + arena_bytes(sizeof(int) * (size_t)(nb + 1));                         // block sums of the scan
+}
+
 CellGrid choose_grid(const t3_plan *plan, int64_t n_gal)
 {
     CellGrid g;

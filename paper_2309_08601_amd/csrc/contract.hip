@@ -935,6 +935,18 @@ int contract_slice(const ChunkLayout &L, int n_z)
     return best;
 }
 
+size_t contract_arena_bytes(const t3_plan *plan, const ChunkLayout &L, int n_z)
+{
+    const int pairs = n_z * n_z;
+    const int S = (L.K + contract_slice(L, n_z) - 1) / contract_slice(L, n_z);
+    const size_t per = (size_t)L.out_blocks() * L.B * L.B;
+    size_t b = arena_bytes(sizeof(double) * 2 * per * (size_t)S * pairs) +
+               arena_bytes(sizeof(double) * 2 * 5 * (size_t)L.B * n_z * kDiagSplit);
+    if (plan->precision == T3_PREC_FP16X3)
+        b += arena_bytes(2 * sizeof(float) * (size_t)kNYArr * kScaleRows * (L.n_max + 1) * pairs);
+    return b;
+}
+
 int reserve_contract(t3_plan *plan, const ChunkLayout &L, int n_z)
 {
     const int pairs = n_z * n_z;

@@ -772,7 +772,9 @@ std::vector<short> dest_table_seg(int S, int cap, const ChunkLayout &L)
 
 }  // namespace
 
-int scan_prepare(t3_plan *plan)
+namespace {
+// Every destination table of the plan's stage-1 variant, and their offsets.
+int dest_tables(const t3_plan *plan, std::vector<short> &all, size_t off[4], int *var_index)
 {
     const auto &vars = variants();
     int vi = -1;
@@ -786,25 +788,44 @@ int scan_prepare(t3_plan *plan)
     L.n_max = plan->n_max;
     L.w_max = plan->w_max;
     L.B = plan->B;
-    std::vector<short> all;
+    all.clear();
     for (int p = 0; p < vars[vi].npass; ++p) {
-        plan->scan_dest_off[p] = all.size();
+        off[p] = all.size();
         auto d = dest_table(vars[vi].pass[p], L);
         all.insert(all.end(), d.begin(), d.end());
     }
-    if (plan->w_max > vars[vi].cap) {  // W orders beyond the main passes
-        plan->scan_dest_off[vars[vi].npass] = all.size();
+    if (plan->w_max > vars[vi].cap) {
+        off[vars[vi].npass] = all.size();
         auto d = dest_table(vars[vi].wext, L);
         all.insert(all.end(), d.begin(), d.end());
     }
-    if (vars[vi].seg > 0) {  // one sweep with two order segments per wavefront
-        plan->scan_dest_off[3] = all.size();
+    if (vars[vi].seg > 0) {
+        off[3] = all.size();
         auto d = dest_table_seg(vars[vi].seg, vars[vi].cap, L);
         all.insert(all.end(), d.begin(), d.end());
     }
+    *var_index = vi;
+    return T3_OK;
+}
+}  // namespace
+
+size_t scan_dest_entries(const t3_plan *plan)
+{
+    std::vector<short> all;
+    size_t off[4] = {0, 0, 0, 0};
+    int vi = -1;
+    return dest_tables(plan, all, off, &vi) == T3_OK ? all.size() : 0;
+}
+
+int scan_prepare(t3_plan *plan)
+{
+    std::vector<short> all;
+    size_t off[4] = {0, 0, 0, 0};
+    int vi = -1;
+    T3_TRY(dest_tables(plan, all, off, &vi));
+    for (int k = 0; k < 4; ++k) plan->scan_dest_off[k] = off[k];
     T3_TRY(plan->dest.reserve(all.size() * sizeof(short)));
-    T3_HIP_CHECK(hipMemcpy(plan->dest.ptr, all.data(), all.size() * sizeof(short),
-                           hipMemcpyHostToDevice));
+    T3_HIP_CHECK(hipMemcpy(plan->dest.ptr, all.data(), all.size() * sizeof(short), hipMemcpyHostToDevice));
     plan->scan_var = vi;
     return T3_OK;
 }

@@ -54,6 +54,26 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
 
+// Device memory the no-allocation entry point carves its buffers from
+// (bump allocation, 256-byte aligned, nothing freed).  While an ArenaScope
+// is active on a thread, DevBuf::reserve carves from the arena instead of
+// allocating, remembering each buffer's previous state, and the scope's end
+// gives every such buffer back its previous (plan-owned) state.
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0, used = 0;
+    std::vector<std::pair<DevBuf *, DevBuf>> saved;
+};
+struct ArenaScope {
+    Arena *prev;
+    Arena *mine;
+    explicit ArenaScope(Arena *a);
+    ~ArenaScope();
+};
+// Bytes one carve of `want` bytes takes from an arena (256-byte granules,
+// at least one, as DevBuf::reserve allocates).
+inline size_t arena_bytes(size_t want) { return ((want < 256 ? 256 : want) + 255) & ~(size_t)255; }
+
 // ---------------------------------------------------------------- chunk layout
 // Stage-1 output for a chunk of K centres (K a multiple of 4): "planes" of
 // FP32 values, one plane per (order, real/imag part) or per j = k sum.
@@ -260,6 +280,12 @@ int forward_grid(t3_plan *plan, const t3_catalog &cat, int64_t delta, const int3
 int level_bbox(GridLevel &lv, const int32_t *px, const int32_t *py, const double *sum, hipStream_t s);
 double fft_cost_ms(const t3_plan *plan, const GridLevel &lv);
 int fft_level(t3_plan *plan, GridLevel &lv, hipStream_t s);
+// Arena bytes of the buffers a forward pass reserves (no-allocation entry
+// point): the cell list of n galaxies on grid g (with its scan scratch), the
+// stage-1 destination tables, and the stage-2 partial sums of one chunk.
+size_t cells_arena_bytes(int64_t n, const CellGrid &g);
+size_t scan_dest_entries(const t3_plan *plan);
+size_t contract_arena_bytes(const t3_plan *plan, const ChunkLayout &L, int n_z);
 int harmonics_export(t3_plan *plan, const CentreSet &cs, const ChunkLayout &L, const float *planes,
                      int64_t c0, int n_c, float *G, float *W, float *D, hipStream_t s);
 int normalise_backward(t3_plan *plan, const double *ups, const double *ggam, int n_sets, double *gups,

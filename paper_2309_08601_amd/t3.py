@@ -66,7 +66,7 @@ class T3Error(RuntimeError):
 
 EXPORTED = ["t3_plan_create", "t3_plan_destroy", "t3_forward", "t3_forward_tomo", "t3_harmonics",
             "t3_normalise_resum", "t3_normalise_backward", "t3_backward", "t3_autotune", "t3_stage_times",
-            "t3_workspace_bytes", "t3_graph_stats", "t3_error_string",
+            "t3_workspace_bytes", "t3_graph_stats", "t3_forward_noalloc", "t3_error_string",
             "t3_last_error_message", "t3_version"]
 
 
@@ -82,6 +82,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.t3_plan_destroy.restype = None
     lib.t3_forward.argtypes = [vp, P(t3_catalog), vp, ctypes.c_int64, vp, P(ctypes.c_int64), vp]
     lib.t3_forward.restype = ctypes.c_int
+    lib.t3_forward_noalloc.argtypes = [vp, P(t3_catalog), vp, ctypes.c_int64, vp, P(ctypes.c_int64), vp]
+    lib.t3_forward_noalloc.restype = ctypes.c_int
     lib.t3_forward_tomo.argtypes = [vp, P(t3_catalog), ctypes.c_int32, P(vp), P(ctypes.c_int64), vp,
                                     P(ctypes.c_int64), vp]
     lib.t3_forward_tomo.restype = ctypes.c_int
@@ -243,6 +245,22 @@ class Plan:
         _check(_lib.t3_forward(self._h, ctypes.byref(cs), _ptr(centres),
                                -1 if centres is None else int(centres.numel()), _ptr(out),
                                ctypes.byref(npairs), _stream()))
+        return torch.view_as_complex(out), int(npairs.value)
+
+    def forward_noalloc(self, cat: DeviceCatalog, centres: Optional[torch.Tensor] = None,
+                        out: Optional[torch.Tensor] = None):
+        """forward() with every internal buffer in the library's static device
+        scratch (nothing allocated by the library; `out` may be preallocated
+        by the caller)."""
+        if out is None:
+            out = torch.empty(self._out_shape()[1:], dtype=torch.float64, device=cat.x.device)
+        cs = cat.c_struct()
+        npairs = ctypes.c_int64(0)
+        if centres is not None:
+            centres = centres.to(torch.int32).contiguous()
+        _check(_lib.t3_forward_noalloc(self._h, ctypes.byref(cs), _ptr(centres),
+                                       -1 if centres is None else int(centres.numel()), _ptr(out),
+                                       ctypes.byref(npairs), _stream()))
         return torch.view_as_complex(out), int(npairs.value)
 
     def forward_tomo(self, cats: List[DeviceCatalog], centres: Optional[List[Optional[torch.Tensor]]] = None,
