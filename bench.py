@@ -43,11 +43,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic(launches_per_step):
-    """HBM bytes per stage-1 launch from the committed counter summary, or
+def profiled_traffic(launches_per_step, summary="k_scan_field_1m.md"):
+    """HBM bytes per stage-1 launch from a committed counter summary, or
     None when the kernel sources or the launch shape (launches per step)
     changed since those counters were taken."""
-    path = os.path.join(ROOT, "profiles", "k_scan_field_1m.md")
+    path = os.path.join(ROOT, "profiles", summary)
     try:
         text = open(path).read()
     except OSError:
@@ -419,7 +419,8 @@ def bench_field_4m(t3, torch, dev, steps, with_oracle=True):
                      "gemm_tflops": gemm_flops / (st[2] / 1e3) / 1e12,
                      "stage1_roofline": {"bound": "alu", "achieved": flops_pair * pairs / s1 / 1e12, "peak": 157.3,
                                          "unit": "TFLOP/s", "frac": flops_pair * pairs / s1 / 157.3e12,
-                                         "launches_per_step": int(nl[1] // steps)}}
+                                         "traffic": profiled_traffic(int(nl[1] // steps), "k_scan_field_4m.md"),
+                                         "flops_per_pair": flops_pair, "launches_per_step": int(nl[1] // steps)}}
         log(f"[bench] field_4m {prec}: {1e3 * ts:.0f} ms/step, {pairs / ts:.3e} pairs/s, stage 1 {st[1]:.0f} ms "
             f"(frac {res[prec]['stage1_roofline']['frac']:.3f}), stage 2 {st[2]:.1f} ms "
             f"({res[prec]['gemm_tflops']:.1f} TFLOP/s)")
