@@ -123,7 +123,6 @@ __device__ __forceinline__ int sweep_core(const SweepArgs &a, int2 cp, double e2
                                           const SweepLDS &L, Consume &&consume, int row_off, int row_step)
 {
     const CellGrid &g = a.g;
-    const unsigned long long lt_mask = (1ull << lane) - 1ull;
     const long long R = (long long)sqrt(e2hi) + 1;
     long long row_lo = floor_div((long long)cp.y - R - g.oy, g.cell);
     long long row_hi = floor_div((long long)cp.y + R - g.oy, g.cell);
@@ -151,34 +150,28 @@ __device__ __forceinline__ int sweep_core(const SweepArgs &a, int2 cp, double e2
         wave_sync_lds();
         if (total == 0) continue;
 
-        // ---- walk the virtual list, prefetching one step ahead
+        // ---- walk the virtual list, prefetching one step ahead (a lane past
+        // the end loads the list's last candidate again and is masked off)
         int t = 0;
         int v = lane;
         bool valid = v < total;
-        int gi = valid ? locate(L.span, t, v) : 0;
-        int2 p = make_int2(cp.x, cp.y);
-        float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (valid) {
-            p = a.npos[gi];
-            c = a.ncw[gi];
-        }
+        int gi = locate(L.span, t, valid ? v : total - 1);
+        int2 p = a.npos[gi];
+        float4 c = a.ncw[gi];
         for (int v0 = 0; v0 < total; v0 += 64) {
             const int vn = v0 + 64 + lane;
             const bool valid_n = vn < total;
-            int gn = 0;
-            int2 pn = make_int2(cp.x, cp.y);
-            float4 cn = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (valid_n) {
-                gn = locate(L.span, t, vn);
-                pn = a.npos[gn];
-                cn = a.ncw[gn];
-            }
+            const int gn = locate(L.span, t, valid_n ? vn : total - 1);
+            const int2 pn = a.npos[gn];
+            const float4 cn = a.ncw[gn];
             const int dx = p.x - cp.x, dy = p.y - cp.y;
             const double r2 = fma((double)dx, (double)dx, (double)dy * (double)dy);
             const bool in = valid && r2 >= e2lo && r2 < e2hi;
             const unsigned long long m = __ballot(in);
             if (in) {
-                const int slot = (tail + __popcll(m & lt_mask)) & (kRing - 1);
+                const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                const int slot = (tail + below) & (kRing - 1);
                 L.q_xyc[slot] = make_int4(dx, dy, __float_as_int(c.x), __float_as_int(c.y));
                 L.q_wi[slot] = make_int2(__float_as_int(c.z), gi);
             }
