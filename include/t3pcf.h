@@ -76,7 +76,9 @@ extern "C" {
 /* (the FP32 error model) in every precision.                            */
 #define T3_PREC_FP32 0    /* FP32 MFMA products, FP32 runs promoted to FP64 */
 #define T3_PREC_BF16X3 1  /* x = hi + lo in bf16; hi*hi + hi*lo + lo*hi for  */
-                          /* Upsilon_0..3, FP32 for the normaliser N_n      */
+                          /* Upsilon_0..3 (for B <= 24 also lo*lo, which    */
+                          /* there shares an MFMA with hi*lo), FP32 for the */
+                          /* normaliser N_n                                 */
 #define T3_PREC_FP16X3 2  /* same in fp16 with power-of-two row scaling     */
 #define T3_PREC_BF16X6 3  /* x = hi + mid + lo in bf16 (all 24 FP32 bits);  */
                           /* the six part products of order <= 2; FP32 N_n  */

@@ -10,10 +10,11 @@
 //     mu = 4: X =  w  W_n,            Y = conj W_n       (normaliser N_n)
 // A complex product is four real MFMAs: Re += Xr Yr - Xi Yi, Im += Xr Yi + Xi Yr.
 //
-// Work decomposition: a workgroup of four wavefronts owns one n (the four
-// shear components, one wavefront each) or four orders of N, one slice of
-// centres and one 32 x 32 tile of the B x B block (grid.y; one tile for
-// B <= 40, four for B = 41..64).  For B = 33..40 only the first tile runs on
+// Work decomposition (B > 24; blocks of at most 24 bins take the real-
+// embedded 16 x 16 kernel k_contract_small below): a workgroup of four
+// wavefronts owns one n (the four shear components, one wavefront each) or
+// two orders of N, one slice of centres and one 32 x 32 tile of the B x B
+// block (grid.y; one tile for B <= 40, four for B = 41..64).  For B = 33..40 only the first tile runs on
 // MFMA: the outputs with a bin index of 32 or more (at most 8 rows and
 // columns) are summed by k_contract_edge on the vector ALUs (FP32 runs of
 // 16 centres promoted to FP64, as the FP32 MFMA runs), rather
@@ -35,7 +36,8 @@
 // Precision variants of the Upsilon products (N_n is always FP32):
 //  * FP32:    v_mfma_f32_32x32x2_f32.
 //  * BF16X3:  x = hi + lo, hi = bf16(x), lo = bf16(x - hi) (about 16 bits);
-//             hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16.
+//             hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16 (B > 24;
+//             the 16 x 16 kernel of B <= 24 adds lo*lo at no cost).
 //  * BF16X6:  x = hi + mid + lo (every FP32 bit); the six products whose
 //             part orders sum to at most 2 (dropped terms are below
 //             2^-24 |x y|).
@@ -43,6 +45,8 @@
 //             row (array, bin) by a power of two that brings its largest
 //             entry into [2^11, 2^12), keeping lo out of the subnormals; the
 //             scales are divided out in FP64.
+#include <type_traits>
+
 #include "t3_internal.h"
 
 namespace t3 {
@@ -525,6 +529,466 @@ __global__ __launch_bounds__(256, 2) void k_contract(ContractArgs a)
     }
 }
 
+// ------------------------------------------------------------ B <= 24
+// A block of at most 24 bins fills a 32 x 32 complex tile to at most 56%
+// (39% at B = 20).  For such blocks the complex product is embedded in one
+// real product of 2B x 2B: operand row 2b + p holds part p (0 real,
+// 1 imaginary) of bin b, so that the real product of X (2B x K) with
+// Y^T (K x 2B) holds every X_p Y_q, and at each promotion of an FP32 run
+//     Re X Y  = Xr Yr - Xi Yi,   Im X Y  = Xr Yi + Xi Yr,
+//     Re X Y* = Xr Yr + Xi Yi,   Im X Y* = Xi Yr - Xr Yi.
+// The 2B rows take T = ceil(2B / 16) tiles of 16 x 16 per side, T^2 tiles
+// per wavefront (69% of the issued products useful at B = 20, 100% at
+// B = 16).  With the parts interleaved, the four real products of one
+// (b1, b2) sit in two neighbouring lanes: one DPP-fused FMA per lane forms
+// its real (even lane) or imaginary (odd lane) part.
+//
+// A workgroup of eight wavefronts splits the work by role: wavefronts 0-3
+// only multiply, wavefronts 4-7 only load and form operands.  Each step of
+// STEP centres is formed into one of two LDS buffers while the multiplying
+// wavefronts read the other (one barrier per step), so every SIMD holds a
+// multiplying and a staging wavefront of each of two workgroups: the FP32
+// MFMAs do not co-issue with vector instructions on this hardware, and the
+// staging arithmetic then fills the issue slots the matrix core leaves.
+//  NK = false: the four products are mu 0..3 of one order n (operand arrays
+//    X0..X2 from the Z2 planes, Y3..Y5 from the Z3 planes, as in k_contract).
+//  NK = true (FP32): N_n of one order n (X = w W_n, Y = W_n); the four
+//    multiplying wavefronts take the four blocks of each step of 4 kBlk
+//    centres and add their FP64 sums in a fixed order at the end (the grid
+//    then matches the Upsilon kernel's).
+// Staging: item (array, centre quad, bin) is one thread's pair of float4
+// loads (real and imaginary planes: four centres of one bin, coalesced over
+// the bins); a thread keeps the same items for the whole slice.  The centre
+// factors of a step reach LDS one step before its operands are formed, in
+// the three sign forms the X operands take.
+// Products:
+//  * FP32: v_mfma_f32_16x16x4_f32; lane group g (lane / 16) takes centre
+//    4 g + s of the block in step s.
+//  * splits: v_mfma_f32_16x16x32_{bf16,f16}, whose 32-deep K holds the 16
+//    centres of a block twice, for two part products at once: lane groups
+//    0-1 carry the centres in part p, groups 2-3 in part p'.  Two-part
+//    splits (BF16X3, FP16X3): [X0|X1].[Y0|Y0] + [X0|X1].[Y1|Y1], all four
+//    part products: lo*lo shares its MFMA with hi*lo, so it costs nothing
+//    here (the 32 x 32 kernel drops it).  BF16X6 (the six products with part
+//    orders summing to at most 2): [X0|X1].[Y0|Y0] + [X0|X1].[Y1|Y1] +
+//    [X0|X2].[Y2|Y0].  FP16X3 rows carry the power-of-two scales of
+//    k_fp16_scale, divided out in FP64.
+constexpr int kSmallBins = 24;
+
+template <int PK>
+constexpr int small_row_elems()  // LDS elements per operand row: the parts of kBlk centres + 16 bytes
+{
+    return PK == T3_PREC_FP32 ? kBlk + 4 : Fmt<PK>::parts * kBlk + 8;
+}
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Waves per SIMD: 4 (two workgroups per CU, at most 128 registers) where the
+// registers fit without spilling, 2 for the N_n kernel and two staging items
+// per thread.
+template <int PK, int T, bool NK, int NIS>
+__global__ __launch_bounds__(512, (NK || NIS > 1) ? 2 : 4) void k_contract_small(ContractArgs a)
+{
+    using E = typename Fmt<PK>::T;            // LDS element
+    constexpr int P = Fmt<PK>::parts;
+    constexpr int RS = small_row_elems<PK>();
+    constexpr int R = 16 * T;                  // real rows per operand array
+    constexpr int NA = NK ? 8 : 6;             // complex operand arrays
+    constexpr int NH = NA / 2;                 // per side
+    constexpr int ARR = R * RS;                // elements per array
+    constexpr int BUF = NA * ARR;              // elements per buffer
+    constexpr int NB = NK ? 4 : 1;             // blocks of kBlk centres per step
+    constexpr int STEP = NB * kBlk;            // centres per step
+    constexpr int NV = NK ? 1 : 3;             // factor forms per centre
+    static_assert(!NK || PK == T3_PREC_FP32, "N_n is computed in FP32");
+    static_assert(!NK || 3 * T * T * 2 * 64 * sizeof(double) <= 2 * BUF * sizeof(E), "N_n sums fit the LDS");
+    // two operand buffers, then a dummy row pair that the stores of unused
+    // staging slots go to (the staging has no branches: see below)
+    __shared__ __attribute__((aligned(16))) E lds[2 * BUF + 2 * RS];
+    __shared__ float4 cwl[2][NV][STEP + 16];  // factor forms of a step's centres + dummy slots
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool producer = wave >= 4;
+    // slice / order / pair mapping as in k_contract (XCD-major)
+    const int ngrp = (NK ? a.w_max : a.n_max) + 1;  // orders
+    const int pairs = a.n_z * a.n_z;
+    const int xcd = blockIdx.x & 7;
+    int jx = blockIdx.x >> 3;
+    const int pair = jx % pairs;
+    jx /= pairs;
+    const int n = jx % ngrp;
+    const int sl = 8 * (jx / ngrp) + xcd;
+    if (sl >= a.S) return;
+    const float *px, *py;
+    pair_planes(a, pair, px, py);
+    const int i_begin = sl * a.slice;
+    const int i_end = min(i_begin + a.slice, a.n_c);
+    const int i_last = i_end - 1, q_last = i_last >> 2;
+    const int nsteps = (i_end - i_begin + STEP - 1) / STEP;
+    const int nm = a.n_max, B = a.B;
+    const float *scl = nullptr;  // fp16 row scales of order n: [array][kScaleRows]
+    if constexpr (PK == T3_PREC_FP16X3) scl = a.scale + ((size_t)pair * (nm + 1) + n) * kNYArr * kScaleRows;
+
+    // padding rows 2B..R-1 of every array stay zero
+    {
+        const int per = (R - 2 * B) * RS;
+        for (int e = tid; e < 2 * NA * per; e += 512) lds[(e / per) * ARR + 2 * B * RS + e % per] = E(0.0f);
+    }
+
+    if (producer) {
+        // ---------------------------------------------------------- staging
+        // Item (array k, centre quad q, bin b) of a side: k = it / 4B,
+        // q = (it mod 4B) / B, b = it mod B; producer thread p takes items
+        // p + 256 u of each side.  Items past the last load the last one
+        // again and store into the dummy row pair, so that the staging has
+        // no branches and the loads of a step are waited for once, when its
+        // operands are formed, while the next step's loads stay in flight.
+        const int ptid = tid - 256;
+        const int nis = NH * 4 * B;  // items per side (NIS = ceil(nis / 256) per thread, set at launch)
+        const unsigned KB = (unsigned)a.K * (unsigned)B;  // floats per plane
+        const unsigned qstride = 4u * (unsigned)B;        // floats from one centre quad to the next
+        unsigned g0[2][NIS];  // float offset of (real plane, quad 0 of the chunk, bin)
+        int qq[2][NIS];       // centre quad of the item within a step
+        int lo[2][NIS];       // LDS element offset of (array, row 2 bin, centre 4 quad); >= 2 BUF: dummy
+        int kx[NIS];          // X side: the factor form of the item's array
+        float sc[2][NIS];     // fp16 row scales (1 otherwise)
+#pragma unroll
+        for (int side = 0; side < 2; ++side)
+#pragma unroll
+            for (int u = 0; u < NIS; ++u) {
+                const int it0 = ptid + 256 * u, it = min(it0, nis - 1);
+                const int k = it / (4 * B), qb = it % (4 * B);
+                const int q = qb / B, b = qb % B;
+                int pl, wb = 0;
+                if constexpr (NK) {
+                    pl = plane_w(n, nm);
+                    wb = k;  // the block of the step whose operands array k holds
+                } else {
+                    const int m = side == 0 ? (k == 0 ? n - 3 : k == 1 ? n - 1 : -n - 1)
+                                            : (k == 0 ? -n - 3 : k == 1 ? -n - 1 : n - 1);
+                    pl = plane_g(m, nm);
+                }
+                qq[side][u] = 4 * wb + q;
+                g0[side][u] = (unsigned)chunk_offset(pl, 0, b, a.K, B);
+                lo[side][u] = it0 < nis ? (side * NH + k) * ARR + 2 * b * RS + 4 * q : 2 * BUF + 4 * (ptid & 3);
+                sc[side][u] = 1.0f;
+                if constexpr (PK == T3_PREC_FP16X3) sc[side][u] = scl[(side * NH + k) * kScaleRows + b];
+                if (side == 0) kx[u] = NK ? 0 : k;
+            }
+
+        struct Stage {
+            float4 re[2][NIS], im[2][NIS];
+            float4 cw;  // centre factors of centre ptid mod STEP of the step
+        };
+        auto load_step = [&](Stage &st, int step) {
+            const int i0 = i_begin + step * STEP;
+            st.cw = a.ccw[min(i0 + (ptid & (STEP - 1)), i_last)];
+            // quads past the slice's last read its last quad (masked when formed)
+            const int qrel = q_last - (i0 >> 2);                  // last valid quad relative to the step
+            const unsigned sbase = (unsigned)(i0 >> 2) * qstride;  // the step's first quad
+            const unsigned slast = (unsigned)q_last * qstride;
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const float *sp = side ? py : px;
+#pragma unroll
+                for (int u = 0; u < NIS; ++u) {
+                    const unsigned o =
+                        g0[side][u] + (qq[side][u] <= qrel ? sbase + (unsigned)qq[side][u] * qstride : slast);
+                    st.re[side][u] = *reinterpret_cast<const float4 *>(sp + o);
+                    st.im[side][u] = *reinterpret_cast<const float4 *>(sp + o + KB);
+                }
+            }
+        };
+        // The factor forms (p, q, r, t) of a centre, Re = p gr + q gi and
+        // Im = r gi + t gr for the X operand of g = gr + i gi:
+        //     -c g: (-cr, ci, -cr, -ci),   -c* g: (-cr, -ci, -cr, ci),
+        //     -c conj g: (-cr, -ci, cr, -ci);   N_n: w g as (w, 0, w, 0).
+        // Written by the first producer wavefront (lanes past STEP write
+        // dummy slots).
+        auto put_cw = [&](int buf, float4 cw) {
+            if (wave != 4) return;
+            const int j = ptid < STEP ? ptid : STEP + (ptid & 15);
+            if constexpr (NK) {
+                cwl[buf][0][j] = make_float4(cw.z, 0.f, cw.z, 0.f);
+            } else {
+                const float cr = cw.x, ci = cw.y;
+                cwl[buf][0][j] = make_float4(-cr, ci, -cr, -ci);
+                cwl[buf][1][j] = make_float4(-cr, -ci, -cr, ci);
+                cwl[buf][2][j] = make_float4(-cr, -ci, cr, -ci);
+            }
+        };
+        // one real row of four centres: FP32 as is, splits part p at p kBlk
+        auto put_row = [&](E *row, float4 v) {
+            if constexpr (PK == T3_PREC_FP32) {
+                *reinterpret_cast<float4 *>(row) = v;
+            } else {
+                uint32_t l[P], h[P];
+                split2<PK>(v.x, v.y, l);
+                split2<PK>(v.z, v.w, h);
+#pragma unroll
+                for (int p = 0; p < P; ++p) *reinterpret_cast<uint2 *>(row + p * kBlk) = make_uint2(l[p], h[p]);
+            }
+        };
+        // operands of one step into LDS buffer buf; MASK: the slice's last,
+        // partial step, whose centres past the end are zero
+        auto stage_mask = [&](Stage &st, int buf, int step, auto mask) {
+            const int i0 = i_begin + step * STEP;
+            const int boff = buf * BUF;
+#pragma unroll
+            for (int side = 0; side < 2; ++side)
+#pragma unroll
+                for (int u = 0; u < NIS; ++u) {
+                    const int q = qq[side][u];
+                    float4 vr = st.re[side][u], vi = st.im[side][u];
+                    if constexpr (decltype(mask)::value) {
+                        const int nv = max(0, min(4, i_end - (i0 + 4 * q)));
+                        vr = keep(vr, nv);
+                        vi = keep(vi, nv);
+                    }
+                    if (side == 0) {
+                        float r[4], m[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const float4 f = cwl[buf][kx[u]][4 * q + e];
+                            const float gr = comp(vr, e), gi = comp(vi, e);
+                            if constexpr (NK) {  // w W_n
+                                r[e] = f.x * gr;
+                                m[e] = f.x * gi;
+                            } else {
+                                r[e] = fmaf(f.x, gr, f.y * gi);
+                                m[e] = fmaf(f.z, gi, f.w * gr);
+                            }
+                        }
+                        vr = make_float4(r[0], r[1], r[2], r[3]);
+                        vi = make_float4(m[0], m[1], m[2], m[3]);
+                    }
+                    if constexpr (PK == T3_PREC_FP16X3) {
+                        const float s = sc[side][u];
+                        vr = make_float4(vr.x * s, vr.y * s, vr.z * s, vr.w * s);
+                        vi = make_float4(vi.x * s, vi.y * s, vi.z * s, vi.w * s);
+                    }
+                    const int o = lo[side][u] + (lo[side][u] < 2 * BUF ? boff : 0);
+                    put_row(lds + o, vr);
+                    put_row(lds + o + RS, vi);
+                }
+        };
+        auto stage = [&](Stage &st, int buf, int step) {  // one wave-uniform branch
+            if (i_begin + (step + 1) * STEP <= i_end)
+                stage_mask(st, buf, step, std::false_type{});
+            else
+                stage_mask(st, buf, step, std::true_type{});
+        };
+
+        // Step k goes to buffer k mod 2 before barrier k, its factor forms
+        // to cwl[k mod 2] before barrier k - 1; step k + 1 is formed while
+        // the multiplying wavefronts read step k.  The loads run NS steps
+        // ahead (NS register stages).
+        constexpr int NS = 2;
+        Stage st[NS];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) load_step(st[j], j);
+        put_cw(0, st[0].cw);
+        __syncthreads();  // factor forms of step 0
+        stage(st[0], 0, 0);
+        load_step(st[0], NS);
+        put_cw(1, st[1].cw);
+        for (int k = 0;; k += NS) {
+            bool done = false;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                if (!done) {
+                    __syncthreads();  // barrier k + j
+                    if (k + j + 1 >= nsteps) {
+                        done = true;
+                    } else {
+                        stage(st[(j + 1) % NS], (k + j + 1) & 1, k + j + 1);
+                        load_step(st[(j + 1) % NS], k + j + 1 + NS);
+                        put_cw((k + j) & 1, st[(j + 2) % NS].cw);  // step k + j + 2
+                    }
+                }
+            }
+            if (done) break;
+        }
+        if constexpr (NK) {  // the consumers' two barriers of the N_n reduction
+            __syncthreads();
+            __syncthreads();
+        }
+        return;
+    }
+
+    // ------------------------------------------------------------ products
+    // this wavefront's product X_ia (conj?) Y_ib; arrays 0 .. NH - 1 are the
+    // X side (Z2 planes), NH .. NA - 1 the Y side (Z3 planes)
+    int ia, ib;
+    bool cj;
+    if constexpr (NK) {
+        ia = wave;       // w W_n of block `wave` of the step
+        ib = NH + wave;  // W_n of the same block
+        cj = true;
+    } else {
+        ia = wave == 3 ? 0 : wave;
+        ib = NH + ((wave == 0 || wave == 2) ? 0 : (wave == 1 ? 1 : 2));
+        cj = wave == 3;
+    }
+    // D row 16 r + 4 (lane / 16) + j = 2 b1 + (j & 1), column 16 c + lane mod 16
+    // = 2 b2 + (lane & 1): lane pair (even, odd) holds the real and the
+    // imaginary column of bins b1 = 8 r + 2 (lane / 16) (j = 0, 1) and b1 + 1
+    // (j = 2, 3).  Per bin, with u = D[2 b1][.] and v = D[2 b1 + 1][.] of the
+    // lane and v' the partner's v (one DPP swap):
+    //     X Y:  even  u - v' = Xr Yr - Xi Yi,     odd  u + v' = Xr Yi + Xi Yr;
+    //     X Y*: even  u + v' = Xr Yr + Xi Yi,     odd -(u - v') = Xi Yr - Xr Yi:
+    // the even lane forms the real part, the odd lane the imaginary part.
+    const int g = lane >> 4, odd = lane & 1;
+    // t = u + s1 v' in FP32 (one DPP-fused FMA), then += s2 t in FP64:
+    // X Y: s1 = -1 / +1 (even / odd), s2 = 1; X Y*: s1 = +1 / -1, s2 = s1
+    const float s1 = (odd ? 1.0f : -1.0f) * (cj ? -1.0f : 1.0f);
+    const double s2 = cj ? (double)s1 : 1.0;
+    floatx4 acc[T][T];
+    double dacc[T][T][2];  // FP64 sums of bins b1 and b1 + 1, this lane's part
+#pragma unroll
+    for (int r = 0; r < T; ++r)
+#pragma unroll
+        for (int c = 0; c < T; ++c) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[r][c][j] = 0.f;
+            dacc[r][c][0] = dacc[r][c][1] = 0.0;
+        }
+    // FP32 runs of one block (kRun = kBlk centres): the four real products of
+    // (b1, b2) are combined into the complex product in FP32 (as the FP32 runs
+    // of the 32 x 32 kernel) and promoted into FP64.  The promotion of a run
+    // comes first in the next block, reading accumulators whose products have
+    // completed; the block's first products then start from zero.
+    auto swap1 = [](float v) {  // lane ^ 1 (DPP quad_perm 1, 0, 3, 2)
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xb1, 0xf, 0xf, true));
+    };
+    auto promote = [&]() {
+#pragma unroll
+        for (int r = 0; r < T; ++r)
+#pragma unroll
+            for (int c = 0; c < T; ++c) {
+                const floatx4 d = acc[r][c];
+                const float t0 = fmaf(swap1(d[1]), s1, d[0]);
+                const float t1 = fmaf(swap1(d[3]), s1, d[2]);
+                dacc[r][c][0] = fma((double)t0, s2, dacc[r][c][0]);
+                dacc[r][c][1] = fma((double)t1, s2, dacc[r][c][1]);
+            }
+    };
+    const floatx4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    auto mfma_block = [&](int buf) {
+        promote();
+        const E *base = lds + buf * BUF + (lane & 15) * RS;
+        if constexpr (PK == T3_PREC_FP32) {
+            // column tile by column tile (one Y fragment live), the T row
+            // tiles' chains interleaved
+            float4 xa[T];
+#pragma unroll
+            for (int t = 0; t < T; ++t) xa[t] = *reinterpret_cast<const float4 *>(base + ia * ARR + 16 * t * RS + 4 * g);
+#pragma unroll
+            for (int c = 0; c < T; ++c) {
+                const float4 yb = *reinterpret_cast<const float4 *>(base + ib * ARR + 16 * c * RS + 4 * g);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int r = 0; r < T; ++r)
+                        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(comp(xa[r], s), comp(yb, s),
+                                                                         s == 0 ? zero4 : acc[r][c], 0, 0, 0);
+            }
+        } else {
+            using V = typename Fmt<PK>::V;
+            auto mma = [&](const uint4 &x, const uint4 &y, floatx4 &c) {
+                if constexpr (PK == T3_PREC_FP16X3)
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(V, x), __builtin_bit_cast(V, y), c,
+                                                               0, 0, 0);
+                else
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(V, x), __builtin_bit_cast(V, y), c,
+                                                                0, 0, 0);
+            };
+            // fragment offsets within a row (elements): [X0|X1] 8 g, [Y0|Y0] 8 (g & 1),
+            // [Y1|Y1] 16 + 8 (g & 1), [X0|X2] 8 g + 16 (g >= 2), [Y2|Y0] 32 + 8 g (g < 2) or 8 (g - 2)
+            const int o01 = 8 * g, o00 = 8 * (g & 1), o11 = 16 + 8 * (g & 1);
+            uint4 x01[T], y00[T], y11[T];
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                x01[t] = *reinterpret_cast<const uint4 *>(base + ia * ARR + 16 * t * RS + o01);
+                y00[t] = *reinterpret_cast<const uint4 *>(base + ib * ARR + 16 * t * RS + o00);
+                y11[t] = *reinterpret_cast<const uint4 *>(base + ib * ARR + 16 * t * RS + o11);
+            }
+#pragma unroll
+            for (int r = 0; r < T; ++r)
+#pragma unroll
+                for (int c = 0; c < T; ++c) {
+                    acc[r][c] = zero4;
+                    mma(x01[r], y00[c], acc[r][c]);
+                }
+#pragma unroll
+            for (int r = 0; r < T; ++r)
+#pragma unroll
+                for (int c = 0; c < T; ++c) mma(x01[r], y11[c], acc[r][c]);
+            if constexpr (P == 3) {
+                const int o02 = 8 * g + (g >= 2 ? 16 : 0), o20 = g < 2 ? 32 + 8 * g : 8 * (g - 2);
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    x01[t] = *reinterpret_cast<const uint4 *>(base + ia * ARR + 16 * t * RS + o02);
+                    y00[t] = *reinterpret_cast<const uint4 *>(base + ib * ARR + 16 * t * RS + o20);
+                }
+#pragma unroll
+                for (int r = 0; r < T; ++r)
+#pragma unroll
+                    for (int c = 0; c < T; ++c) mma(x01[r], y00[c], acc[r][c]);
+            }
+        }
+    };
+
+    __syncthreads();  // factor forms of step 0
+    for (int k = 0; k < nsteps; ++k) {
+        __syncthreads();  // barrier k: step k in buffer k mod 2
+        mfma_block(k & 1);
+    }
+    promote();
+    if constexpr (NK) {
+        // the four blocks' sums, added in wavefront order
+        constexpr int ND = T * T * 2;
+        __syncthreads();  // every wavefront is done with the operands
+        double *red = reinterpret_cast<double *>(lds);
+        if (wave > 0) {
+#pragma unroll
+            for (int r = 0; r < T; ++r)
+#pragma unroll
+                for (int c = 0; c < T; ++c)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) red[((wave - 1) * ND + 2 * (r * T + c) + h) * 64 + lane] = dacc[r][c][h];
+        }
+        __syncthreads();
+        if (wave > 0) return;
+#pragma unroll
+        for (int w = 0; w < 3; ++w)
+#pragma unroll
+            for (int r = 0; r < T; ++r)
+#pragma unroll
+                for (int c = 0; c < T; ++c)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) dacc[r][c][h] += red[(w * ND + 2 * (r * T + c) + h) * 64 + lane];
+    }
+    const int nq = 4 * (nm + 1) + a.w_max + 1;
+    const int qb = NK ? 4 * (nm + 1) + n : wave * (nm + 1) + n;
+    double *dst = a.partial + (((size_t)pair * a.S + sl) * nq + qb) * B * B * 2;
+#pragma unroll
+    for (int r = 0; r < T; ++r)
+#pragma unroll
+        for (int c = 0; c < T; ++c)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int b1 = 8 * r + 2 * g + h, b2 = 8 * c + ((lane & 15) >> 1);
+                if (b1 < B && b2 < B) {
+                    double f = 1.0;
+                    if constexpr (PK == T3_PREC_FP16X3)
+                        f = 1.0 / ((double)scl[ia * kScaleRows + b1] * (double)scl[ib * kScaleRows + b2]);
+                    dst[2 * ((size_t)b1 * B + b2) + odd] = dacc[r][c][h] * f;  // even lane Re, odd lane Im
+                }
+            }
+}
+
 // Edge bins for B = 33..40: every output (b1, b2) of the B x B blocks with
 // b1 >= T or b2 >= T (T = 32, the extent of the one MFMA tile), for the
 // slice's centres, written into the slice's partial block like the tiles.
@@ -888,6 +1352,25 @@ __global__ void k_reduce(const double *partial, int S, int n_max, int w_max, int
 int mfma_tiles(int B) { return B <= kEdgeMaxBins ? 1 : (B + kRows - 1) / kRows; }
 bool edge_bins(int B) { return B > kEdgeT && B <= kEdgeMaxBins; }
 
+// T = ceil(2B / 16) tiles per side; NIS = staging items per producer thread
+// and side (the NA / 2 complex arrays of a side hold 4 B items each).
+template <int PK, bool NK>
+void launch_small(int B, dim3 g, hipStream_t s, const ContractArgs &a)
+{
+    const int T = (2 * B + 15) / 16;
+    const int NIS = ((NK ? 4 : 3) * 4 * B + 255) / 256;
+    if (T == 1)
+        hipLaunchKernelGGL((k_contract_small<PK, 1, NK, 1>), g, dim3(512), 0, s, a);
+    else if (T == 2 && NIS == 1)
+        hipLaunchKernelGGL((k_contract_small<PK, 2, NK, 1>), g, dim3(512), 0, s, a);
+    else if (T == 2)
+        hipLaunchKernelGGL((k_contract_small<PK, 2, NK, 2>), g, dim3(512), 0, s, a);
+    else if (NIS == 1)
+        hipLaunchKernelGGL((k_contract_small<PK, 3, NK, 1>), g, dim3(512), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_contract_small<PK, 3, NK, 2>), g, dim3(512), 0, s, a);
+}
+
 __global__ void k_zero(double *p, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -991,15 +1474,28 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
     const dim3 gy((unsigned)((L.n_max + 1) * S8 * pairs), nt * nt);
     const dim3 gn((unsigned)((L.w_max + 2) / 2 * S8 * pairs), nt * nt);
     const dim3 blk(256);
+    // B <= 24: the real-embedded 16 x 16 tiles
+    const bool small = L.B <= kSmallBins;
+    const dim3 gs((unsigned)((L.n_max + 1) * S8 * pairs));
+    const dim3 gsn((unsigned)((L.w_max + 1) * S8 * pairs));
     switch (plan->precision) {
         case T3_PREC_FP32:
-            hipLaunchKernelGGL((k_contract<T3_PREC_FP32, false>), gy, blk, 0, s, a);
+            if (small)
+                launch_small<T3_PREC_FP32, false>(L.B, gs, s, a);
+            else
+                hipLaunchKernelGGL((k_contract<T3_PREC_FP32, false>), gy, blk, 0, s, a);
             break;
         case T3_PREC_BF16X3:
-            hipLaunchKernelGGL((k_contract<T3_PREC_BF16X3, false>), gy, blk, 0, s, a);
+            if (small)
+                launch_small<T3_PREC_BF16X3, false>(L.B, gs, s, a);
+            else
+                hipLaunchKernelGGL((k_contract<T3_PREC_BF16X3, false>), gy, blk, 0, s, a);
             break;
         case T3_PREC_BF16X6:
-            hipLaunchKernelGGL((k_contract<T3_PREC_BF16X6, false>), gy, blk, 0, s, a);
+            if (small)
+                launch_small<T3_PREC_BF16X6, false>(L.B, gs, s, a);
+            else
+                hipLaunchKernelGGL((k_contract<T3_PREC_BF16X6, false>), gy, blk, 0, s, a);
             break;
         default: {
             const int ns = kNYArr * kScaleRows * (L.n_max + 1) * pairs;
@@ -1010,12 +1506,18 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
             hipLaunchKernelGGL(k_fp16_scale, dim3((ns + 255) / 256), blk, 0, s, (const unsigned *)mx, sc, ns);
             T3_HIP_CHECK(hipGetLastError());
             a.scale = sc;
-            hipLaunchKernelGGL((k_contract<T3_PREC_FP16X3, false>), gy, blk, 0, s, a);
+            if (small)
+                launch_small<T3_PREC_FP16X3, false>(L.B, gs, s, a);
+            else
+                hipLaunchKernelGGL((k_contract<T3_PREC_FP16X3, false>), gy, blk, 0, s, a);
             break;
         }
     }
     T3_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((k_contract<T3_PREC_FP32, true>), gn, blk, 0, s, a);
+    if (small)
+        launch_small<T3_PREC_FP32, true>(L.B, gsn, s, a);
+    else
+        hipLaunchKernelGGL((k_contract<T3_PREC_FP32, true>), gn, blk, 0, s, a);
     T3_HIP_CHECK(hipGetLastError());
     if (edge_bins(L.B)) {
         hipLaunchKernelGGL(k_contract_edge<false>, dim3((unsigned)(S * pairs), L.n_max + 1), blk, 0, s, a);
