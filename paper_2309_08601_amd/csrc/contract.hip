@@ -583,11 +583,12 @@ constexpr int small_row_elems()  // LDS elements per operand row: the parts of k
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// SAME (N_n of one catalog: Z2 = Z3): the X operand w W_n and the Y operand
+// W_n come from the same loads.
 // Waves per SIMD: 4 (two workgroups per CU, at most 128 registers) where the
-// registers fit without spilling, 2 for the N_n kernel and two staging items
-// per thread.
-template <int PK, int T, bool NK, int NIS>
-__global__ __launch_bounds__(512, (NK || NIS > 1) ? 2 : 4) void k_contract_small(ContractArgs a)
+// registers fit without spilling, else 2.
+template <int PK, int T, bool NK, int NIS, bool SAME>
+__global__ __launch_bounds__(512, ((NK && !SAME) || (!NK && NIS > 1)) ? 2 : 4) void k_contract_small(ContractArgs a)
 {
     using E = typename Fmt<PK>::T;            // LDS element
     constexpr int P = Fmt<PK>::parts;
@@ -601,6 +602,13 @@ __global__ __launch_bounds__(512, (NK || NIS > 1) ? 2 : 4) void k_contract_small
     constexpr int STEP = NB * kBlk;            // centres per step
     constexpr int NV = NK ? 1 : 3;             // factor forms per centre
     static_assert(!NK || PK == T3_PREC_FP32, "N_n is computed in FP32");
+    static_assert(NK || !SAME, "shared loads serve N_n only");
+    constexpr int NLS = SAME ? 1 : 2;           // sides that load
+    // N_n of one catalog is Hermitian in (b1, b2): only the tiles on and
+    // above the diagonal are multiplied, the ones below are their conjugate
+    // transposes
+    constexpr bool HERM = NK && SAME;
+    auto tile_on = [](int r, int c) { return !HERM || c >= r; };
     static_assert(!NK || 3 * T * T * 2 * 64 * sizeof(double) <= 2 * BUF * sizeof(E), "N_n sums fit the LDS");
     // two operand buffers, then a dummy row pair that the stores of unused
     // staging slots go to (the staging has no branches: see below)
@@ -678,7 +686,7 @@ __global__ __launch_bounds__(512, (NK || NIS > 1) ? 2 : 4) void k_contract_small
             }
 
         struct Stage {
-            float4 re[2][NIS], im[2][NIS];
+            float4 re[NLS][NIS], im[NLS][NIS];
             float4 cw;  // centre factors of centre ptid mod STEP of the step
         };
         auto load_step = [&](Stage &st, int step) {
@@ -689,7 +697,7 @@ __global__ __launch_bounds__(512, (NK || NIS > 1) ? 2 : 4) void k_contract_small
             const unsigned sbase = (unsigned)(i0 >> 2) * qstride;  // the step's first quad
             const unsigned slast = (unsigned)q_last * qstride;
 #pragma unroll
-            for (int side = 0; side < 2; ++side) {
+            for (int side = 0; side < NLS; ++side) {
                 const float *sp = side ? py : px;
 #pragma unroll
                 for (int u = 0; u < NIS; ++u) {
@@ -740,7 +748,7 @@ __global__ __launch_bounds__(512, (NK || NIS > 1) ? 2 : 4) void k_contract_small
 #pragma unroll
                 for (int u = 0; u < NIS; ++u) {
                     const int q = qq[side][u];
-                    float4 vr = st.re[side][u], vi = st.im[side][u];
+                    float4 vr = st.re[SAME ? 0 : side][u], vi = st.im[SAME ? 0 : side][u];
                     if constexpr (decltype(mask)::value) {
                         const int nv = max(0, min(4, i_end - (i0 + 4 * q)));
                         vr = keep(vr, nv);
@@ -854,11 +862,12 @@ __global__ __launch_bounds__(512, (NK || NIS > 1) ? 2 : 4) void k_contract_small
             for (int j = 0; j < 4; ++j) acc[r][c][j] = 0.f;
             dacc[r][c][0] = dacc[r][c][1] = 0.0;
         }
-    // FP32 runs of one block (kRun = kBlk centres): the four real products of
-    // (b1, b2) are combined into the complex product in FP32 (as the FP32 runs
-    // of the 32 x 32 kernel) and promoted into FP64.  The promotion of a run
-    // comes first in the next block, reading accumulators whose products have
-    // completed; the block's first products then start from zero.
+    // FP32 runs of one block (kRun = kBlk centres, the error model of the
+    // 32 x 32 kernel): at the end of a run the four real products of (b1, b2)
+    // are combined into the complex product in FP32 and promoted into FP64.
+    // The promotion of a run comes first in the next step, reading
+    // accumulators whose products have completed; the step's first products
+    // then start from zero.
     auto swap1 = [](float v) {  // lane ^ 1 (DPP quad_perm 1, 0, 3, 2)
         return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xb1, 0xf, 0xf, true));
     };
@@ -867,6 +876,7 @@ __global__ __launch_bounds__(512, (NK || NIS > 1) ? 2 : 4) void k_contract_small
         for (int r = 0; r < T; ++r)
 #pragma unroll
             for (int c = 0; c < T; ++c) {
+                if (!tile_on(r, c)) continue;
                 const floatx4 d = acc[r][c];
                 const float t0 = fmaf(swap1(d[1]), s1, d[0]);
                 const float t1 = fmaf(swap1(d[3]), s1, d[2]);
@@ -890,9 +900,11 @@ __global__ __launch_bounds__(512, (NK || NIS > 1) ? 2 : 4) void k_contract_small
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
 #pragma unroll
-                    for (int r = 0; r < T; ++r)
+                    for (int r = 0; r < T; ++r) {
+                        if (!tile_on(r, c)) continue;
                         acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(comp(xa[r], s), comp(yb, s),
                                                                          s == 0 ? zero4 : acc[r][c], 0, 0, 0);
+                    }
             }
         } else {
             using V = typename Fmt<PK>::V;
@@ -905,37 +917,33 @@ __global__ __launch_bounds__(512, (NK || NIS > 1) ? 2 : 4) void k_contract_small
                                                                 0, 0, 0);
             };
             // fragment offsets within a row (elements): [X0|X1] 8 g, [Y0|Y0] 8 (g & 1),
-            // [Y1|Y1] 16 + 8 (g & 1), [X0|X2] 8 g + 16 (g >= 2), [Y2|Y0] 32 + 8 g (g < 2) or 8 (g - 2)
+            // [Y1|Y1] 16 + 8 (g & 1), [X0|X2] 8 g + 16 (g >= 2), [Y2|Y0] 32 + 8 g (g < 2) or 8 (g - 2);
+            // column tile by column tile (the Y fragments of one column live)
             const int o01 = 8 * g, o00 = 8 * (g & 1), o11 = 16 + 8 * (g & 1);
-            uint4 x01[T], y00[T], y11[T];
+            const int o02 = 8 * g + (g >= 2 ? 16 : 0), o20 = g < 2 ? 32 + 8 * g : 8 * (g - 2);
+            uint4 x01[T], x02[P == 3 ? T : 1];
 #pragma unroll
             for (int t = 0; t < T; ++t) {
                 x01[t] = *reinterpret_cast<const uint4 *>(base + ia * ARR + 16 * t * RS + o01);
-                y00[t] = *reinterpret_cast<const uint4 *>(base + ib * ARR + 16 * t * RS + o00);
-                y11[t] = *reinterpret_cast<const uint4 *>(base + ib * ARR + 16 * t * RS + o11);
+                if constexpr (P == 3) x02[t] = *reinterpret_cast<const uint4 *>(base + ia * ARR + 16 * t * RS + o02);
             }
 #pragma unroll
-            for (int r = 0; r < T; ++r)
+            for (int c = 0; c < T; ++c) {
+                const E *yc = base + ib * ARR + 16 * c * RS;
+                const uint4 y00 = *reinterpret_cast<const uint4 *>(yc + o00);
+                const uint4 y11 = *reinterpret_cast<const uint4 *>(yc + o11);
 #pragma unroll
-                for (int c = 0; c < T; ++c) {
+                for (int r = 0; r < T; ++r) {
                     acc[r][c] = zero4;
-                    mma(x01[r], y00[c], acc[r][c]);
+                    mma(x01[r], y00, acc[r][c]);
                 }
 #pragma unroll
-            for (int r = 0; r < T; ++r)
+                for (int r = 0; r < T; ++r) mma(x01[r], y11, acc[r][c]);
+                if constexpr (P == 3) {
+                    const uint4 y20 = *reinterpret_cast<const uint4 *>(yc + o20);
 #pragma unroll
-                for (int c = 0; c < T; ++c) mma(x01[r], y11[c], acc[r][c]);
-            if constexpr (P == 3) {
-                const int o02 = 8 * g + (g >= 2 ? 16 : 0), o20 = g < 2 ? 32 + 8 * g : 8 * (g - 2);
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    x01[t] = *reinterpret_cast<const uint4 *>(base + ia * ARR + 16 * t * RS + o02);
-                    y00[t] = *reinterpret_cast<const uint4 *>(base + ib * ARR + 16 * t * RS + o20);
+                    for (int r = 0; r < T; ++r) mma(x02[r], y20, acc[r][c]);
                 }
-#pragma unroll
-                for (int r = 0; r < T; ++r)
-#pragma unroll
-                    for (int c = 0; c < T; ++c) mma(x01[r], y00[c], acc[r][c]);
             }
         }
     };
@@ -957,7 +965,8 @@ __global__ __launch_bounds__(512, (NK || NIS > 1) ? 2 : 4) void k_contract_small
 #pragma unroll
                 for (int c = 0; c < T; ++c)
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) red[((wave - 1) * ND + 2 * (r * T + c) + h) * 64 + lane] = dacc[r][c][h];
+                    for (int h = 0; h < 2; ++h)
+                        if (tile_on(r, c)) red[((wave - 1) * ND + 2 * (r * T + c) + h) * 64 + lane] = dacc[r][c][h];
         }
         __syncthreads();
         if (wave > 0) return;
@@ -968,7 +977,8 @@ __global__ __launch_bounds__(512, (NK || NIS > 1) ? 2 : 4) void k_contract_small
 #pragma unroll
                 for (int c = 0; c < T; ++c)
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) dacc[r][c][h] += red[(w * ND + 2 * (r * T + c) + h) * 64 + lane];
+                    for (int h = 0; h < 2; ++h)
+                        if (tile_on(r, c)) dacc[r][c][h] += red[(w * ND + 2 * (r * T + c) + h) * 64 + lane];
     }
     const int nq = 4 * (nm + 1) + a.w_max + 1;
     const int qb = NK ? 4 * (nm + 1) + n : wave * (nm + 1) + n;
@@ -979,12 +989,15 @@ __global__ __launch_bounds__(512, (NK || NIS > 1) ? 2 : 4) void k_contract_small
         for (int c = 0; c < T; ++c)
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
+                if (!tile_on(r, c)) continue;
                 const int b1 = 8 * r + 2 * g + h, b2 = 8 * c + ((lane & 15) >> 1);
                 if (b1 < B && b2 < B) {
                     double f = 1.0;
                     if constexpr (PK == T3_PREC_FP16X3)
                         f = 1.0 / ((double)scl[ia * kScaleRows + b1] * (double)scl[ib * kScaleRows + b2]);
-                    dst[2 * ((size_t)b1 * B + b2) + odd] = dacc[r][c][h] * f;  // even lane Re, odd lane Im
+                    const double v = dacc[r][c][h] * f;
+                    dst[2 * ((size_t)b1 * B + b2) + odd] = v;  // even lane Re, odd lane Im
+                    if (HERM && c > r) dst[2 * ((size_t)b2 * B + b1) + odd] = odd ? -v : v;
                 }
             }
 }
@@ -1354,21 +1367,31 @@ bool edge_bins(int B) { return B > kEdgeT && B <= kEdgeMaxBins; }
 
 // T = ceil(2B / 16) tiles per side; NIS = staging items per producer thread
 // and side (the NA / 2 complex arrays of a side hold 4 B items each).
-template <int PK, bool NK>
-void launch_small(int B, dim3 g, hipStream_t s, const ContractArgs &a)
+template <int PK, bool NK, bool SAME>
+void launch_small_same(int B, dim3 g, hipStream_t s, const ContractArgs &a)
 {
     const int T = (2 * B + 15) / 16;
     const int NIS = ((NK ? 4 : 3) * 4 * B + 255) / 256;
     if (T == 1)
-        hipLaunchKernelGGL((k_contract_small<PK, 1, NK, 1>), g, dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_contract_small<PK, 1, NK, 1, SAME>), g, dim3(512), 0, s, a);
     else if (T == 2 && NIS == 1)
-        hipLaunchKernelGGL((k_contract_small<PK, 2, NK, 1>), g, dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_contract_small<PK, 2, NK, 1, SAME>), g, dim3(512), 0, s, a);
     else if (T == 2)
-        hipLaunchKernelGGL((k_contract_small<PK, 2, NK, 2>), g, dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_contract_small<PK, 2, NK, 2, SAME>), g, dim3(512), 0, s, a);
     else if (NIS == 1)
-        hipLaunchKernelGGL((k_contract_small<PK, 3, NK, 1>), g, dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_contract_small<PK, 3, NK, 1, SAME>), g, dim3(512), 0, s, a);
     else
-        hipLaunchKernelGGL((k_contract_small<PK, 3, NK, 2>), g, dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_contract_small<PK, 3, NK, 2, SAME>), g, dim3(512), 0, s, a);
+}
+
+// same: one catalog (Z2 = Z3 for every launched pair), for the N_n kernel
+template <int PK, bool NK>
+void launch_small(int B, dim3 g, hipStream_t s, const ContractArgs &a, bool same = false)
+{
+    if (NK && same)
+        launch_small_same<PK, NK, NK>(B, g, s, a);
+    else
+        launch_small_same<PK, NK, false>(B, g, s, a);
 }
 
 __global__ void k_zero(double *p, size_t n)
@@ -1515,7 +1538,7 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
     }
     T3_HIP_CHECK(hipGetLastError());
     if (small)
-        launch_small<T3_PREC_FP32, true>(L.B, gsn, s, a);
+        launch_small<T3_PREC_FP32, true>(L.B, gsn, s, a, n_z == 1);
     else
         hipLaunchKernelGGL((k_contract<T3_PREC_FP32, true>), gn, blk, 0, s, a);
     T3_HIP_CHECK(hipGetLastError());
