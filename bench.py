@@ -477,23 +477,38 @@ def bench_tomo(t3, torch, dev):
     torch.cuda.synchronize()
     t_graph = time.perf_counter() - t0   # replay of the captured schedule
     captures, launches = plan.graph_stats()
+    tuned = plan.settings()
     # eager run with HIP events for the stage split
     tp = t3.Plan(wl.edges(), wl.n_max, box_size=box, timing=True, cell_arcmin=0.0)
     tp.autotune(dcs, sample_per_bin=4000)  # cached choice, no timing
     _, np2 = tp.forward_tomo(dcs)
     ms, nl = tp.stage_times()
+    # the other stage-1 launch mode at the tuned settings (persistent work
+    # queue over all (centre, catalog) tasks against one launch per catalog)
+    other = 1 - tuned["scan_mode"]
+    to = t3.Plan(wl.edges(), wl.n_max, box_size=box, timing=True, cell_arcmin=tuned["cell_arcmin"],
+                 scan_mode=other, lane_neighbours=tuned["lane_neighbours"] or 128.0,
+                 lane=tuned["lane_neighbours"] > 0, tile_mode=tuned["tile_mode"],
+                 chunk_centres=tuned["chunk_centres"])
+    _, np3 = to.forward_tomo(dcs)
+    ms_other, nl_other = to.stage_times()
+    assert np3 == np2
+    modes = {tuned["scan_mode"]: (ms, nl), other: (ms_other, nl_other)}
     n_c = sum(c.n for c in cats)
     B, nm, nz = wl.n_bins, wl.n_max, len(cats)
     gemm_flops = 8.0 * 5 * (nm + 1) * B * B * nz * nz * n_c
     log(f"[bench] tomography: {npairs} pairs in {t_graph:.2f} s (graph replay; first call with capture "
-        f"{t_first:.2f} s; {captures} capture(s), {launches} launches), stages ms {[round(v, 1) for v in ms]}")
+        f"{t_first:.2f} s; {captures} capture(s), {launches} launches), stages ms {[round(v, 1) for v in ms]}, "
+        f"tuned {tuned}; stage 1 with per-catalog launches {modes[0][0][1]:.1f} ms, with the persistent "
+        f"work queue {modes[1][0][1]:.1f} ms")
     return {"workload": f"tomo_5bin: 5 bins {'/'.join(str(c.n) for c in cats)} galaxies in 600' x 600', "
                         f"all 125 ordered triples, 20 log bins 0.5'-100', n_max=30, FP32",
             "pairs": npairs, "seconds": t_graph, "value": npairs / t_graph, "unit": "galaxy-pairs/s",
             "first_call_seconds": t_first, "graph_captures": captures, "graph_launches": launches,
             "gemm_tflops": gemm_flops / (ms[2] / 1e3) / 1e12, "stage_ms": {"cells": ms[0], "stage1": ms[1],
                                                                              "stage2": ms[2]},
-            "autotune_seconds": t_tune, "autotune_best_sample_ms": tune_ms}
+            "autotune_seconds": t_tune, "autotune_best_sample_ms": tune_ms, "tuned": tuned,
+            "stage1_ms_by_launch_mode": {"per_catalog": modes[0][0][1], "persistent": modes[1][0][1]}}
 
 
 def bench_grad(t3, torch, dev):

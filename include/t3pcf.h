@@ -134,6 +134,14 @@ typedef struct {
                            /* each allocation).  A call that would exceed it  */
                            /* returns T3_ENOMEM without allocating; see       */
                            /* t3_workspace_bytes.                             */
+    double lane_neighbours; /* stage-1 bins with at most this many expected   */
+                           /* neighbours per centre run one lane per centre;  */
+                           /* 0 -> 128 (the bound of the FP32 lane sums);     */
+                           /* in (0, 128]; T3_FLAG_NO_LANE turns the lane     */
+                           /* kernel off                                      */
+    int32_t tile_mode;     /* stage-2 tiles for B <= 24: 0 real-embedded      */
+                           /* 16 x 16 (2B x 2B real product), 1 complex       */
+                           /* 32 x 32 (as for B > 24)                         */
 } t3_params;
 
 typedef struct {
@@ -401,16 +409,33 @@ int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets,
 int t3_backward(t3_plan *plan, const t3_catalog *cat, const int32_t *centres, int64_t n_centres,
                 const double *grad_ups, float *grad_g1, float *grad_g2, float *grad_w, void *stream);
 
-/* Autotuner.  Times the forward pass of this plan on a deterministic sample
- * of at most sample_per_bin centres of every catalog (cats: HOST array of
- * n_z catalogs, as for t3_forward_tomo) for a few candidate settings -- cell
- * size 0.6x / 1x / 1.6x the automatic one, and both stage-1 launch modes --
- * and keeps the fastest in the plan (cell size, launch mode).  The choice is
- * cached per process, keyed by (n_bins, n_max, n_z, precision, catalog-size
- * class); a cached choice is applied without timing.  best_ms (HOST,
- * optional) receives the best sample time.  Synchronises the stream. */
+/* Autotuner (Sect. 3.5: the batched tomographic evaluation of eq. tomoGn
+ * is tuned once per problem shape and replayed).  Times the forward pass of
+ * this plan on a deterministic sample of at most sample_per_bin centres of
+ * every catalog (cats: HOST array of n_z catalogs, as for t3_forward_tomo)
+ * and keeps the fastest settings in the plan, one coordinate at a time from
+ * the best so far: cell size 0.6x / 1x / 1.6x the automatic one with both
+ * stage-1 launch modes; the stage-1 lane-kernel threshold (0, 64 or 128
+ * expected neighbours per centre; none above 128, the bound of the FP32
+ * lane sums; skipped with T3_FLAG_NO_LANE); for B <= 24 the stage-2 tile
+ * shape (real-embedded 16 x 16 or complex 32 x 32 MFMA tiles); and, when
+ * the plan's chunk capacity is automatic, 1, 1/2 or 1/4 of the automatic
+ * capacity.  Each candidate is timed twice (best kept); ties keep the
+ * earlier one.  The choice is cached per process, keyed by (n_bins, n_max,
+ * n_z, precision, catalog-size class, box, sample_per_bin, requested chunk
+ * capacity); a cached choice is applied without timing.  best_ms (HOST,
+ * optional) receives the best sample time (0 for a cached choice).
+ * Synchronises the stream. */
 int t3_autotune(t3_plan *plan, const t3_catalog *cats, int32_t n_z, int64_t sample_per_bin,
                 double *best_ms, void *stream);
+
+/* The plan's current tunable settings (each output HOST and optional):
+ * cell side in arcmin, stage-1 launch mode (0 one wavefront per task,
+ * 1 persistent work queue), lane-kernel threshold in expected neighbours,
+ * stage-2 tile shape for B <= 24 (0 real-embedded 16 x 16, 1 complex
+ * 32 x 32) and requested chunk capacity in centres (0: automatic). */
+int t3_plan_settings(const t3_plan *plan, double *cell_arcmin, int32_t *scan_mode, double *lane_neighbours,
+                     int32_t *tile_mode, int32_t *chunk_centres);
 
 /* Stage timings of the most recent t3_forward / t3_forward_tomo call of a
  * plan created with T3_FLAG_TIMING, from HIP events recorded on the

@@ -748,7 +748,7 @@ int backward(t3_plan *plan, const t3_catalog &cat, const int32_t *centres, int64
         T3_HIP_CHECK(hipFuncSetAttribute((const void *)k_adj_coef,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int n_lane = 0;
-    if (!kept && n_c > 0) T3_TRY(lane_bins(plan, sc, 0, B, kLaneNeighbours, s, &n_lane));
+    if (!kept && n_c > 0) T3_TRY(lane_bins(plan, sc, 0, B, plan->lane_neighbours, s, &n_lane));
     for (int64_t c0 = 0; c0 < n_c; c0 += L.K) {
         const int nc = (int)((n_c - c0) < L.K ? (n_c - c0) : L.K);
         const float *planes = kept ? plan->kept.as<float>() + (size_t)(c0 / L.K) * L.floats() : plan->chunk.as<float>();

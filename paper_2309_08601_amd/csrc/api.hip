@@ -220,7 +220,7 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
     int n_lane = plan->B;
     for (int z = 0; z < n_z; ++z) {
         int k = 0;
-        T3_TRY(lane_bins(plan, plan->cats[z], 0, plan->B, kLaneNeighbours, s, &k));
+        T3_TRY(lane_bins(plan, plan->cats[z], 0, plan->B, plan->lane_neighbours, s, &k));
         if (plan->cats[z].n > 0) n_lane = std::min(n_lane, k);
     }
     if (n_lane == plan->B && n_all == 0) n_lane = 0;
@@ -307,6 +307,7 @@ static int forward_impl(t3_plan *plan, const t3_catalog *cats, int n_z, const in
         put(n_lane);
         put(plan->scan_mode);
         put(plan->scan_var);
+        put(plan->tile_mode);
         put(plan->precision);
         put((int64_t)plan->flags);
         put(keep ? 1 : 0);
@@ -463,6 +464,9 @@ int t3_plan_create(const t3_params *p, t3_plan **out)
             return fail(T3_EINVAL, "t3_plan_create: bad cell size");
         if (p->chunk_centres < 0) return fail(T3_EINVAL, "t3_plan_create: bad chunk size");
         if (p->scan_mode < 0 || p->scan_mode > 1) return fail(T3_EINVAL, "t3_plan_create: bad scan mode");
+        if (!(p->lane_neighbours >= 0.0 && p->lane_neighbours <= kLaneNeighbours))
+            return fail(T3_EINVAL, "t3_plan_create: lane_neighbours must be in [0, 128] (0: automatic)");
+        if (p->tile_mode < 0 || p->tile_mode > 1) return fail(T3_EINVAL, "t3_plan_create: bad tile mode");
 
         t3_plan *plan = new (std::nothrow) t3_plan();
         if (!plan) return fail(T3_ENOMEM, "t3_plan_create: host allocation failed");
@@ -478,6 +482,8 @@ int t3_plan_create(const t3_params *p, t3_plan **out)
         plan->cell_arcmin = p->cell_arcmin;
         plan->chunk_req = p->chunk_centres;
         plan->scan_mode = p->scan_mode;
+        plan->lane_neighbours = p->lane_neighbours > 0.0 ? p->lane_neighbours : kLaneNeighbours;
+        plan->tile_mode = p->tile_mode;
         plan->budget.limit = p->max_workspace_bytes;
         plan->edges_lat.resize(p->n_bins + 1);
         plan->e2.resize(p->n_bins + 1);
@@ -668,7 +674,7 @@ int t3_harmonics(t3_plan *plan, const t3_catalog *cat, const int32_t *centres, i
             L.K = (int)std::max<int64_t>(256, (n_centres + 255) & ~(int64_t)255);
         T3_TRY(plan->chunk.reserve(sizeof(float) * L.floats()));
         int n_lane = 0;
-        T3_TRY(lane_bins(plan, sc, 0, plan->B, kLaneNeighbours, s, &n_lane));
+        T3_TRY(lane_bins(plan, sc, 0, plan->B, plan->lane_neighbours, s, &n_lane));
         for (int64_t c0 = 0; c0 < n_centres; c0 += L.K) {
             const int n = (int)((n_centres - c0) < L.K ? (n_centres - c0) : L.K);
             const SortedCatalog *cl[1] = {&sc};
@@ -816,6 +822,37 @@ int t3_normalise_backward(t3_plan *plan, const double *ups, int32_t n_sets, cons
     return normalise_backward(plan, ups, grad_gamma_n, n_sets, grad_ups, (hipStream_t)stream);
 }
 
+namespace {
+// The settings the autotuner chooses.
+struct TuneChoice {
+    double cell = 0;    // cell side, arcmin
+    int mode = 0;       // stage-1 launch mode
+    double lane = 0;    // lane-kernel threshold, expected neighbours per centre
+    int tile = 0;       // stage-2 tile shape for B <= 24
+    int chunk = 0;      // chunk capacity request (0: automatic)
+};
+
+void apply_choice(t3_plan *plan, const TuneChoice &c)
+{
+    plan->cell_arcmin = c.cell;
+    plan->scan_mode = c.mode;
+    plan->lane_neighbours = c.lane;
+    plan->tile_mode = c.tile;
+    plan->chunk_req = c.chunk;
+}
+
+TuneChoice choice_of(const t3_plan *plan)
+{
+    TuneChoice c;
+    c.cell = plan->cell_arcmin;
+    c.mode = plan->scan_mode;
+    c.lane = plan->lane_neighbours;
+    c.tile = plan->tile_mode;
+    c.chunk = plan->chunk_req;
+    return c;
+}
+}  // namespace
+
 int t3_autotune(t3_plan *plan, const t3_catalog *cats, int32_t n_z, int64_t sample_per_bin, double *best_ms,
                 void *stream)
 {
@@ -832,14 +869,15 @@ int t3_autotune(t3_plan *plan, const t3_catalog *cats, int32_t n_z, int64_t samp
         int size_class = 0;
         for (int64_t v = n_mean; v > 1; v >>= 1) ++size_class;
         static std::mutex mu;
-        static std::map<std::tuple<int, int, int, int, int, int64_t>, std::pair<double, int>> cache;
-        const auto key = std::make_tuple(plan->B, plan->n_max, n_z, plan->precision, size_class, plan->box_size);
+        static std::map<std::tuple<int, int, int, int, int, int64_t, int64_t, int>, TuneChoice> cache;
+        const int64_t sample_class = sample_per_bin;
+        const auto key = std::make_tuple(plan->B, plan->n_max, n_z, plan->precision, size_class, plan->box_size,
+                                         sample_class, plan->chunk_req);
         {
             std::lock_guard<std::mutex> lk(mu);
             auto it = cache.find(key);
             if (it != cache.end()) {
-                plan->cell_arcmin = it->second.first;
-                plan->scan_mode = it->second.second;
+                apply_choice(plan, it->second);
                 if (best_ms) *best_ms = 0.0;
                 return T3_OK;
             }
@@ -864,58 +902,104 @@ int t3_autotune(t3_plan *plan, const t3_catalog *cats, int32_t n_z, int64_t samp
 
         const double area = (double)plan->box_size * (double)plan->box_size;
         const double auto_side = std::sqrt(8.0 * area / (double)std::max<int64_t>(n_mean, 1)) * plan->unit;
-        const double keep_cell = plan->cell_arcmin;
-        const int keep_mode = plan->scan_mode;
+        const TuneChoice keep = choice_of(plan);
         const uint32_t keep_flags = plan->flags;
         plan->flags = (plan->flags & ~T3_FLAG_TIMING) | T3_FLAG_NO_GRAPH;
         hipEvent_t e0, e1;
         T3_HIP_CHECK(hipEventCreate(&e0));
         T3_HIP_CHECK(hipEventCreate(&e1));
-        double best = 1e300, best_cell = keep_cell;
-        int best_mode = keep_mode, rc = T3_OK;
-        const double factors[3] = {0.6, 1.0, 1.6};
-        for (int mode = 0; mode < 2 && rc == T3_OK; ++mode)
-            for (double f : factors) {
-                plan->cell_arcmin = f * auto_side;
-                plan->scan_mode = mode;
-                double ms_best = 1e300;
-                for (int rep = 0; rep < 2 && rc == T3_OK; ++rep) {
-                    if ((rc = (hipEventRecord(e0, s) == hipSuccess) ? T3_OK : T3_EHIP) != T3_OK) break;
-                    rc = forward_impl(plan, cats, n_z, cl, cnt.data(), plan->tune_out.as<double>(), nullptr, s);
-                    if (rc != T3_OK) break;
-                    float ms = 0.f;
-                    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                        rc = fail(T3_EHIP, "t3_autotune: event timing failed");
-                        break;
-                    }
-                    ms_best = std::min(ms_best, (double)ms);
+        int rc = T3_OK;
+        // best of two timed forward passes of the sample with settings c
+        auto time_of = [&](const TuneChoice &c) -> double {
+            apply_choice(plan, c);
+            double ms_best = 1e300;
+            for (int rep = 0; rep < 2 && rc == T3_OK; ++rep) {
+                if ((rc = (hipEventRecord(e0, s) == hipSuccess) ? T3_OK : T3_EHIP) != T3_OK) break;
+                rc = forward_impl(plan, cats, n_z, cl, cnt.data(), plan->tune_out.as<double>(), nullptr, s);
+                if (rc != T3_OK) break;
+                float ms = 0.f;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    rc = fail(T3_EHIP, "t3_autotune: event timing failed");
+                    break;
                 }
-                if (rc == T3_OK && ms_best < best) {
-                    best = ms_best;
-                    best_cell = plan->cell_arcmin;
-                    best_mode = mode;
-                }
+                ms_best = std::min(ms_best, (double)ms);
             }
+            return ms_best;
+        };
+        // One coordinate at a time, each from the best so far (ties keep the
+        // earlier candidate): cell size x stage-1 launch mode, then the
+        // lane-kernel threshold, the stage-2 tile shape (B <= 24) and the
+        // chunk capacity (when the plan leaves it automatic).
+        TuneChoice best = keep;
+        double best_t = 1e300;
+        auto consider = [&](const TuneChoice &c) {
+            if (rc != T3_OK) return;
+            const double t = time_of(c);
+            if (rc == T3_OK && t < best_t) {
+                best_t = t;
+                best = c;
+            }
+        };
+        const double factors[3] = {0.6, 1.0, 1.6};
+        for (int mode = 0; mode < 2; ++mode)
+            for (double f : factors) {
+                TuneChoice c = best;
+                c.cell = f * auto_side;
+                c.mode = mode;
+                consider(c);
+            }
+        if (!(keep_flags & T3_FLAG_NO_LANE)) {
+            // at most 128 expected neighbours: the bound of the FP32 lane sums
+            for (double lane : {0.0, 64.0, 128.0}) {
+                TuneChoice c = best;
+                c.lane = lane;
+                if (c.lane != best.lane) consider(c);
+            }
+        }
+        if (plan->B <= 24) {
+            TuneChoice c = best;
+            c.tile = 1 - best.tile;
+            consider(c);
+        }
+        if (keep.chunk <= 0) {
+            ChunkLayout L = layout_of(plan);
+            const int k_auto = choose_chunk(plan, L);
+            for (int div : {2, 4}) {
+                TuneChoice c = best;
+                c.chunk = std::max(256, (k_auto / div) & ~255);
+                consider(c);
+            }
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         plan->flags = keep_flags;
         if (rc != T3_OK) {
-            plan->cell_arcmin = keep_cell;
-            plan->scan_mode = keep_mode;
+            apply_choice(plan, keep);
             return rc;
         }
-        plan->cell_arcmin = best_cell;
-        plan->scan_mode = best_mode;
+        apply_choice(plan, best);
         {
             std::lock_guard<std::mutex> lk(mu);
-            cache[key] = std::make_pair(best_cell, best_mode);
+            cache[key] = best;
         }
-        if (best_ms) *best_ms = best;
+        if (best_ms) *best_ms = best_t;
         return T3_OK;
     } catch (...) {
         return fail(T3_EINVAL, "t3_autotune: exception");
     }
+}
+
+int t3_plan_settings(const t3_plan *plan, double *cell_arcmin, int32_t *scan_mode, double *lane_neighbours,
+                     int32_t *tile_mode, int32_t *chunk_centres)
+{
+    if (!plan) return fail(T3_EINVAL, "t3_plan_settings: null plan");
+    if (cell_arcmin) *cell_arcmin = plan->cell_arcmin;
+    if (scan_mode) *scan_mode = plan->scan_mode;
+    if (lane_neighbours) *lane_neighbours = plan->lane_neighbours;
+    if (tile_mode) *tile_mode = plan->tile_mode;
+    if (chunk_centres) *chunk_centres = plan->chunk_req;
+    return T3_OK;
 }
 
 int t3_graph_stats(const t3_plan *plan, int64_t *captures, int64_t *launches)

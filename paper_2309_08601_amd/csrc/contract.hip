@@ -1497,8 +1497,9 @@ int contract_chunk(t3_plan *plan, const CentreSet &cs, int64_t c0, int n_c, cons
     const dim3 gy((unsigned)((L.n_max + 1) * S8 * pairs), nt * nt);
     const dim3 gn((unsigned)((L.w_max + 2) / 2 * S8 * pairs), nt * nt);
     const dim3 blk(256);
-    // B <= 24: the real-embedded 16 x 16 tiles
-    const bool small = L.B <= kSmallBins;
+    // B <= 24: the real-embedded 16 x 16 tiles (unless the plan asks for the
+    // complex 32 x 32 ones)
+    const bool small = L.B <= kSmallBins && plan->tile_mode == 0;
     const dim3 gs((unsigned)((L.n_max + 1) * S8 * pairs));
     const dim3 gsn((unsigned)((L.w_max + 1) * S8 * pairs));
     switch (plan->precision) {

@@ -354,7 +354,7 @@ int forward_grid(t3_plan *plan, const t3_catalog &cat, int64_t delta, const int3
     const SortedCatalog *cl[1] = {&plan->cats[0]};
     const bool jk = !(plan->flags & T3_FLAG_KEEP_JK);
     int n_lane = 0;
-    T3_TRY(lane_bins(plan, plan->cats[0], 0, b_disc, kLaneNeighbours, s, &n_lane));
+    T3_TRY(lane_bins(plan, plan->cats[0], 0, b_disc, plan->lane_neighbours, s, &n_lane));
     for (int64_t c0 = 0; c0 < cs.n; c0 += L.K) {
         const int n = (int)((cs.n - c0) < L.K ? (cs.n - c0) : L.K);
         T3_TRY(timing_mark(plan, 1, true, s));

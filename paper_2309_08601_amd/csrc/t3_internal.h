@@ -187,6 +187,8 @@ struct t3_plan {
     t3::CentreSet centres;      // centres of t3_harmonics / t3_backward
     t3::CentreSet csets[8];     // centres per tomographic bin of a forward call
     int scan_mode = 0;          // 0: one wavefront per task, 1: persistent work queue
+    double lane_neighbours = 128.0;  // stage-1 bins with at most this many expected neighbours: one lane per centre
+    int tile_mode = 0;          // stage 2, B <= 24: 0 real-embedded 16 x 16 tiles, 1 complex 32 x 32 tiles
     hipStream_t cap_stream = nullptr;     // graph capture stream (default priority)
     hipGraphExec_t graph_exec = nullptr;  // last captured forward schedule
     std::vector<int64_t> graph_key;       // what that schedule was captured for

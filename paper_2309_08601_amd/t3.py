@@ -40,7 +40,8 @@ class t3_params(ctypes.Structure):
                 ("lattice_unit", ctypes.c_double), ("box_lo_x", ctypes.c_int32),
                 ("box_lo_y", ctypes.c_int32), ("box_size", ctypes.c_int64),
                 ("cell_arcmin", ctypes.c_double), ("chunk_centres", ctypes.c_int32),
-                ("scan_mode", ctypes.c_int32), ("max_workspace_bytes", ctypes.c_int64)]
+                ("scan_mode", ctypes.c_int32), ("max_workspace_bytes", ctypes.c_int64),
+                ("lane_neighbours", ctypes.c_double), ("tile_mode", ctypes.c_int32)]
 
 
 class t3_catalog(ctypes.Structure):
@@ -66,7 +67,7 @@ class T3Error(RuntimeError):
 
 EXPORTED = ["t3_plan_create", "t3_plan_destroy", "t3_forward", "t3_forward_tomo", "t3_harmonics",
             "t3_normalise_resum", "t3_normalise_backward", "t3_backward", "t3_autotune", "t3_stage_times",
-            "t3_workspace_bytes", "t3_graph_stats", "t3_forward_noalloc", "t3_error_string",
+            "t3_workspace_bytes", "t3_graph_stats", "t3_plan_settings", "t3_forward_noalloc", "t3_error_string",
             "t3_last_error_message", "t3_version"]
 
 
@@ -114,6 +115,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.t3_workspace_bytes.restype = ctypes.c_int
     lib.t3_graph_stats.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64)]
     lib.t3_graph_stats.restype = ctypes.c_int
+    lib.t3_plan_settings.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int32), P(ctypes.c_double),
+                                     P(ctypes.c_int32), P(ctypes.c_int32)]
+    lib.t3_plan_settings.restype = ctypes.c_int
     lib.t3_error_string.argtypes = [ctypes.c_int]
     lib.t3_error_string.restype = ctypes.c_char_p
     lib.t3_last_error_message.argtypes = []
@@ -185,7 +189,8 @@ class Plan:
                  precision: str = "fp32", keep_jk: bool = False, lattice_unit: float = 0.0,
                  cell_arcmin: float = 0.0, chunk_centres: int = 0, timing: bool = False,
                  graph: bool = True, scan_mode: int = 0, edge_correct: bool = False, lane: bool = True,
-                 keep_planes: bool = False, deterministic: bool = False, max_workspace_bytes: int = 0):
+                 keep_planes: bool = False, deterministic: bool = False, max_workspace_bytes: int = 0,
+                 lane_neighbours: float = 0.0, tile_mode: int = 0):
         self.edges = np.ascontiguousarray(edges, dtype=np.float64)
         self.B = len(self.edges) - 1
         self.n_max = int(n_max)
@@ -199,7 +204,8 @@ class Plan:
                       | (T3_FLAG_DETERMINISTIC if deterministic else 0),
                       float(lattice_unit),
                       int(box_lo[0]), int(box_lo[1]), int(box_size), float(cell_arcmin),
-                      int(chunk_centres), int(scan_mode), int(max_workspace_bytes))
+                      int(chunk_centres), int(scan_mode), int(max_workspace_bytes), float(lane_neighbours),
+                      int(tile_mode))
         h = ctypes.c_void_p()
         _check(_lib.t3_plan_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h
@@ -400,7 +406,9 @@ class Plan:
         return out
 
     def autotune(self, cats, sample_per_bin: int = 20000) -> float:
-        """Pick cell size and stage-1 launch mode by timing a centre sample."""
+        """Pick cell size, stage-1 launch mode, lane-kernel threshold, stage-2
+        tile shape and chunk capacity by timing a centre sample (cached per
+        problem shape); returns the best sample time in ms (0 if cached)."""
         cats = cats if isinstance(cats, (list, tuple)) else [cats]
         arr = (t3_catalog * len(cats))(*[c.c_struct() for c in cats])
         best = ctypes.c_double(0.0)
@@ -414,6 +422,18 @@ class Plan:
         nl = (ctypes.c_int64 * 4)()
         _check(_lib.t3_stage_times(self._h, ms, nl))
         return list(ms), list(nl)
+
+    def settings(self) -> dict:
+        """The plan's tunable settings (see t3_plan_settings)."""
+        cell = ctypes.c_double(0.0)
+        mode = ctypes.c_int32(0)
+        lane = ctypes.c_double(0.0)
+        tile = ctypes.c_int32(0)
+        chunk = ctypes.c_int32(0)
+        _check(_lib.t3_plan_settings(self._h, ctypes.byref(cell), ctypes.byref(mode), ctypes.byref(lane),
+                                     ctypes.byref(tile), ctypes.byref(chunk)))
+        return {"cell_arcmin": cell.value, "scan_mode": mode.value, "lane_neighbours": lane.value,
+                "tile_mode": tile.value, "chunk_centres": chunk.value}
 
     def graph_stats(self):
         """(captures, launches) of the plan's chunk-schedule graph."""

@@ -68,6 +68,10 @@ def _params(**kw):
     (dict(max_workspace_bytes=-1), -1),
     (dict(box_size=0), -1),
     (dict(box_size=1 << 40), -2),
+    (dict(lane_neighbours=-1.0), -1),
+    (dict(lane_neighbours=129.0), -1),
+    (dict(lane_neighbours=float("nan")), -1),
+    (dict(tile_mode=2), -1),
 ])
 def test_plan_create_rejects(lib, kw, code):
     pytest.importorskip("torch")
@@ -92,6 +96,26 @@ def test_plan_create_and_destroy_ok(lib, flags):
     assert h.value
     t3._lib.t3_plan_destroy(h)
     assert t3._lib.t3_error_string(-5) == b"position outside the lattice box"
+
+
+def test_plan_settings_reports_parameters(lib):
+    """The tunables a plan is created with are what t3_plan_settings reports
+    (lane threshold 0 means the automatic 128)."""
+    pytest.importorskip("torch")
+    from paper_2309_08601_amd import t3
+    for kw, lane in [(dict(), 128.0), (dict(lane_neighbours=64.0, tile_mode=1, scan_mode=1, chunk_centres=512), 64.0)]:
+        p, edges = _params(**kw)
+        h = ctypes.c_void_p()
+        assert t3._lib.t3_plan_create(ctypes.byref(p), ctypes.byref(h)) == 0
+        cell, mode, ln, tile, chunk = (ctypes.c_double(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32(),
+                                       ctypes.c_int32())
+        assert t3._lib.t3_plan_settings(h, ctypes.byref(cell), ctypes.byref(mode), ctypes.byref(ln),
+                                        ctypes.byref(tile), ctypes.byref(chunk)) == 0
+        assert ln.value == lane
+        assert tile.value == kw.get("tile_mode", 0) and mode.value == kw.get("scan_mode", 0)
+        assert chunk.value == kw.get("chunk_centres", 0)
+        t3._lib.t3_plan_destroy(h)
+    assert t3._lib.t3_plan_settings(None, None, None, None, None, None) == -1
 
 
 def test_edge_correct_plan_rejects_adjoint_and_bad_theta(lib):

@@ -94,18 +94,38 @@ def test_graph_captured_once_and_replayed(t3):
 
 
 def test_autotune_keeps_results(t3):
+    """The tuner picks among its candidates, caches the choice per shape,
+    and every setting it may pick (stage-2 tile shape, lane threshold,
+    chunk capacity, launch mode) gives the oracle's multipoles."""
     from oracle import multipole as mp
     cats, dcs = _small(t3)
     edges = np.geomspace(1.0, 12.0, 5)
     lo, size = box_for(40.0)
+    o = mp.multipoles_tomo(cats, edges, 6)
+    ref = mp.pack_nonneg(o["ups"], o["N"], 6)
     plan = t3.Plan(edges, 6, box_lo=lo, box_size=size)
     best = plan.autotune(dcs, sample_per_bin=300)
-    assert best >= 0.0
+    assert best > 0.0
+    st = plan.settings()
+    print("tuned:", st, f"{best:.3f} ms", flush=True)
+    assert st["scan_mode"] in (0, 1) and st["tile_mode"] in (0, 1)
+    assert st["lane_neighbours"] in (0.0, 64.0, 128.0) and st["cell_arcmin"] > 0.0
+    assert st["chunk_centres"] == 0 or st["chunk_centres"] % 256 == 0
     ups, npairs = plan.forward_tomo(dcs)
-    o = mp.multipoles_tomo(cats, edges, 6)
     assert npairs == o["npairs"]
-    e, _ = multipole_errors(ups.cpu().numpy(), mp.pack_nonneg(o["ups"], o["N"], 6))
+    e, _ = multipole_errors(ups.cpu().numpy(), ref)
     assert e.max() <= FP32_TOL
+    # cached: a second plan of the same shape takes the choice without timing
+    again = t3.Plan(edges, 6, box_lo=lo, box_size=size)
+    assert again.autotune(dcs, sample_per_bin=300) == 0.0
+    assert again.settings() == st
+    for kw in [dict(tile_mode=1), dict(tile_mode=0, lane_neighbours=64.0), dict(lane=False, chunk_centres=256),
+               dict(scan_mode=1, tile_mode=1, chunk_centres=512)]:
+        p = t3.Plan(edges, 6, box_lo=lo, box_size=size, **kw)
+        ups, npairs = p.forward_tomo(dcs)
+        assert npairs == o["npairs"], kw
+        e, _ = multipole_errors(ups.cpu().numpy(), ref)
+        assert e.max() <= FP32_TOL, (kw, e.max())
 
 
 def test_tomo_5bin_workload_4k_centres_per_bin(t3):
