@@ -20,10 +20,12 @@
 // else, so bin membership is exact.  z is formed in FP64 (rsqrt seed + one
 // Newton step), anchors z^{4k} are FP64 and rounded once to FP32 (those at
 // multiples of 8 form the only dependency chain, each z^{8k+4} hangs off the
-// anchor below); between anchors powers p_m = z^m advance by FP32 complex
-// multiplication from the nearer anchor (at most two steps), so the error of
-// any p_m is a few FP32 ulp whatever m (with chains of up to 4 steps, small
-// tomographic samples reached the 1e-6 FP32 bar on single blocks).
+// anchor below); around an anchor z^a, z^{a+1} takes one FP32 complex
+// multiplication and z^{a-1}, z^{a+2} one FMA per component from the
+// relation z^{k+1} + z^{k-1} = 2 cos(phi) z^k, so every p_m = z^m is at most
+// two FP32 steps from an anchor and its error a few FP32 ulp whatever m
+// (with chains of up to 4 steps, small tomographic samples reached the 1e-6
+// FP32 bar on single blocks).
 // G_m and G_{-m} share p_m:
 //     S1 += Re c Re p,  S2 += Im c Im p,  S3 += Re c Im p,  S4 += Im c Re p
 //     G_m = (S1 - S2, S3 + S4),   G_{-m} = (S1 + S2, S4 - S3)
@@ -138,41 +140,43 @@ __device__ __forceinline__ void accumulate(float (&acc)[V], int dx, int dy, floa
             acc[k + 1] = fmaf(wt, pi, acc[k + 1]);
         }
     };
-    // FP32 steps from a power (fr, fi) of order m0: forward up to order m0 + 2,
-    // or backward (z^-1 = conj z on the unit circle) down to order m0 - 1
-    auto up2 = [&](int m0, float fr, float fi) {
-#pragma unroll
-        for (int j = 1; j <= 2; ++j) {
-            if (m0 + j > S::MTOP) break;
-            const float tr = fmaf(fr, fzr, -fi * fzi);
-            fi = fmaf(fr, fzi, fi * fzr);
-            fr = tr;
-            add(m0 + j, fr, fi);
+    // Powers around an FP32 anchor f = z^a: z^{a+1} = f z by one complex
+    // multiplication, z^{a-1} and z^{a+2} from the three-term relation
+    // z^{k+1} + z^{k-1} = 2 cos(phi) z^k of a unit z (one FMA per component),
+    // each at most two steps from the anchor.  When the anchor is z^0 = 1,
+    // z^1 is z itself and z^2 the rounded FP64 square.
+    const float tc = 2.0f * fzr;
+    auto around = [&](int a, float fr, float fi, bool one) {
+        float ur = fzr, ui = fzi;
+        if (!one) {
+            ur = fmaf(fr, fzr, -fi * fzi);
+            ui = fmaf(fr, fzi, fi * fzr);
         }
+        add(a - 1, fmaf(tc, fr, -ur), fmaf(tc, fi, -ui));
+        add(a, fr, fi);
+        add(a + 1, ur, ui);
+        if (one)
+            add(a + 2, (float)z2r, (float)z2i);
+        else
+            add(a + 2, fmaf(tc, ur, -fr), fmaf(tc, ui, -fi));
     };
-    auto down1 = [&](int m0, float fr, float fi) {
-        if (m0 - 1 <= S::MTOP) add(m0 - 1, fmaf(fr, fzr, fi * fzi), fmaf(fi, fzr, -fr * fzi));
-    };
-    // Segments of 8 orders: the FP64 anchors a = z^{8k} form the only chain
-    // (one z^8 step per segment); z^{8k+4} = a z^4 is a second FP64 anchor of
-    // depth one; every other power is at most two FP32 multiplications from
-    // one of them (8k+1, 8k+2 forward from 8k; 8k+3 backward from 8k+4;
-    // 8k+5, 8k+6 forward from 8k+4; 8k+7 backward from 8k+8).
+    // Anchors every 4 orders: a = z^{8k} forms the only FP64 chain (one z^8
+    // step per 8 orders), z^{8k+4} = a z^4 hangs off it; anchor a covers
+    // orders a - 1 .. a + 2.
+    constexpr bool kUnit0 = SEG == 0 && S::M0 == 0;
 #pragma unroll
-    for (int b0 = S::M0; b0 < S::MTOP; b0 += kAnchor) {
-        up2(b0, (float)ar, (float)ai);
-        if (b0 + 2 >= S::MTOP) break;
-        const double hr = fma(ar, z4r, -ai * z4i), hi = fma(ar, z4i, ai * z4r);
-        const float fhr = (float)hr, fhi = (float)hi;
-        down1(b0 + 4, fhr, fhi);
-        if (b0 + 4 <= S::MTOP) add(b0 + 4, fhr, fhi);
-        up2(b0 + 4, fhr, fhi);
-        if (b0 + 6 >= S::MTOP) break;
-        const double nr = fma(ar, z8r, -ai * z8i), ni = fma(ar, z8i, ai * z8r);
+    for (int b0 = S::M0; b0 <= S::MTOP + 1; b0 += kAnchor) {
+        const bool one = kUnit0 && b0 == 0;
+        around(b0, one ? 1.0f : (float)ar, one ? 0.0f : (float)ai, one);
+        if (b0 + 3 > S::MTOP) break;
+        const double hr = one ? z4r : fma(ar, z4r, -ai * z4i);
+        const double hi = one ? z4i : fma(ar, z4i, ai * z4r);
+        around(b0 + 4, (float)hr, (float)hi, false);
+        if (b0 + 7 > S::MTOP) break;
+        const double nr = one ? z8r : fma(ar, z8r, -ai * z8i);
+        const double ni = one ? z8i : fma(ar, z8i, ai * z8r);
         ar = nr;
         ai = ni;
-        down1(b0 + 8, (float)ar, (float)ai);
-        if (b0 + 8 <= S::MTOP) add(b0 + 8, (float)ar, (float)ai);
     }
     if (EXTRA && with_extra) {
         constexpr int k = 4 * S::NG + 2 * S::NW;
