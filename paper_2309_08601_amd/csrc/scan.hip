@@ -61,6 +61,7 @@ struct ScanArgs {
     const short *dest;      // slot -> plane (or -1) for this pass
     unsigned long long *npairs;
     unsigned *queue;        // persistent mode: task counter (zeroed before launch); else null
+    int stage;              // single-catalog k_scan: totals staged in LDS, 4-centre rows stored at the end
     int grab;               // persistent mode: tasks taken per counter increment
     double e2[kMaxBins + 1];
 };
@@ -294,9 +295,12 @@ __device__ __forceinline__ void flush(float (&acc)[V], double (&accd)[P], int la
 }
 
 // Harmonic sums of one centre against one neighbour catalog, every bin.
+// stg (else null): the wavefront's column of the workgroup's LDS stage,
+// element (slot, bin) at stg[4 (slot n_bins + bin)]; the totals go there
+// instead of to the planes.
 template <int GA, int GB, int WA, int WB, bool EXTRA>
 __device__ __forceinline__ unsigned long long scan_task(const ScanArgs &a, int z, int ci, int lane,
-                                                        const SweepLDS &lds)
+                                                        const SweepLDS &lds, float *stg = nullptr)
 {
     using S = PassShape<GA, GB, WA, WB, EXTRA>;
     const int2 cp = a.cpos[ci];
@@ -339,11 +343,51 @@ __device__ __forceinline__ unsigned long long scan_task(const ScanArgs &a, int z
 #pragma unroll
         for (int k = 0; k < S::P; ++k) {
             const int slot = S::P * lane + k;
-            const int pl = a.dest[slot];
-            if (pl >= 0) out[chunk_offset(pl, ci, a.b_out0 + b, a.K, a.B_out)] = (float)accd[k];
+            if (stg) {
+                if (slot < S::V) stg[4 * (slot * a.n_bins + b)] = (float)accd[k];
+            } else {
+                const int pl = a.dest[slot];
+                if (pl >= 0) out[chunk_offset(pl, ci, a.b_out0 + b, a.K, a.B_out)] = (float)accd[k];
+            }
         }
     }
     return pairs;
+}
+
+// Store of a workgroup's staged totals: the last of its wavefronts to finish
+// writes, per plane, the row of 4 consecutive centres x n_bins bins, which is
+// contiguous in the plane layout, as 16-byte vectors (full rows instead of
+// 4-byte stores from four wavefronts at different times).  done: the
+// workgroup's LDS counter of finished wavefronts, zeroed before any finishes.
+template <int V>
+__device__ __forceinline__ void store_stage(const ScanArgs &a, int quad, int lane, const float4 *stage, int *done)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    int prev = 0;
+    if (lane == 0) prev = atomicAdd(done, 1);
+    prev = __shfl(prev, 0, 64);
+    const int rem = a.n_c - kWaves * quad;
+    const int nq = rem < kWaves ? rem : kWaves;  // centres of this workgroup
+    if (prev != nq - 1) return;                  // wave-uniform
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int nb = a.n_bins;
+    const int per = 64 / nb;  // slots per step
+    const int ds = lane / nb, b = lane - ds * nb;
+    if (ds >= per) return;
+    float *out = a.out[0];
+    for (int s = ds; s < V; s += per) {
+        const int pl = a.dest[s];
+        if (pl < 0) continue;
+        const float4 v = stage[s * nb + b];
+        float *o = out + chunk_offset(pl, kWaves * quad, a.b_out0 + b, a.K, a.B_out);
+        if (nq == kWaves) {
+            *reinterpret_cast<float4 *>(o) = v;
+        } else {
+            o[0] = v.x;
+            if (nq > 1) o[1] = v.y;
+            if (nq > 2) o[2] = v.z;
+        }
+    }
 }
 
 // Two workgroups per CU (2 wavefronts per SIMD): measured faster than one
@@ -361,16 +405,25 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
     __shared__ int2 spans[kWaves][2 * kRowsPerBlock + 1];
 
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: LDS bases stay scalar
     const SweepLDS lds{q_xyc[wv], q_wi[wv], spans[wv]};
     unsigned long long pairs = 0;
     if constexpr (!GENERAL) {
+        // a.stage: [V][n_bins] float4 of dynamic LDS, one float per wavefront
+        extern __shared__ float4 stage[];
+        __shared__ int done;
         const int nwg = gridDim.x;  // multiple of 8
         const int per = nwg >> 3;
         const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
         const int ci = wg * kWaves + wv;
+        if (a.stage) {
+            if (threadIdx.x == 0) done = 0;
+            __syncthreads();
+        }
         if (ci >= a.n_c) return;  // whole wavefront leaves together
-        pairs = scan_task<GA, GB, WA, WB, EXTRA>(a, 0, ci, lane, lds);
+        pairs = scan_task<GA, GB, WA, WB, EXTRA>(a, 0, ci, lane, lds,
+                                                 a.stage ? reinterpret_cast<float *>(stage) + wv : nullptr);
+        if (a.stage) store_stage<PassShape<GA, GB, WA, WB, EXTRA>::V>(a, wg, lane, stage, &done);
         if (lane == 0 && a.npairs) atomicAdd(a.npairs, pairs);
         return;
     }
@@ -496,7 +549,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan_seg(ScanArgs a)
     __shared__ int2 q_wi[kWaves][kRing];
     __shared__ int2 spans[kWaves][2 * kRowsPerBlock + 1];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: LDS bases stay scalar
     const SweepLDS lds{q_xyc[wv], q_wi[wv], spans[wv]};
     const int nwg = gridDim.x;  // multiple of 8
     const int per = nwg >> 3;
@@ -643,6 +696,18 @@ struct PassDesc {
     void (*kernel_general)(ScanArgs);  // n_z catalogs, either launch mode
     void (*kernel_lane)(ScanArgs);     // single catalog, one lane per centre (small bins)
 };
+
+// Accumulator slots of a pass (the V of its PassShape).
+inline int pass_slots(const PassDesc &p)
+{
+    const int NG = p.gb >= p.ga ? p.gb - p.ga + 1 : 0;
+    const int NW = p.wb >= p.wa ? p.wb - p.wa + 1 : 0;
+    return 4 * NG + 2 * NW + (p.extra ? 11 : 0);
+}
+
+// Dynamic LDS for staged totals: with the rings (about 16 KB) a workgroup
+// stays within 64 KB, two workgroups per CU.
+constexpr size_t kStageBytes = 46 * 1024;
 
 template <int GA, int GB, int WA, int WB, bool EXTRA>
 PassDesc make_pass()
@@ -934,15 +999,20 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
             hipLaunchKernelGGL(pd.kernel_general, dim3((unsigned)nwg), dim3(64 * kWaves), 0, s, a);
             T3_HIP_CHECK(hipGetLastError());
         } else {
-            // one launch of the single-catalog kernel per catalog, densest first
+            // one launch of the single-catalog kernel per catalog, densest first;
+            // the totals go through LDS when the workgroup's rows fit
             const int nwg1 = (((n_c + kWaves - 1) / kWaves) + 7) & ~7;
+            const size_t stage_bytes = sizeof(float4) * (size_t)pass_slots(pd) * (size_t)a.n_bins;
+            const bool stage = stage_bytes <= kStageBytes;
             for (int k = 0; k < n_z; ++k) {
                 ScanArgs a1 = a;
                 const int z = a.order[k];
                 a1.sw[0] = a.sw[z];
                 a1.out[0] = a.out[z];
                 a1.n_z = 1;
-                hipLaunchKernelGGL(pd.kernel, dim3((unsigned)nwg1), dim3(64 * kWaves), 0, s, a1);
+                a1.stage = stage ? 1 : 0;
+                hipLaunchKernelGGL(pd.kernel, dim3((unsigned)nwg1), dim3(64 * kWaves), stage ? stage_bytes : 0, s,
+                                   a1);
                 T3_HIP_CHECK(hipGetLastError());
             }
         }

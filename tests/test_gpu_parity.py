@@ -94,6 +94,30 @@ def test_harmonics_match_oracle(t3):
     assert np.array_equal(W1[:, :, 0].real.cpu().numpy().astype(np.float64), cnt)
 
 
+@pytest.mark.parametrize("nm,n_cent", [(10, 301), (10, 302), (30, 303), (30, 304)])
+def test_harmonics_wavefront_bins_ragged_quads(t3, nm, n_cent):
+    """Every bin on the one-wavefront-per-centre kernel (the lane threshold
+    set below any bin's expected count), whose workgroups of four centres
+    store their totals as four-centre rows: centre counts 1, 2, 3 and 0
+    mod 4, each plane and bin of every centre against the oracle."""
+    _, mp = _oracle()
+    cat = random_catalog(2500, 50.0, seed=900 + n_cent)
+    edges = np.geomspace(0.8, 14.0, 8)
+    lo, size = box_for(50.0)
+    plan = t3.Plan(edges, nm, box_lo=lo, box_size=size, lane_neighbours=1e-6)
+    idx = centre_sample(cat.n, n_cent, seed=n_cent)
+    G, W, D = plan.harmonics(t3.DeviceCatalog.from_catalog(cat), torch.from_numpy(idx).cuda())
+    h = mp.harmonics(cat.subset(idx), cat, edges, nm)
+    G = G.cpu().numpy().astype(np.complex128)
+    W = W.cpu().numpy().astype(np.complex128)
+    D = D.cpu().numpy().astype(np.complex128)
+    eg = np.abs(G - h["G"]).max() / np.abs(h["G"]).max()
+    ew = np.abs(W - h["W"][:, :, nm:]).max() / np.abs(h["W"][:, :, nm:]).max()
+    ed = np.abs(D - h["D"]).max() / np.abs(h["D"]).max()
+    print(f"n_max {nm}, {n_cent} centres: G {eg:.2e}, W {ew:.2e}, D {ed:.2e}", flush=True)
+    assert eg < 2e-6 and ew < 2e-6 and ed < 2e-6
+
+
 @pytest.mark.parametrize("nm", [0, 3, 10, 14, 20, 24, 30, 32, 48, 64])  # with 8, 12, 40 elsewhere: every compiled capacity
 def test_forward_small_orders(t3, nm):
     _, mp = _oracle()
