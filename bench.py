@@ -302,9 +302,24 @@ def main():
                           "rel_err_gamma_n_per_mu": [float(e_g[m].max()) for m in range(4)],
                           "rel_err_gamma_n_per_mu_n": [[float(f"{v:.3e}") for v in e_g[m]] for m in range(4)]}
             log(f"[bench] {prec}: max rel err Upsilon {e_u.max():.2e}, Gamma_n {e_g.max():.2e}")
+        out["split_at_1e-5"] = split_at_bar(errs, {q: split[q]["stage2_ms"] for q in split},
+                                            {q: split[q]["gemm_tflops"] for q in split})
         out["errors_vs_oracle"] = errs
         out["errors_vs_oracle"]["sample"] = f"{n_s} centres"
     print(json.dumps(out), flush=True)
+
+
+def split_at_bar(errs, stage2_ms, tflops):
+    """The split mode that carries the 1e-5 comparison: the fastest (stage-2
+    time) whose worst per-(mu, n) Gamma_n error on the oracle sample is at
+    most half the bar, so that another centre sample stays below it."""
+    ok = [p for p in stage2_ms if errs[p]["max_rel_err_gamma_n"] <= 0.5e-5]
+    if not ok:
+        return None
+    best = min(ok, key=lambda p: stage2_ms[p])
+    return {"mode": best, "stage2_ms": stage2_ms[best], "gemm_tflops": tflops[best],
+            "max_rel_err_gamma_n": errs[best]["max_rel_err_gamma_n"],
+            "rule": "fastest split mode whose worst Gamma_n error on the sample is at most half of 1e-5"}
 
 
 def cpu_model() -> str:
@@ -450,6 +465,9 @@ def bench_field_4m(t3, torch, dev, steps, with_oracle=True):
             log(f"[bench] field_4m {prec}: max rel err Upsilon {e_u.max():.2e}, Gamma_n {e_g.max():.2e}")
             del p
         res["errors_vs_oracle"] = errs
+        timed = [q for q in ("bf16x3", "bf16x6", "fp16x3") if q in res]
+        res["split_at_1e-5"] = split_at_bar(errs, {q: res[q]["stage_ms_per_step"]["stage2_contract"] for q in timed},
+                                            {q: res[q]["gemm_tflops"] for q in timed})
     return res
 
 
@@ -465,7 +483,7 @@ def bench_tomo(t3, torch, dev):
     box = int(round(wl.side / LATTICE_UNIT))
     plan = t3.Plan(wl.edges(), wl.n_max, box_size=box)
     t0 = time.perf_counter()
-    tune_ms = plan.autotune(dcs, sample_per_bin=4000)
+    tune_ms = plan.autotune(dcs, sample_per_bin=16000)
     t_tune = time.perf_counter() - t0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -480,7 +498,7 @@ def bench_tomo(t3, torch, dev):
     tuned = plan.settings()
     # eager run with HIP events for the stage split
     tp = t3.Plan(wl.edges(), wl.n_max, box_size=box, timing=True, cell_arcmin=0.0)
-    tp.autotune(dcs, sample_per_bin=4000)  # cached choice, no timing
+    tp.autotune(dcs, sample_per_bin=16000)  # cached choice, no timing
     _, np2 = tp.forward_tomo(dcs)
     ms, nl = tp.stage_times()
     # the other stage-1 launch mode at the tuned settings (persistent work
