@@ -79,47 +79,67 @@ struct PassShape {
     static constexpr int MTOP = GB > WB ? GB : WB;
 };
 
-// One neighbour through the recurrence.  acc layout: [4*NG S-sums][2*NW W][NX extras]
-// SEG > 0 (order segments, see k_scan_seg): when upper is set the orders are
-// SEG + GA .. SEG + GB (the chain starts from the FP64 power z^SEG), else GA .. GB.
-template <int GA, int GB, int WA, int WB, bool EXTRA, int V, int SEG = 0>
-__device__ __forceinline__ void accumulate(float (&acc)[V], int dx, int dy, float cr, float ci,
-                                           float wt, bool upper = false, bool with_extra = true)
+// FP64 powers z, z^2, z^4, z^8 of the unit vector z = (dx + i dy) / r.
+struct ZPowers {
+    double r1, i1, r2, i2, r4, i4, r8, i8;
+};
+
+__device__ __forceinline__ ZPowers z_powers(int dx, int dy)
 {
-    using S = PassShape<GA, GB, WA, WB, EXTRA>;
-    static_assert(V == S::V, "accumulator size");
     const double xd = (double)dx, yd = (double)dy;
     const double r2 = fma(xd, xd, yd * yd);
     double s = (double)__builtin_amdgcn_rsqf((float)r2);
     s = s * fma(-0.5 * r2 * s, s, 1.5);
-    const double zr = xd * s, zi = yd * s;
-    const float fzr = (float)zr, fzi = (float)zi;
-    // z^2, z^4, z^8 in FP64
-    const double z2r = fma(zr, zr, -zi * zi), z2i = 2.0 * zr * zi;
-    const double z4r = fma(z2r, z2r, -z2i * z2i), z4i = 2.0 * z2r * z2i;
-    const double z8r = fma(z4r, z4r, -z4i * z4i), z8i = 2.0 * z4r * z4i;
-    // running FP64 anchor a = z^{M0} (times z^SEG for the upper segment)
-    double ar = 1.0, ai = 0.0;
-    if constexpr (SEG > 0) {
-        static_assert(S::M0 == 0 && SEG < 64, "segments start at order 1");
-        // z^SEG from the binary powers z, z^2, z^4, ... (FP64)
-        double pr = zr, pi = zi, br = 1.0, bi = 0.0;
+    ZPowers z;
+    z.r1 = xd * s;
+    z.i1 = yd * s;
+    z.r2 = fma(z.r1, z.r1, -z.i1 * z.i1);
+    z.i2 = 2.0 * z.r1 * z.i1;
+    z.r4 = fma(z.r2, z.r2, -z.i2 * z.i2);
+    z.i4 = 2.0 * z.r2 * z.i2;
+    z.r8 = fma(z.r4, z.r4, -z.i4 * z.i4);
+    z.i8 = 2.0 * z.r4 * z.i4;
+    return z;
+}
+
+// z^E (0 < E < 64) from the binary powers z, z^2, z^4, ... (FP64).
+template <int E>
+__device__ __forceinline__ void z_power(const ZPowers &z, double &br, double &bi)
+{
+    static_assert(E > 0 && E < 64, "exponent range");
+    double pr = z.r1, pi = z.i1;
+    br = 1.0;
+    bi = 0.0;
 #pragma unroll
-        for (int bit = 0; (1 << bit) <= SEG; ++bit) {
-            if (SEG & (1 << bit)) {
-                const double tr = fma(br, pr, -bi * pi);
-                bi = fma(br, pi, bi * pr);
-                br = tr;
-            }
-            if ((2 << bit) <= SEG) {
-                const double qr = fma(pr, pr, -pi * pi);
-                pi = 2.0 * pr * pi;
-                pr = qr;
-            }
+    for (int bit = 0; (1 << bit) <= E; ++bit) {
+        if (E & (1 << bit)) {
+            const double tr = fma(br, pr, -bi * pi);
+            bi = fma(br, pi, bi * pr);
+            br = tr;
         }
-        ar = upper ? br : 1.0;
-        ai = upper ? bi : 0.0;
+        if ((2 << bit) <= E) {
+            const double qr = fma(pr, pr, -pi * pi);
+            pi = 2.0 * pr * pi;
+            pr = qr;
+        }
     }
+}
+
+// One neighbour through the recurrence, from its FP64 powers z and the FP64
+// base (ar, ai) of the orders: the orders GA .. GB are taken as the powers
+// base * z^m (base 1 for the plain passes, z^SEG for the upper order segment;
+// UNIT0: the base is 1 at compile time).
+// acc layout: [4*NG S-sums][2*NW W][NX extras]
+template <int GA, int GB, int WA, int WB, bool EXTRA, int V, bool UNIT0>
+__device__ __forceinline__ void accumulate_z(float (&acc)[V], const ZPowers &zp, double ar, double ai, float cr,
+                                             float ci, float wt, bool with_extra)
+{
+    using S = PassShape<GA, GB, WA, WB, EXTRA>;
+    static_assert(V == S::V, "accumulator size");
+    const double zr = zp.r1, zi = zp.i1, z2r = zp.r2, z2i = zp.i2, z4r = zp.r4, z4i = zp.i4, z8r = zp.r8,
+                 z8i = zp.i8;
+    const float fzr = (float)zr, fzi = (float)zi;
+    // running FP64 anchor a = base z^{M0}
 #pragma unroll
     for (int k = 0; k < S::M0 / kAnchor; ++k) {
         const double tr = fma(ar, z8r, -ai * z8i);
@@ -164,7 +184,7 @@ __device__ __forceinline__ void accumulate(float (&acc)[V], int dx, int dy, floa
     // Anchors every 4 orders: a = z^{8k} forms the only FP64 chain (one z^8
     // step per 8 orders), z^{8k+4} = a z^4 hangs off it; anchor a covers
     // orders a - 1 .. a + 2.
-    constexpr bool kUnit0 = SEG == 0 && S::M0 == 0;
+    constexpr bool kUnit0 = UNIT0 && S::M0 == 0;
 #pragma unroll
     for (int b0 = S::M0; b0 <= S::MTOP + 1; b0 += kAnchor) {
         const bool one = kUnit0 && b0 == 0;
@@ -203,6 +223,25 @@ __device__ __forceinline__ void accumulate(float (&acc)[V], int dx, int dy, floa
         // DW += w^2
         acc[k + 10] = fmaf(wt, wt, acc[k + 10]);
     }
+}
+
+// One neighbour (dx, dy, c = cr + i ci, weight wt) through the recurrence.
+// SEG > 0 (order segments, see k_scan_seg): when upper is set the orders are
+// SEG + GA .. SEG + GB (the chain starts from the FP64 power z^SEG), else GA .. GB.
+template <int GA, int GB, int WA, int WB, bool EXTRA, int V, int SEG = 0>
+__device__ __forceinline__ void accumulate(float (&acc)[V], int dx, int dy, float cr, float ci,
+                                           float wt, bool upper = false, bool with_extra = true)
+{
+    const ZPowers z = z_powers(dx, dy);
+    double ar = 1.0, ai = 0.0;
+    if constexpr (SEG > 0) {
+        static_assert(GA == 1, "segments start at order 1");
+        double br, bi;
+        z_power<SEG>(z, br, bi);
+        ar = upper ? br : 1.0;
+        ai = upper ? bi : 0.0;
+    }
+    accumulate_z<GA, GB, WA, WB, EXTRA, V, SEG == 0>(acc, z, ar, ai, cr, ci, wt, with_extra);
 }
 
 // Cross-lane exchange steps of the reduce-scatter.  Each step halves the
@@ -493,8 +532,12 @@ __device__ __forceinline__ void flush_half(float (&acc)[V], double (&accd)[P], i
     for (int k = 0; k < V; ++k) acc[k] = 0.0f;
 }
 
+// zp: the wavefront's LDS table of the batch entries' FP64 powers, [5][64]:
+// z, z^2, z^4, z^8 and z^SW of entry j at zp[q][j] (computed once per entry,
+// read by the lower-half and the upper-half lane that take it).
 template <int SW>
-__device__ __forceinline__ unsigned long long scan_task_seg(const ScanArgs &a, int ci, int lane, const SweepLDS &lds)
+__device__ __forceinline__ unsigned long long scan_task_seg(const ScanArgs &a, int ci, int lane, const SweepLDS &lds,
+                                                            double2 (*zp)[64])
 {
     using S = PassShape<1, SW, 1, SW, true>;
     constexpr int P = (S::V + 31) / 32;   // slots per lane after the half-wave reduction
@@ -513,9 +556,23 @@ __device__ __forceinline__ unsigned long long scan_task_seg(const ScanArgs &a, i
         for (int k = 0; k < P; ++k) accd[k] = 0.0;
         int batches = 0;  // wave-uniform
         pairs += (unsigned long long)sweep_annulus_halves(
-            a.sw[0], cp, a.e2[b], a.e2[b + 1], lane, lds, [&](const int4 &e, float ew, int step) {
-                accumulate<1, SW, 1, SW, true, S::V, SW>(acc, e.x, e.y, __int_as_float(e.z),
-                                                         __int_as_float(e.w), ew, upper, step == 0);
+            a.sw[0], cp, a.e2[b], a.e2[b + 1], lane, lds,
+            [&](const int4 &e, int j) {
+                const ZPowers z = z_powers(e.x, e.y);
+                double br, bi;
+                z_power<SW>(z, br, bi);
+                zp[0][j] = make_double2(z.r1, z.i1);
+                zp[1][j] = make_double2(z.r2, z.i2);
+                zp[2][j] = make_double2(z.r4, z.i4);
+                zp[3][j] = make_double2(z.r8, z.i8);
+                zp[4][j] = make_double2(br, bi);
+            },
+            [&](const int4 &e, float ew, int step, int j) {
+                const double2 p1 = zp[0][j], p2 = zp[1][j], p4 = zp[2][j], p8 = zp[3][j], pb = zp[4][j];
+                const ZPowers z{p1.x, p1.y, p2.x, p2.y, p4.x, p4.y, p8.x, p8.y};
+                accumulate_z<1, SW, 1, SW, true, S::V, false>(acc, z, upper ? pb.x : 1.0, upper ? pb.y : 0.0,
+                                                              __int_as_float(e.z), __int_as_float(e.w), ew,
+                                                              step == 0);
             },
             [&]() {
                 // two neighbours per lane per batch: FP32 runs of at most 64 terms
@@ -548,6 +605,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan_seg(ScanArgs a)
     __shared__ int4 q_xyc[kWaves][kRing];
     __shared__ int2 q_wi[kWaves][kRing];
     __shared__ int2 spans[kWaves][2 * kRowsPerBlock + 1];
+    __shared__ double2 zpow[kWaves][5][64];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: LDS bases stay scalar
     const SweepLDS lds{q_xyc[wv], q_wi[wv], spans[wv]};
@@ -556,7 +614,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan_seg(ScanArgs a)
     const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     const int ci = wg * kWaves + wv;
     if (ci >= a.n_c) return;  // whole wavefront leaves together
-    const unsigned long long pairs = scan_task_seg<SW>(a, ci, lane, lds);
+    const unsigned long long pairs = scan_task_seg<SW>(a, ci, lane, lds, zpow[wv]);
     if (lane == 0 && a.npairs) atomicAdd(a.npairs, pairs);
 }
 

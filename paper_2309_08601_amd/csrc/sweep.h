@@ -225,15 +225,22 @@ __device__ __forceinline__ int sweep_annulus(const SweepArgs &a, int2 cp, double
 // Sweep one annulus, every half-wave (lanes 0-31, 32-63) taking all pending
 // neighbours of a batch in two steps: in step 0 a lower-half lane gets entry
 // (lane & 31) and an upper-half lane entry 32 + (lane & 31), in step 1 the
-// other one; item(e, ew, step) is called for each, then done() once per
-// batch.  Inactive entries as in sweep_annulus.
-template <class Item, class Done>
+// other one.  Per batch, prep(e, j) is first called with each lane's own
+// entry j = lane (for per-entry values in the caller's wavefront-private
+// LDS, visible to every lane afterwards), then item(e, ew, step, j) for each
+// step, then done() once.  Inactive entries as in sweep_annulus.
+template <class Prep, class Item, class Done>
 __device__ __forceinline__ int sweep_annulus_halves(const SweepArgs &a, int2 cp, double e2lo, double e2hi,
-                                                    int lane, const SweepLDS &L, Item &&item, Done &&done)
+                                                    int lane, const SweepLDS &L, Prep &&prep, Item &&item,
+                                                    Done &&done)
 {
     return sweep_core(
         a, cp, e2lo, e2hi, lane, L,
         [&](int head, int count) {
+            int4 e0 = L.q_xyc[(head + lane) & (kRing - 1)];
+            if (lane >= count) e0 = make_int4(1, 0, 0, 0);
+            prep(e0, lane);
+            wave_sync_lds();
 #pragma unroll 1
             for (int k = 0; k < 2; ++k) {
                 const int j = (((lane >> 5) ^ k) << 5) + (lane & 31);
@@ -245,7 +252,7 @@ __device__ __forceinline__ int sweep_annulus_halves(const SweepArgs &a, int2 cp,
                     e = make_int4(1, 0, 0, 0);
                     ew = make_int2(0, 0);
                 }
-                item(e, __int_as_float(ew.x), k);
+                item(e, __int_as_float(ew.x), k, j);
             }
             done();
         },
