@@ -18,9 +18,9 @@
 // Arithmetic per neighbour: dx, dy are exact lattice integers, r^2 is exact
 // in FP64 and is compared with the same FP64 squared edges as everywhere
 // else, so bin membership is exact.  z is formed in FP64 (rsqrt seed + one
-// Newton step), anchors z^{4k} are FP64 and rounded once to FP32 (those at
-// multiples of 8 form the only dependency chain, each z^{8k+4} hangs off the
-// anchor below); around an anchor z^a, z^{a+1} takes one FP32 complex
+// Newton step), anchors z^{4k} are FP64 and rounded once to FP32 (z^4 by
+// squaring, then the three-term relation Z_{k+1} = 2 cos(4 phi) Z_k - Z_{k-1},
+// two FMAs per anchor); around an anchor z^a, z^{a+1} takes one FP32 complex
 // multiplication and z^{a-1}, z^{a+2} one FMA per component from the
 // relation z^{k+1} + z^{k-1} = 2 cos(phi) z^k, so every p_m = z^m is at most
 // two FP32 steps from an anchor and its error a few FP32 ulp whatever m
@@ -38,7 +38,7 @@ namespace t3 {
 namespace {
 
 constexpr int kWaves = 4;       // wavefronts (centres) per workgroup
-constexpr int kAnchor = 8;      // FP64 anchor chain stride of the power recurrence
+constexpr int kAnchor = 8;      // z^8 steps from the base to the first anchor of a pass above order 8
 constexpr int kMaxBins = kMaxRadialBins;
 constexpr int kMaxZ = 8;        // neighbour catalogs per launch (tomographic bins)
 constexpr int kFlush = 64;      // batches of 64 neighbours per FP32 run before FP64 promotion
@@ -181,23 +181,32 @@ __device__ __forceinline__ void accumulate_z(float (&acc)[V], const ZPowers &zp,
         else
             add(a + 2, fmaf(tc, ur, -fr), fmaf(tc, ui, -fi));
     };
-    // Anchors every 4 orders: a = z^{8k} forms the only FP64 chain (one z^8
-    // step per 8 orders), z^{8k+4} = a z^4 hangs off it; anchor a covers
-    // orders a - 1 .. a + 2.
+    // FP64 anchors Z_j = a z^{M0 + 4j} (a the base) at every fourth order,
+    // each covering orders M0 + 4j - 1 .. M0 + 4j + 2: Z_1 = Z_0 z^4, then
+    // the three-term relation Z_{j+1} = 2 cos(4 phi) Z_j - Z_{j-1} (two FMAs
+    // per anchor; in FP64 it adds at most about j^2 FP64 ulp, far below one
+    // FP32 ulp at any order used here).
     constexpr bool kUnit0 = UNIT0 && S::M0 == 0;
+    const double t4 = 2.0 * z4r;
+    double cr0 = ar, ci0 = ai, pr0 = 0.0, pi0 = 0.0;
 #pragma unroll
-    for (int b0 = S::M0; b0 <= S::MTOP + 1; b0 += kAnchor) {
-        const bool one = kUnit0 && b0 == 0;
-        around(b0, one ? 1.0f : (float)ar, one ? 0.0f : (float)ai, one);
-        if (b0 + 3 > S::MTOP) break;
-        const double hr = one ? z4r : fma(ar, z4r, -ai * z4i);
-        const double hi = one ? z4i : fma(ar, z4i, ai * z4r);
-        around(b0 + 4, (float)hr, (float)hi, false);
-        if (b0 + 7 > S::MTOP) break;
-        const double nr = one ? z8r : fma(ar, z8r, -ai * z8i);
-        const double ni = one ? z8i : fma(ar, z8i, ai * z8r);
-        ar = nr;
-        ai = ni;
+    for (int j = 0; S::M0 + 4 * j <= S::MTOP + 1; ++j) {
+        const int a0 = S::M0 + 4 * j;
+        const bool one = kUnit0 && j == 0;
+        around(a0, one ? 1.0f : (float)cr0, one ? 0.0f : (float)ci0, one);
+        if (a0 + 3 > S::MTOP) break;
+        double nr, ni;
+        if (j == 0) {
+            nr = one ? z4r : fma(cr0, z4r, -ci0 * z4i);
+            ni = one ? z4i : fma(cr0, z4i, ci0 * z4r);
+        } else {
+            nr = fma(t4, cr0, -pr0);
+            ni = fma(t4, ci0, -pi0);
+        }
+        pr0 = cr0;
+        pi0 = ci0;
+        cr0 = nr;
+        ci0 = ni;
     }
     if (EXTRA && with_extra) {
         constexpr int k = 4 * S::NG + 2 * S::NW;
