@@ -153,10 +153,16 @@ int choose_chunk(const t3_plan *plan, const ChunkLayout &L)
         // stage-1 workgroups (512 resident, 4 centres each), so fewer,
         // longer launches waste less (measured on the 1M field: 8.7k centres
         // per chunk 1125 ms of stage 1, 64k centres 994 ms).  About 1 GiB of
-        // planes per catalog, at most 64k centres, whole rounds of 2048.
+        // planes per catalog, at most 64k centres, whole rounds of 2048: the
+        // n_max = 30 pass measured 4% slower with 4 GiB chunks (262k
+        // centres).  The order-segment pass, whose centres take about four
+        // times longer each, gains from 4 GiB (4M field, n_max = 40: 139k
+        // centres per chunk 4.5% faster than 35k).  Stage 2 addresses a
+        // catalog's planes with 32-bit float offsets: below 2^30 floats here.
+        const bool seg = scan_uses_segments(plan);
         const double per_centre = (double)L.n_planes() * L.B * sizeof(float);
-        K = (int)(1024.0 * 1024 * 1024 / per_centre);
-        if (K > 65536) K = 65536;
+        K = (int)((seg ? 4.0 : 1.0) * 1024 * 1024 * 1024 / per_centre);
+        if (K > (seg ? 262144 : 65536)) K = seg ? 262144 : 65536;
         K = K >= 2048 ? (K & ~2047) : K;
     }
     if (K < 256) K = 256;

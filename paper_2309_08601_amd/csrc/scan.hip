@@ -945,6 +945,13 @@ int dest_tables(const t3_plan *plan, std::vector<short> &all, size_t off[4], int
 }
 }  // namespace
 
+bool scan_uses_segments(const t3_plan *plan)
+{
+    for (const Variant &v : variants())
+        if (v.cap >= plan->n_max) return v.kernel_seg != nullptr;
+    return false;
+}
+
 size_t scan_dest_entries(const t3_plan *plan)
 {
     std::vector<short> all;

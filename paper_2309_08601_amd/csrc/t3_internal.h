@@ -240,6 +240,9 @@ int gather_sorted_centres(t3_plan *plan, const SortedCatalog &sc, CentreSet &cs,
 int check_flag(t3_plan *plan, hipStream_t s, const char *what);
 
 int scan_prepare(t3_plan *plan);
+// Whether the plan's stage-1 variant sweeps each annulus once for two order
+// segments (k_scan_seg: n_max above one pass, up to 48).
+bool scan_uses_segments(const t3_plan *plan);
 // Stage 1 for centres [c0, c0 + n_c) of cs against n_z neighbour catalogs
 // (planes of catalog z at planes + z * zstride).  mode 0: one wavefront per
 // centre, one launch per catalog; mode 1: one persistent launch over every
