@@ -41,6 +41,7 @@ constexpr int kWaves = 4;       // wavefronts (centres) per workgroup
 constexpr int kAnchor = 8;      // z^8 steps from the base to the first anchor of a pass above order 8
 constexpr int kMaxBins = kMaxRadialBins;
 constexpr int kMaxZ = 8;        // neighbour catalogs per launch (tomographic bins)
+constexpr int kPartials = 4;   // FP64 partial slots per lane (the P of every plain pass)
 constexpr int kFlush = 64;      // batches of 64 neighbours per FP32 run before FP64 promotion
 
 // One launch covers the centres of a chunk against n_z neighbour catalogs
@@ -314,8 +315,11 @@ constexpr bool kConvertAfter = PassShape<GA, GB, WA, WB, EXTRA>::P % 2 == 0;
 // waits for the totals, then the 6-step reduce-scatter above, after which
 // lane l holds the wave totals of slots [P l, P l + P).  These are added to
 // the lane's FP64 partials and the FP32 accumulators restart from zero.
-template <int GA, int GB, int WA, int WB, bool EXTRA, int V, int P>
-__device__ __forceinline__ void flush(float (&acc)[V], double (&accd)[P], int lane)
+// accl: the wavefront's FP64 partials in LDS, slot k of lane l at
+// accl[64 k + l] (in LDS rather than registers: the FP32 accumulators of
+// the larger passes already fill the register file).
+template <int GA, int GB, int WA, int WB, bool EXTRA, int V>
+__device__ __forceinline__ void flush(float (&acc)[V], double *accl, int lane)
 {
     using S = PassShape<GA, GB, WA, WB, EXTRA>;
     constexpr int VP = S::VP;
@@ -337,7 +341,7 @@ __device__ __forceinline__ void flush(float (&acc)[V], double (&accd)[P], int la
     dpp_step<kDppQuadXor2, VP / 32>(v, (lane & 2) != 0);
     dpp_step<kDppQuadXor1, VP / 64>(v, (lane & 1) != 0);
 #pragma unroll
-    for (int k = 0; k < S::P; ++k) accd[k] += (double)v[k];
+    for (int k = 0; k < S::P; ++k) accl[64 * k + lane] += (double)v[k];
 #pragma unroll
     for (int k = 0; k < S::V; ++k) acc[k] = 0.0f;
 }
@@ -348,7 +352,7 @@ __device__ __forceinline__ void flush(float (&acc)[V], double (&accd)[P], int la
 // instead of to the planes.
 template <int GA, int GB, int WA, int WB, bool EXTRA>
 __device__ __forceinline__ unsigned long long scan_task(const ScanArgs &a, int z, int ci, int lane,
-                                                        const SweepLDS &lds, float *stg = nullptr)
+                                                        const SweepLDS &lds, double *accl, float *stg = nullptr)
 {
     using S = PassShape<GA, GB, WA, WB, EXTRA>;
     const int2 cp = a.cpos[ci];
@@ -358,9 +362,9 @@ __device__ __forceinline__ unsigned long long scan_task(const ScanArgs &a, int z
         float acc[S::V];
 #pragma unroll
         for (int k = 0; k < S::V; ++k) acc[k] = 0.0f;
-        double accd[S::P];
+        static_assert(S::P <= kPartials, "FP64 partial slots");
 #pragma unroll
-        for (int k = 0; k < S::P; ++k) accd[k] = 0.0;
+        for (int k = 0; k < S::P; ++k) accl[64 * k + lane] = 0.0;
         int batches = 0;  // wave-uniform: batches since the last FP64 promotion
 
         pairs += (unsigned long long)sweep_annulus(
@@ -369,11 +373,14 @@ __device__ __forceinline__ unsigned long long scan_task(const ScanArgs &a, int z
                 accumulate<GA, GB, WA, WB, EXTRA>(acc, e.x, e.y, __int_as_float(e.z),
                                                   __int_as_float(e.w), ew);
                 if (++batches == kFlush) {
-                    flush<GA, GB, WA, WB, EXTRA>(acc, accd, lane);
+                    flush<GA, GB, WA, WB, EXTRA>(acc, accl, lane);
                     batches = 0;
                 }
             });
-        if (batches > 0) flush<GA, GB, WA, WB, EXTRA>(acc, accd, lane);
+        if (batches > 0) flush<GA, GB, WA, WB, EXTRA>(acc, accl, lane);
+        double accd[S::P];
+#pragma unroll
+        for (int k = 0; k < S::P; ++k) accd[k] = accl[64 * k + lane];
         if constexpr (kConvertAfter<GA, GB, WA, WB, EXTRA>) {
             // slot pairs (2j, 2j + 1) of an order pair are (S1, S2) or (S3, S4)
 #pragma unroll
@@ -451,10 +458,12 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
     __shared__ int4 q_xyc[kWaves][kRing];
     __shared__ int2 q_wi[kWaves][kRing];
     __shared__ int2 spans[kWaves][2 * kRowsPerBlock + 1];
+    __shared__ double partials[kWaves][64 * kPartials];
 
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: LDS bases stay scalar
     const SweepLDS lds{q_xyc[wv], q_wi[wv], spans[wv]};
+    double *accl = partials[wv];
     unsigned long long pairs = 0;
     if constexpr (!GENERAL) {
         // a.stage: [V][n_bins] float4 of dynamic LDS, one float per wavefront
@@ -469,7 +478,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
             __syncthreads();
         }
         if (ci >= a.n_c) return;  // whole wavefront leaves together
-        pairs = scan_task<GA, GB, WA, WB, EXTRA>(a, 0, ci, lane, lds,
+        pairs = scan_task<GA, GB, WA, WB, EXTRA>(a, 0, ci, lane, lds, accl,
                                                  a.stage ? reinterpret_cast<float *>(stage) + wv : nullptr);
         if (a.stage) store_stage<PassShape<GA, GB, WA, WB, EXTRA>::V>(a, wg, lane, stage, &done);
         if (lane == 0 && a.npairs) atomicAdd(a.npairs, pairs);
@@ -497,7 +506,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
         }
         if (base >= total) break;  // wave-uniform
         for (int t = base; t < end; ++t)
-            pairs += scan_task<GA, GB, WA, WB, EXTRA>(a, a.order[t / a.n_c], t % a.n_c, lane, lds);
+            pairs += scan_task<GA, GB, WA, WB, EXTRA>(a, a.order[t / a.n_c], t % a.n_c, lane, lds, accl);
         if (!a.queue) break;
     }
     if (lane == 0 && a.npairs) atomicAdd(a.npairs, pairs);
@@ -772,9 +781,9 @@ inline int pass_slots(const PassDesc &p)
     return 4 * NG + 2 * NW + (p.extra ? 11 : 0);
 }
 
-// Dynamic LDS for staged totals: with the rings (about 16 KB) a workgroup
-// stays within 64 KB, two workgroups per CU.
-constexpr size_t kStageBytes = 46 * 1024;
+// Dynamic LDS for staged totals: with the rings and the FP64 partials
+// (about 24 KB) a workgroup stays within 64 KB, two workgroups per CU.
+constexpr size_t kStageBytes = 38 * 1024;
 
 template <int GA, int GB, int WA, int WB, bool EXTRA>
 PassDesc make_pass()
