@@ -46,7 +46,6 @@ namespace t3 {
 namespace {
 
 constexpr int kWaves = 4;
-constexpr int kAnchor = 8;
 
 // Coefficient block of one (centre, bin) for a compiled order capacity C:
 //   [0, 4M)       m = 1..M (M = C + 3): s_m re, s_m im, d_m re, d_m im
@@ -361,24 +360,11 @@ __device__ __forceinline__ void pair_grad(const float *c, int dx, int dy, float 
     const float fzr = (float)zr, fzi = (float)zi;
     const double z2r = fma(zr, zr, -zi * zi), z2i = 2.0 * zr * zi;
     const double z4r = fma(z2r, z2r, -z2i * z2i), z4i = 2.0 * z2r * z2i;
-    const double z8r = fma(z4r, z4r, -z4i * z4i), z8i = 2.0 * z4r * z4i;
-    double ar = 1.0, ai = 0.0;
-    float pr = 1.0f, pi = 0.0f;
     float gr = c[4 * M], gim = c[4 * M + 1];  // Gb_0
     float gw = c[4 * M + 2];                   // Re Wb_0
-#pragma unroll
-    for (int m = 1; m <= M; ++m) {
-        if (m % kAnchor == 0) {
-            const double tr = fma(ar, z8r, -ai * z8i);
-            ai = fma(ar, z8i, ai * z8r);
-            ar = tr;
-            pr = (float)ar;
-            pi = (float)ai;
-        } else {
-            const float tr = fmaf(pr, fzr, -pi * fzi);
-            pi = fmaf(pr, fzi, pi * fzr);
-            pr = tr;
-        }
+    // the terms of order m with the power (pr, pi) = z^m
+    auto term = [&](int m, float pr, float pi) {
+        if (m < 1 || m > M) return;
         const float4 sd = *reinterpret_cast<const float4 *>(c + 4 * (m - 1));
         gr = fmaf(pr, sd.x, fmaf(pi, sd.z, gr));
         gim = fmaf(pr, sd.y, fmaf(pi, sd.w, gim));
@@ -386,6 +372,45 @@ __device__ __forceinline__ void pair_grad(const float *c, int dx, int dy, float 
             const float2 wb = *reinterpret_cast<const float2 *>(c + 4 * M + 2 + 2 * m);
             gw = fmaf(pr, wb.x, fmaf(pi, wb.y, gw));
         }
+    };
+    // Powers as in the forward scan: FP64 anchors Z_k = z^{4k} (z^4 by
+    // squaring, then Z_{k+1} = 2 cos(4 phi) Z_k - Z_{k-1}) rounded once to
+    // FP32; around an anchor z^a, z^{a+1} = z^a z by one FP32 complex
+    // multiplication and z^{a-1}, z^{a+2} from z^{k+1} + z^{k-1} = 2 cos(phi) z^k.
+    const float tc = 2.0f * fzr;
+    const double t4 = 2.0 * z4r;
+    double cr0 = 1.0, ci0 = 0.0, pr0 = 0.0, pi0 = 0.0;
+#pragma unroll
+    for (int k = 0; 4 * k <= M + 1; ++k) {
+        const int a0 = 4 * k;
+        float fr = (float)cr0, fi = (float)ci0, ur = fzr, ui = fzi;
+        if (k == 0) {
+            fr = 1.0f;
+            fi = 0.0f;
+        } else {
+            ur = fmaf(fr, fzr, -fi * fzi);
+            ui = fmaf(fr, fzi, fi * fzr);
+        }
+        term(a0 - 1, fmaf(tc, fr, -ur), fmaf(tc, fi, -ui));
+        term(a0, fr, fi);
+        term(a0 + 1, ur, ui);
+        if (k == 0)
+            term(2, (float)z2r, (float)z2i);
+        else
+            term(a0 + 2, fmaf(tc, ur, -fr), fmaf(tc, ui, -fi));
+        if (a0 + 3 > M) break;
+        double nr, ni;
+        if (k == 0) {
+            nr = z4r;
+            ni = z4i;
+        } else {
+            nr = fma(t4, cr0, -pr0);
+            ni = fma(t4, ci0, -pi0);
+        }
+        pr0 = cr0;
+        pi0 = ci0;
+        cr0 = nr;
+        ci0 = ni;
     }
     if (jk) {
         const int o = 4 * M + 2 + 2 * (C + 1);
