@@ -124,6 +124,9 @@ typedef struct {
     int64_t box_size;      /* side in lattice steps, > 0, box_lo + size <= 2^31 */
     double cell_arcmin;    /* spatial-hash cell side; 0 -> automatic          */
     int32_t chunk_centres; /* centres per stage-1/stage-2 chunk; 0 -> auto    */
+                           /* (about 1 GiB of planes per catalog, at most     */
+                           /* 65,536 centres; 4 GiB and 262,144 for n_max 40  */
+                           /* and 48)                                          */
     int32_t scan_mode;     /* stage-1 launch: 0 one wavefront per centre, one */
                            /* launch per neighbour catalog; 1 one persistent  */
                            /* launch over all (centre, catalog) tasks with a  */
@@ -420,7 +423,9 @@ int t3_backward(t3_plan *plan, const t3_catalog *cat, const int32_t *centres, in
  * lane sums; skipped with T3_FLAG_NO_LANE); for B <= 24 the stage-2 tile
  * shape (real-embedded 16 x 16 or complex 32 x 32 MFMA tiles); and, when
  * the plan's chunk capacity is automatic, 1, 1/2 or 1/4 of the automatic
- * capacity.  Each candidate is timed twice (best kept); ties keep the
+ * capacity (a capacity at or above the sample's centres per catalog runs
+ * the sample as one chunk, like the automatic one, and is not tried).
+ * Each candidate is timed twice (best kept); ties keep the
  * earlier one.  The choice is cached per process, keyed by (n_bins, n_max,
  * n_z, precision, catalog-size class, box, sample_per_bin, requested chunk
  * capacity); a cached choice is applied without timing.  best_ms (HOST,
