@@ -12,8 +12,10 @@
 //  * per-lane FP32 accumulators hold one bin of one centre; every 64 batches
 //    and at the end of the bin a 6-step reduce-scatter (permlane swaps and
 //    DPP permutations) leaves each lane a few wave totals, which are added to
-//    per-lane FP64 partials; at the end of the bin those are stored into the
-//    chunk planes (layout in t3_internal.h).
+//    the wavefront's FP64 partials (in LDS); at the end of the bin those are
+//    stored into the chunk planes (layout in t3_internal.h) -- in the
+//    single-catalog launch through an LDS stage, from which the last of the
+//    workgroup's four wavefronts writes rows of four centres.
 //
 // Arithmetic per neighbour: dx, dy are exact lattice integers, r^2 is exact
 // in FP64 and is compared with the same FP64 squared edges as everywhere
@@ -41,7 +43,7 @@ constexpr int kWaves = 4;       // wavefronts (centres) per workgroup
 constexpr int kAnchor = 8;      // z^8 steps from the base to the first anchor of a pass above order 8
 constexpr int kMaxBins = kMaxRadialBins;
 constexpr int kMaxZ = 8;        // neighbour catalogs per launch (tomographic bins)
-constexpr int kPartials = 4;   // FP64 partial slots per lane (the P of every plain pass)
+constexpr int kPartials = 4;    // FP64 partial slots per lane (the P of every plain pass)
 constexpr int kFlush = 64;      // batches of 64 neighbours per FP32 run before FP64 promotion
 
 // One launch covers the centres of a chunk against n_z neighbour catalogs
