@@ -110,7 +110,10 @@ def test_autotune_keeps_results(t3):
     print("tuned:", st, f"{best:.3f} ms", flush=True)
     assert st["scan_mode"] in (0, 1) and st["tile_mode"] in (0, 1)
     assert st["lane_neighbours"] in (0.0, 64.0, 128.0) and st["cell_arcmin"] > 0.0
-    assert st["chunk_centres"] == 0 or st["chunk_centres"] % 256 == 0
+    # every chunk capacity the tuner could try (1/2 and 1/4 of the automatic
+    # one) holds the whole 300-centre sample, like the automatic capacity, so
+    # none is tried and the capacity stays automatic
+    assert st["chunk_centres"] == 0
     ups, npairs = plan.forward_tomo(dcs)
     assert npairs == o["npairs"]
     e, _ = multipole_errors(ups.cpu().numpy(), ref)
