@@ -34,6 +34,9 @@
 // which costs 4 FMAs for two orders.  The conversion is linear, so it is
 // applied to the FP64 wave totals when each (S1, S2) and (S3, S4) pair ends
 // on one lane of the reduce-scatter, else to the FP32 lane partials first.
+// Orders that a pass needs only as G_{-m} (the top three or four of the
+// n_max = C pass) take the same 4 FMAs into two registers, Re and Im of
+// c conj(p), and skip the conversion.
 #include "sweep.h"
 
 namespace t3 {
@@ -69,13 +72,25 @@ struct ScanArgs {
     double e2[kMaxBins + 1];
 };
 
-// Per-pass register footprint.
+// First G order of a pass taken only as G_{-m}: a pass whose G orders end
+// three above its W capacity C (G_m for m <= n_max - 1 and G_{-m} for
+// m <= n_max + 3 with n_max <= C) needs orders C .. C + 3 only as G_{-m}.
+constexpr int neg_only_from(int ga, int gb, int wb)
+{
+    return gb >= ga && gb == wb + 3 ? (wb > ga ? wb : ga) : gb + 1;
+}
+
+// Per-pass register footprint.  acc layout: [4 NG S-sums of the +-m order
+// pairs][2 NGN (Re, Im) of G_{-m} for the negative-only orders][2 NW W]
+// [NX extras].
 template <int GA, int GB, int WA, int WB, bool EXTRA>
 struct PassShape {
-    static constexpr int NG = GB >= GA ? GB - GA + 1 : 0;  // +-m order pairs
-    static constexpr int NW = WB >= WA ? WB - WA + 1 : 0;  // W orders
-    static constexpr int NX = EXTRA ? 11 : 0;               // G0, W0, D terms
-    static constexpr int V = 4 * NG + 2 * NW + NX;
+    static constexpr int NEG = neg_only_from(GA, GB, WB);
+    static constexpr int NG = NEG - 1 >= GA ? NEG - GA : 0;   // +-m order pairs
+    static constexpr int NGN = GB >= NEG ? GB - NEG + 1 : 0;  // negative-only orders
+    static constexpr int NW = WB >= WA ? WB - WA + 1 : 0;     // W orders
+    static constexpr int NX = EXTRA ? 11 : 0;                  // G0, W0, D terms
+    static constexpr int V = 4 * NG + 2 * NGN + 2 * NW + NX;
     static constexpr int P = (V + 63) / 64;                // slots per lane after reduce
     static constexpr int VP = 64 * P;
     static constexpr int M0 = GA > 1 ? ((GA - 1) / kAnchor) * kAnchor : 0;
@@ -132,7 +147,7 @@ __device__ __forceinline__ void z_power(const ZPowers &z, double &br, double &bi
 // base (ar, ai) of the orders: the orders GA .. GB are taken as the powers
 // base * z^m (base 1 for the plain passes, z^SEG for the upper order segment;
 // UNIT0: the base is 1 at compile time).
-// acc layout: [4*NG S-sums][2*NW W][NX extras]
+// acc layout: [4*NG S-sums][2*NGN G_{-m}][2*NW W][NX extras]
 template <int GA, int GB, int WA, int WB, bool EXTRA, int V, bool UNIT0>
 __device__ __forceinline__ void accumulate_z(float (&acc)[V], const ZPowers &zp, double ar, double ai, float cr,
                                              float ci, float wt, bool with_extra)
@@ -151,15 +166,20 @@ __device__ __forceinline__ void accumulate_z(float (&acc)[V], const ZPowers &zp,
     }
     // the sums of one order m with its power (pr, pi)
     auto add = [&](int m, float pr, float pi) {
-        if (m >= GA && m <= GB) {
+        if (m >= GA && m < S::NEG) {
             const int k = 4 * (m - GA);
             acc[k + 0] = fmaf(cr, pr, acc[k + 0]);
             acc[k + 1] = fmaf(ci, pi, acc[k + 1]);
             acc[k + 2] = fmaf(cr, pi, acc[k + 2]);
             acc[k + 3] = fmaf(ci, pr, acc[k + 3]);
+        } else if (m >= S::NEG && m <= GB) {
+            // G_{-m} += c conj(p)
+            const int k = 4 * S::NG + 2 * (m - S::NEG);
+            acc[k + 0] = fmaf(cr, pr, fmaf(ci, pi, acc[k + 0]));
+            acc[k + 1] = fmaf(ci, pr, fmaf(-cr, pi, acc[k + 1]));
         }
         if (m >= WA && m <= WB) {
-            const int k = 4 * S::NG + 2 * (m - WA);
+            const int k = 4 * S::NG + 2 * S::NGN + 2 * (m - WA);
             acc[k + 0] = fmaf(wt, pr, acc[k + 0]);
             acc[k + 1] = fmaf(wt, pi, acc[k + 1]);
         }
@@ -212,7 +232,7 @@ __device__ __forceinline__ void accumulate_z(float (&acc)[V], const ZPowers &zp,
         ci0 = ni;
     }
     if (EXTRA && with_extra) {
-        constexpr int k = 4 * S::NG + 2 * S::NW;
+        constexpr int k = 4 * S::NG + 2 * S::NGN + 2 * S::NW;
         // G_0 += c ; W_0 += w (imaginary part stays 0)
         acc[k + 0] += cr;
         acc[k + 1] += ci;
@@ -778,9 +798,11 @@ struct PassDesc {
 // Accumulator slots of a pass (the V of its PassShape).
 inline int pass_slots(const PassDesc &p)
 {
-    const int NG = p.gb >= p.ga ? p.gb - p.ga + 1 : 0;
+    const int NEG = neg_only_from(p.ga, p.gb, p.wb);
+    const int NG = NEG - 1 >= p.ga ? NEG - p.ga : 0;
+    const int NGN = p.gb >= NEG ? p.gb - NEG + 1 : 0;
     const int NW = p.wb >= p.wa ? p.wb - p.wa + 1 : 0;
-    return 4 * NG + 2 * NW + (p.extra ? 11 : 0);
+    return 4 * NG + 2 * NGN + 2 * NW + (p.extra ? 11 : 0);
 }
 
 // Dynamic LDS for staged totals: with the rings and the FP64 partials
@@ -838,9 +860,11 @@ const std::vector<Variant> &variants()
 // Destination table of one pass for a given n_max: slot -> plane or -1.
 std::vector<short> dest_table(const PassDesc &p, const ChunkLayout &L)
 {
-    const int NG = p.gb >= p.ga ? p.gb - p.ga + 1 : 0;
+    const int NEG = neg_only_from(p.ga, p.gb, p.wb);
+    const int NG = NEG - 1 >= p.ga ? NEG - p.ga : 0;
+    const int NGN = p.gb >= NEG ? p.gb - NEG + 1 : 0;
     const int NW = p.wb >= p.wa ? p.wb - p.wa + 1 : 0;
-    const int V = 4 * NG + 2 * NW + (p.extra ? 11 : 0);
+    const int V = 4 * NG + 2 * NGN + 2 * NW + (p.extra ? 11 : 0);
     const int VP = 64 * ((V + 63) / 64);
     std::vector<short> d(VP, -1);
     const int nm = L.n_max;
@@ -856,15 +880,23 @@ std::vector<short> dest_table(const PassDesc &p, const ChunkLayout &L)
             d[4 * k + 3] = (short)L.plane_G(-m, 1);
         }
     }
+    for (int k = 0; k < NGN; ++k) {
+        // slot order Re G_-m, Im G_-m
+        const int m = NEG + k;
+        if (m <= nm + 3) {
+            d[4 * NG + 2 * k] = (short)L.plane_G(-m, 0);
+            d[4 * NG + 2 * k + 1] = (short)L.plane_G(-m, 1);
+        }
+    }
     for (int k = 0; k < NW; ++k) {
         const int m = p.wa + k;
         if (m <= L.w_max) {
-            d[4 * NG + 2 * k] = (short)L.plane_W(m, 0);
-            d[4 * NG + 2 * k + 1] = (short)L.plane_W(m, 1);
+            d[4 * NG + 2 * NGN + 2 * k] = (short)L.plane_W(m, 0);
+            d[4 * NG + 2 * NGN + 2 * k + 1] = (short)L.plane_W(m, 1);
         }
     }
     if (p.extra) {
-        const int k = 4 * NG + 2 * NW;
+        const int k = 4 * NG + 2 * NGN + 2 * NW;
         if (nm >= 1) {  // G_0 is needed only for n_max >= 1
             d[k + 0] = (short)L.plane_G(0, 0);
             d[k + 1] = (short)L.plane_G(0, 1);
