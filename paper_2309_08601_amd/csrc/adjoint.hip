@@ -463,10 +463,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_adj_scatter(ScatterArgs a)
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int nwg = gridDim.x;
-    const int per = nwg >> 3;
-    const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    const int c0 = wg * kWaves;  // first centre of the group
+    // groups in launch order: the round-robin dispatch over the 8 XCDs keeps
+    // every XCD on neighbouring groups, which share neighbours in the
+    // Infinity Cache (2% faster kept-plane backward than contiguous ranges
+    // of groups per XCD)
+    const int c0 = blockIdx.x * kWaves;  // first centre of the group
     if (c0 >= a.n_c) return;     // the whole workgroup leaves together
     const int nk = min(kWaves, a.n_c - c0);
     double dmax = 0.0;
@@ -823,8 +824,7 @@ int backward(t3_plan *plan, const t3_catalog &cat, const int32_t *centres, int64
         sa.det_hdr = det_hdr;
         sa.n_nb = n;
         for (int b = 0; b <= B; ++b) sa.e2[b] = plan->e2[b];
-        int nwg = (nc + kWaves - 1) / kWaves;
-        nwg = (nwg + 7) & ~7;
+        const int nwg = (nc + kWaves - 1) / kWaves;
         hipLaunchKernelGGL(sv->kernel, dim3((unsigned)nwg), dim3(64 * kWaves), 0, s, sa);
         T3_HIP_CHECK(hipGetLastError());
         if (det) {

@@ -154,8 +154,8 @@ int choose_chunk(const t3_plan *plan, const ChunkLayout &L)
         // longer launches waste less (measured on the 1M field: 8.7k centres
         // per chunk 1125 ms of stage 1, 64k centres 994 ms).  About 1 GiB of
         // planes per catalog, at most 64k centres, whole rounds of 2048: the
-        // n_max = 30 pass measured 4% slower with 4 GiB chunks (262k
-        // centres).  The order-segment pass, whose centres take about four
+        // n_max = 30 pass gains under 1% from 4 GiB chunks (262k centres),
+        // not worth four times the memory.  The order-segment pass, whose centres take about four
         // times longer each, gains from 4 GiB (4M field, n_max = 40: 139k
         // centres per chunk 4.5% faster than 35k).  Stage 2 addresses a
         // catalog's planes with 32-bit float offsets: below 2^30 floats here.

@@ -491,9 +491,12 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
         // a.stage: [V][n_bins] float4 of dynamic LDS, one float per wavefront
         extern __shared__ float4 stage[];
         __shared__ int done;
-        const int nwg = gridDim.x;  // multiple of 8
-        const int per = nwg >> 3;
-        const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+        // workgroups in launch order: the hardware deals them out round-robin
+        // over the 8 XCDs, so all XCDs work on neighbouring centres of the
+        // cell-sorted order at once and meet the same neighbours in the
+        // shared Infinity Cache (1.2% faster on the 1M field than giving each
+        // XCD a contiguous eighth of the chunk)
+        const int wg = blockIdx.x;
         const int ci = wg * kWaves + wv;
         if (a.stage) {
             if (threadIdx.x == 0) done = 0;
@@ -509,12 +512,8 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan(ScanArgs a)
     const int total = a.n_z * a.n_c;
     int base = 0, end = 0;
     if (!a.queue) {
-        // one wavefront per task; XCD-aware order: consecutive tasks stay on
-        // one XCD (workgroups are dispatched round-robin over the 8 XCDs)
-        const int nwg = gridDim.x;  // multiple of 8
-        const int per = nwg >> 3;
-        const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-        base = wg * kWaves + wv;
+        // one wavefront per task, tasks in launch order (as above)
+        base = blockIdx.x * kWaves + wv;
         end = base + 1 < total ? base + 1 : total;
     }
     // persistent mode: take `grab` consecutive tasks per counter increment
@@ -649,10 +648,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void k_scan_seg(ScanArgs a)
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: LDS bases stay scalar
     const SweepLDS lds{q_xyc[wv], q_wi[wv], spans[wv]};
-    const int nwg = gridDim.x;  // multiple of 8
-    const int per = nwg >> 3;
-    const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    const int ci = wg * kWaves + wv;
+    const int ci = blockIdx.x * kWaves + wv;  // launch order, as in k_scan
     if (ci >= a.n_c) return;  // whole wavefront leaves together
     const unsigned long long pairs = scan_task_seg<SW>(a, ci, lane, lds, zpow[wv]);
     if (lane == 0 && a.npairs) atomicAdd(a.npairs, pairs);
@@ -1084,7 +1080,6 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
         a.grab = 4;
     } else {
         nwg = (total + kWaves - 1) / kWaves;
-        nwg = (nwg + 7) & ~7;
         a.queue = nullptr;
         a.grab = 0;
     }
@@ -1097,7 +1092,7 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
             // every main-pass order in one sweep: k_scan_seg stands for the passes
             a.dest = plan->dest.as<short>() + plan->scan_dest_off[3];
             a.npairs = npairs;
-            const int nwg1 = (((n_c + kWaves - 1) / kWaves) + 7) & ~7;
+            const int nwg1 = (n_c + kWaves - 1) / kWaves;
             for (int k = 0; k < n_z; ++k) {
                 ScanArgs a1 = a;
                 const int z = a.order[k];
@@ -1118,7 +1113,7 @@ int scan_chunk(t3_plan *plan, const SortedCatalog *const *cats, const int *order
         } else {
             // one launch of the single-catalog kernel per catalog, densest first;
             // the totals go through LDS when the workgroup's rows fit
-            const int nwg1 = (((n_c + kWaves - 1) / kWaves) + 7) & ~7;
+            const int nwg1 = (n_c + kWaves - 1) / kWaves;
             const size_t stage_bytes = sizeof(float4) * (size_t)pass_slots(pd) * (size_t)a.n_bins;
             const bool stage = stage_bytes <= kStageBytes;
             for (int k = 0; k < n_z; ++k) {
