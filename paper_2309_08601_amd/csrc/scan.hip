@@ -481,10 +481,12 @@ __device__ __forceinline__ void store_stage(const ScanArgs &a, int quad, int lan
 // neighbours of one compact run, while the XCDs stay on the same stretch
 // of the chunk and finish together.  It is a bijection on [0, 8 kXcdRun q)
 // for whole q, so grids are rounded up to multiples of 8 kXcdRun.
-// Measured on the 1M field, stage 1 per step: 780 ms; 784 ms with
-// workgroups in launch order, which miss L2 6.5x as often; 796 ms with
-// each XCD on a contiguous eighth of the chunk, whose XCDs finish apart.
-constexpr int kXcdRun = 64;
+// Measured on the 1M field, stage 1 per step, runs of 32 / 64 / 128 / 256
+// workgroups: 775 / 780 / 785 / 798 ms (one box); in plain launch order,
+// which misses L2 6.5x as often, 4 ms more than runs of 64, and with each
+// XCD on a contiguous eighth of the chunk, whose XCDs finish apart, 16 ms
+// more.
+constexpr int kXcdRun = 32;
 __device__ __forceinline__ int xcd_run_order(int b)
 {
     const int x = b & 7, k = b >> 3;
