@@ -58,3 +58,13 @@ def test_kernel_source_hash_is_a_stable_sha256(bench):
     h = bench.kernel_source_hash()
     assert len(h) == 64 and int(h, 16) >= 0
     assert bench.kernel_source_hash() == h
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU only" in (r.stdout + r.stderr)
+    assert "{" not in r.stdout  # no bench line
